@@ -1,0 +1,222 @@
+/*
+ * ebr.h - C ABI of libebr, an MI355X (gfx950) implementation of the retrieval
+ * hot path of "An Efficient Embedding Based Ad Retrieval with GPU-Powered
+ * Feature Interaction" (arXiv 2511.22460).
+ *
+ * For every query and every ad of the inventory the library computes
+ *
+ *     s(u, a) = <u, e_a> + sum_j m_j * W[k_j, a]
+ *
+ * and returns the K ads with the largest s, ordered by (s descending, ad id
+ * ascending). The first term is the dual-tower inner product (Section 3.1,
+ * equation "dual-tower"; IPNN-extended towers are the same product over longer
+ * vectors, Section 3.2). The second is the HitMatch explicit cross term
+ * (Section 3.3, equation "hitmatch"), served from an inverted list that maps
+ * each user feature value (key) to the ids of the ads carrying it, the input
+ * of the indexing algorithm of Section 3.4 (Algorithm 1). The
+ * paper's binary L with per-feature weight w_i x_i is the case W == 1 (pass
+ * post_w = NULL) with m_j = w_j x_j (feat_mult). The paper's query carries its
+ * non-zero feature values {(k, w_hat)} (Algorithm 2, its input).
+ *
+ * Conventions for every call:
+ *  - Return codes are ebr_status; EBR_OK is 0, errors are negative, and
+ *    ebr_last_error() gives a thread-local message for the last failure.
+ *  - No exception crosses the ABI. On error no output buffer is written.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory of the device current at the call (for instance a torch tensor's
+ *    data_ptr()). hip_stream is a hipStream_t (NULL = the null stream).
+ *  - The library never allocates device memory: the index lives in a
+ *    caller-owned arena, batch scratch in a caller-owned workspace, each sized
+ *    by a *_size query. Both must outlive the objects that use them.
+ *  - HIP failures map to EBR_EDEVICE with hipGetErrorString text.
+ */
+#ifndef EBR_H
+#define EBR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EBR_OK = 0,
+    EBR_EINVAL = -1,       /* invalid argument or input data */
+    EBR_ENOMEM = -2,       /* arena / workspace / scratch budget too small */
+    EBR_EDEVICE = -3,      /* HIP runtime or kernel failure */
+    EBR_EAGAIN = -4,       /* not ready yet / queue full */
+    EBR_ENOTFOUND = -5,    /* unknown ticket */
+    EBR_ESHUTDOWN = -6,    /* server is shutting down */
+    EBR_EUNSUPPORTED = -7  /* valid but outside what this build implements */
+} ebr_status;
+
+/* Arithmetic type of the ad-embedding scan. */
+typedef enum { EBR_F32 = 0, EBR_BF16 = 1, EBR_FP8E4M3 = 2 } ebr_dtype;
+
+typedef struct ebr_index ebr_index; /* opaque; immutable after build */
+
+/* ------------------------------------------------------------------------ index */
+
+/*
+ * Index input, all host memory, copied during ebr_build_index.
+ *  n_ads        N, 1 <= N < 2^32.
+ *  dim          d, a multiple of 16 in [16, 128] (64 in the paper's towers,
+ *               Section 4.1; wider with IPNN, Section 3.2).
+ *  ad_emb       N x d FP32, row-major; the ground truth of the deep term.
+ *  n_keys       V >= 0, number of posting lists (user feature values).
+ *  key_offsets  V + 1 non-decreasing int64, key_offsets[0] == 0: key k owns
+ *               postings [key_offsets[k], key_offsets[k+1]). Total < 2^32.
+ *  post_ids     ad ids, strictly increasing within each key, < N (lists are
+ *               sets, Algorithm 1 takes their union).
+ *  post_w       FP32 cross weights per posting, or NULL for unit weights
+ *               (the paper's binary L).
+ *  dtypes       bitmask of (1u << ebr_dtype) scan copies to build; FP32 is
+ *               always built (it is also the exact rescore source).
+ * EBR_EINVAL: unsorted or duplicate postings, ids >= N, non-finite embeddings
+ * or weights, d not a supported multiple of 16, totals out of range.
+ */
+typedef struct {
+    int64_t n_ads;
+    int32_t dim;
+    const float* ad_emb;
+    int64_t n_keys;
+    const int64_t* key_offsets;
+    const uint32_t* post_ids;
+    const float* post_w;
+    uint32_t dtypes;
+} ebr_build_desc;
+
+typedef struct {
+    int64_t n_ads, n_keys, n_postings, n_chunks, n_tiles;
+    int32_t dim, tile_ads;
+    uint64_t arena_bytes;
+    uint64_t bytes_emb_f32, bytes_emb_bf16, bytes_emb_fp8;
+    uint64_t bytes_chunk_headers, bytes_packed_ids, bytes_weights;
+    double bits_per_id;      /* packed delta bits + header bits, per posting */
+    double bytes_per_posting;/* whole posting store (headers + ids + weights) */
+    double encode_ms;        /* host encode time of the last build */
+    double upload_ms;        /* host-to-device copy time of the last build */
+} ebr_index_info;
+
+/* Exact arena size (bytes) ebr_build_index needs for desc. Host only; no GPU use. */
+ebr_status ebr_index_size(const ebr_build_desc* desc, size_t* arena_bytes);
+
+/*
+ * Encode the posting lists (Section 3.4, "Block Compression" and "Storage
+ * Layout", redesigned: 64-posting chunks of bit-packed id gaps with a per-key
+ * chunk directory, raw FP32 weights), lay the embeddings out for the matrix
+ * cores, and copy everything into dev_arena (device, >= ebr_index_size bytes,
+ * 256-byte aligned). Synchronises hip_stream before returning. *out receives a
+ * handle that owns host metadata only; free it with ebr_free_index.
+ */
+ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t arena_bytes,
+                           void* hip_stream, ebr_index** out);
+
+ebr_status ebr_index_stats(const ebr_index* index, ebr_index_info* out);
+
+/*
+ * Test hook: decode key's list on the GPU from the compressed arena into the
+ * device arrays ids / w of capacity cap; *len (host) receives the list length.
+ * Blocking. EBR_ENOMEM if cap < length (nothing written).
+ */
+ebr_status ebr_decode_key(const ebr_index* index, int64_t key, uint32_t* ids, float* w,
+                          int64_t cap, int64_t* len, void* hip_stream);
+
+void ebr_free_index(ebr_index* index);
+
+/* ------------------------------------------------------------------------ query */
+
+/*
+ * One batch of queries.
+ *  n_queries     B >= 0.
+ *  user_emb      device, B x d FP32 row-major user vectors.
+ *  feat_offsets  host, B + 1 int64 CSR over features, feat_offsets[0] == 0.
+ *  feat_keys     host, keys of each query, distinct within a query, < V.
+ *  feat_mult     host FP32 multiplier per feature (the paper's w_hat), or NULL
+ *                for 1.0.
+ *  k             host, per-query K, 0 <= K_q <= min(N, 8192).
+ *  scan_dtype    EBR_F32 (this build); others return EBR_EUNSUPPORTED.
+ *  rescore_factor  reserved for the reduced-precision scans; ignored for F32.
+ * Results of query q occupy positions [sum_{p<q} K_p, sum_{p<=q} K_p).
+ */
+typedef struct {
+    int32_t n_queries;
+    const float* user_emb;
+    const int64_t* feat_offsets;
+    const int32_t* feat_keys;
+    const float* feat_mult;
+    const int32_t* k;
+    ebr_dtype scan_dtype;
+    int32_t rescore_factor;
+} ebr_batch;
+
+/* Workspace bytes ebr_score_topk / ebr_score_dense need for this batch. Host only. */
+ebr_status ebr_workspace_size(const ebr_index* index, const ebr_batch* batch, size_t* bytes);
+
+/*
+ * Top-K of every query of the batch. ws: device workspace of ws_bytes >=
+ * ebr_workspace_size (256-byte aligned). out_ids (uint32) and out_scores (FP32
+ * s(u, a)) are device arrays of sum K_q entries, each query's slice ordered by
+ * (score descending, id ascending); -0.0 scores are returned as +0.0.
+ * The call blocks until the results are complete on hip_stream.
+ * EBR_EINVAL: keys out of range or repeated in a query, K_q out of range,
+ * non-finite multipliers or user vectors.
+ */
+ebr_status ebr_score_topk(const ebr_index* index, const ebr_batch* batch, void* ws,
+                          size_t ws_bytes, uint32_t* out_ids, float* out_scores,
+                          void* hip_stream);
+
+/*
+ * Test hook for small inventories: the full B x N FP32 deep and wide terms as
+ * the top-K path computes them (row-major, device). The path's score of ad a
+ * for query q is exactly the FP32 sum deep[q*N+a] + wide[q*N+a]. Blocking.
+ */
+ebr_status ebr_score_dense(const ebr_index* index, const ebr_batch* batch, void* ws,
+                           size_t ws_bytes, float* deep, float* wide, void* hip_stream);
+
+/* ------------------------------------------------------------------------ timing */
+
+/*
+ * Per-phase device times of the last ebr_score_topk on the calling thread,
+ * measured with HIP events recorded on the call's stream around each phase
+ * (only while timing is enabled with ebr_set_timing(1); off by default).
+ *  decode_ms    batch key dedup upload, posting decode into tile buckets
+ *  sample_ms    scoring of the sample tiles and the per-query threshold select
+ *  score_ms     the fused scoring kernel over the whole inventory (all rounds)
+ *  finalize_ms  candidate sort and output (all rounds)
+ *  host_ms      host validation and planning
+ *  rounds       scoring rounds (1 unless a threshold had to be revised)
+ */
+typedef struct {
+    double decode_ms, sample_ms, score_ms, finalize_ms, host_ms;
+    int32_t rounds;
+} ebr_timings;
+
+ebr_status ebr_set_timing(int enable);
+ebr_status ebr_get_timings(ebr_timings* out);
+
+/* ------------------------------------------------------------------------ codec */
+
+/*
+ * Host codec of one posting list in the index's chunk format, for tests and
+ * tools that have no GPU. ids: n strictly increasing uint32. The encoding is
+ * ceil(n / 64) 16-byte chunk headers followed by the packed gap words.
+ * ebr_codec_size: bytes ebr_codec_encode writes.
+ * ebr_codec_decode: inverse; EBR_EINVAL on a malformed encoding.
+ */
+ebr_status ebr_codec_size(const uint32_t* ids, int64_t n, size_t* bytes);
+ebr_status ebr_codec_encode(const uint32_t* ids, int64_t n, void* out, size_t cap,
+                            size_t* used);
+ebr_status ebr_codec_decode(const void* in, size_t bytes, int64_t n, uint32_t* ids);
+
+/* Thread-local text of the last error (never NULL). */
+const char* ebr_last_error(void);
+
+/* Library version string. */
+const char* ebr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EBR_H */

@@ -1,0 +1,337 @@
+"""Python binding of libebr (the C ABI declared in include/ebr.h).
+
+Argument marshalling only: every step of the retrieval path runs inside
+libebr.so (host runtime + gfx950 kernels). PyTorch supplies device memory
+(the index arena, the batch workspace, outputs) and the current HIP stream.
+There is no fallback: if the library cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import _build
+
+_lib = None
+
+EBR_OK, EBR_EINVAL, EBR_ENOMEM, EBR_EDEVICE, EBR_EAGAIN, EBR_ENOTFOUND, EBR_ESHUTDOWN, \
+    EBR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+F32, BF16, FP8E4M3 = 0, 1, 2
+_STATUS = {0: "EBR_OK", -1: "EBR_EINVAL", -2: "EBR_ENOMEM", -3: "EBR_EDEVICE", -4: "EBR_EAGAIN",
+           -5: "EBR_ENOTFOUND", -6: "EBR_ESHUTDOWN", -7: "EBR_EUNSUPPORTED"}
+
+#: every symbol include/ebr.h declares
+EXPORTS = ("ebr_index_size", "ebr_build_index", "ebr_index_stats", "ebr_decode_key",
+           "ebr_free_index", "ebr_workspace_size", "ebr_score_topk", "ebr_score_dense",
+           "ebr_codec_size", "ebr_codec_encode", "ebr_codec_decode", "ebr_last_error",
+           "ebr_version", "ebr_set_timing", "ebr_get_timings")
+
+
+class EbrError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BuildDesc(ctypes.Structure):
+    _fields_ = [("n_ads", ctypes.c_int64), ("dim", ctypes.c_int32), ("ad_emb", ctypes.c_void_p),
+                ("n_keys", ctypes.c_int64), ("key_offsets", ctypes.c_void_p),
+                ("post_ids", ctypes.c_void_p), ("post_w", ctypes.c_void_p),
+                ("dtypes", ctypes.c_uint32)]
+
+
+class IndexInfo(ctypes.Structure):
+    _fields_ = [("n_ads", ctypes.c_int64), ("n_keys", ctypes.c_int64),
+                ("n_postings", ctypes.c_int64), ("n_chunks", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int64), ("dim", ctypes.c_int32), ("tile_ads", ctypes.c_int32),
+                ("arena_bytes", ctypes.c_uint64), ("bytes_emb_f32", ctypes.c_uint64),
+                ("bytes_emb_bf16", ctypes.c_uint64), ("bytes_emb_fp8", ctypes.c_uint64),
+                ("bytes_chunk_headers", ctypes.c_uint64), ("bytes_packed_ids", ctypes.c_uint64),
+                ("bytes_weights", ctypes.c_uint64), ("bits_per_id", ctypes.c_double),
+                ("bytes_per_posting", ctypes.c_double), ("encode_ms", ctypes.c_double),
+                ("upload_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class Timings(ctypes.Structure):
+    _fields_ = [("decode_ms", ctypes.c_double), ("sample_ms", ctypes.c_double),
+                ("score_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double),
+                ("host_ms", ctypes.c_double), ("rounds", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+def set_timing(enable: bool):
+    _check(load().ebr_set_timing(1 if enable else 0), "ebr_set_timing")
+
+
+def last_timings() -> dict:
+    t = Timings()
+    _check(load().ebr_get_timings(ctypes.byref(t)), "ebr_get_timings")
+    return t.as_dict()
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("n_queries", ctypes.c_int32), ("user_emb", ctypes.c_void_p),
+                ("feat_offsets", ctypes.c_void_p), ("feat_keys", ctypes.c_void_p),
+                ("feat_mult", ctypes.c_void_p), ("k", ctypes.c_void_p),
+                ("scan_dtype", ctypes.c_int), ("rescore_factor", ctypes.c_int32)]
+
+
+def lib_path() -> str:
+    return _build.LIB
+
+
+def load():
+    """Load libebr.so (building it first only if no built library exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:  # torch first, so its HIP runtime is the one the library binds to
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    h = ctypes.CDLL(_build.LIB)
+    P, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    st = ctypes.c_int
+    sig = {
+        "ebr_index_size": ([P, ctypes.POINTER(sz)], st),
+        "ebr_build_index": ([P, P, sz, P, ctypes.POINTER(P)], st),
+        "ebr_index_stats": ([P, P], st),
+        "ebr_decode_key": ([P, i64, P, P, i64, ctypes.POINTER(i64), P], st),
+        "ebr_free_index": ([P], None),
+        "ebr_workspace_size": ([P, P, ctypes.POINTER(sz)], st),
+        "ebr_score_topk": ([P, P, P, sz, P, P, P], st),
+        "ebr_score_dense": ([P, P, P, sz, P, P, P], st),
+        "ebr_codec_size": ([P, i64, ctypes.POINTER(sz)], st),
+        "ebr_codec_encode": ([P, i64, P, sz, ctypes.POINTER(sz)], st),
+        "ebr_codec_decode": ([P, sz, i64, P], st),
+        "ebr_last_error": ([], ctypes.c_char_p),
+        "ebr_version": ([], ctypes.c_char_p),
+        "ebr_set_timing": ([ctypes.c_int], st),
+        "ebr_get_timings": ([P], st),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(h, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = h
+    return h
+
+
+def _check(rc: int, where: str):
+    if rc != EBR_OK:
+        raise EbrError(rc, where, load().ebr_last_error().decode(errors="replace"))
+
+
+def version() -> str:
+    return load().ebr_version().decode()
+
+
+def _np(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+# ------------------------------------------------------------------------------ codec (host)
+
+def codec_encode(ids) -> bytes:
+    ids = _np(ids, np.uint32)
+    n = len(ids)
+    need = ctypes.c_size_t()
+    _check(load().ebr_codec_size(_ptr(ids), n, ctypes.byref(need)), "ebr_codec_size")
+    buf = np.zeros(max(1, need.value), dtype=np.uint8)
+    used = ctypes.c_size_t()
+    _check(load().ebr_codec_encode(_ptr(ids), n, buf.ctypes.data, need.value, ctypes.byref(used)),
+           "ebr_codec_encode")
+    return buf[:used.value].tobytes()
+
+
+def codec_decode(blob: bytes, n: int) -> np.ndarray:
+    src = np.frombuffer(blob, dtype=np.uint8) if len(blob) else np.zeros(1, np.uint8)
+    out = np.empty(max(1, n), dtype=np.uint32)
+    _check(load().ebr_codec_decode(src.ctypes.data, len(blob), n, out.ctypes.data),
+           "ebr_codec_decode")
+    return out[:n]
+
+
+def index_size(ad_emb, key_offsets, post_ids, post_w=None, dtypes: int = 1) -> int:
+    desc, _keep = _desc(ad_emb, key_offsets, post_ids, post_w, dtypes)
+    n = ctypes.c_size_t()
+    _check(load().ebr_index_size(ctypes.byref(desc), ctypes.byref(n)), "ebr_index_size")
+    return n.value
+
+
+def _desc(ad_emb, key_offsets, post_ids, post_w, dtypes):
+    E = _np(ad_emb, np.float32)
+    offs = _np(key_offsets, np.int64)
+    ids = _np(post_ids, np.uint32)
+    w = _np(post_w, np.float32)
+    d = BuildDesc(E.shape[0], E.shape[1] if E.ndim == 2 else 0, _ptr(E), len(offs) - 1,
+                  _ptr(offs), _ptr(ids) if len(ids) else None, _ptr(w) if w is not None and len(w) else None,
+                  dtypes)
+    return d, (E, offs, ids, w)
+
+
+# ------------------------------------------------------------------------------ index
+
+class Index:
+    """A resident index: compressed posting lists + embeddings in a torch-owned device arena."""
+
+    def __init__(self, ad_emb, key_offsets, post_ids, post_w=None, dtypes: int = 1, device=None,
+                 stream=None):
+        import torch
+        self.device = torch.device(device if device is not None else "cuda")
+        desc, keep = _desc(ad_emb, key_offsets, post_ids, post_w, dtypes)
+        n = ctypes.c_size_t()
+        _check(load().ebr_index_size(ctypes.byref(desc), ctypes.byref(n)), "ebr_index_size")
+        self.arena = torch.empty(max(256, n.value), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _check(load().ebr_build_index(ctypes.byref(desc), self.arena.data_ptr(), self.arena.numel(),
+                                      _stream(stream), ctypes.byref(h)), "ebr_build_index")
+        self._h = h
+        self.n_ads, self.dim = keep[0].shape
+        self.n_keys = len(keep[1]) - 1
+        self._ws = None
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        return cls(wl.ad_emb, wl.key_offsets, wl.post_ids, wl.post_w, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ebr_free_index(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> dict:
+        info = IndexInfo()
+        _check(load().ebr_index_stats(self._h, ctypes.byref(info)), "ebr_index_stats")
+        return info.as_dict()
+
+    def decode_key(self, key: int, stream=None):
+        import torch
+        n = ctypes.c_int64()
+        rc = load().ebr_decode_key(self._h, key, None, None, 0, ctypes.byref(n), _stream(stream))
+        if rc not in (EBR_OK, EBR_ENOMEM):
+            _check(rc, "ebr_decode_key")
+        cap = max(1, n.value)
+        ids = torch.empty(cap, dtype=torch.int32, device=self.device)
+        w = torch.empty(cap, dtype=torch.float32, device=self.device)
+        _check(load().ebr_decode_key(self._h, key, ids.data_ptr(), w.data_ptr(), cap,
+                                     ctypes.byref(n), _stream(stream)), "ebr_decode_key")
+        return ids[:n.value], w[:n.value]
+
+    # -------------------------------------------------------------------------- batches
+
+    def _batch(self, user_emb, feat_offsets, feat_keys, feat_mult, k, scan_dtype, rescore):
+        import torch
+        if not (isinstance(user_emb, torch.Tensor) and user_emb.is_cuda):
+            raise TypeError("user_emb must be a CUDA (HIP) tensor")
+        if user_emb.dtype != torch.float32 or user_emb.dim() != 2 or user_emb.shape[1] != self.dim:
+            raise ValueError(f"user_emb must be float32 [B, {self.dim}]")
+        user_emb = user_emb.contiguous()
+        offs = _np(feat_offsets, np.int64)
+        keys = _np(feat_keys, np.int32)
+        mult = _np(feat_mult, np.float32)
+        kq = _np(k, np.int32) if k is not None else None
+        B = user_emb.shape[0]
+        if len(offs) != B + 1:
+            raise ValueError("feat_offsets must have B + 1 entries")
+        if kq is not None and len(kq) != B:
+            raise ValueError("k must have B entries")
+        keep = (user_emb, offs, keys, mult, kq)
+        b = Batch(B, user_emb.data_ptr(), _ptr(offs), _ptr(keys) if len(keys) else None,
+                  _ptr(mult) if mult is not None and len(mult) else None,
+                  _ptr(kq) if kq is not None and len(kq) else None, scan_dtype, rescore)
+        return b, keep
+
+    def workspace(self, nbytes: int):
+        import torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(256, nbytes), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def workspace_size(self, user_emb, feat_offsets, feat_keys, k, feat_mult=None,
+                       scan_dtype: int = F32, rescore_factor: int = 4) -> int:
+        b, keep = self._batch(user_emb, feat_offsets, feat_keys, feat_mult, k, scan_dtype,
+                              rescore_factor)
+        n = ctypes.c_size_t()
+        _check(load().ebr_workspace_size(self._h, ctypes.byref(b), ctypes.byref(n)),
+               "ebr_workspace_size")
+        return n.value
+
+    def score_topk(self, user_emb, feat_offsets, feat_keys, k, feat_mult=None,
+                   scan_dtype: int = F32, rescore_factor: int = 4, out=None, stream=None):
+        """Top-K per query. Returns (ids int32 tensor [sum K], scores float32 tensor [sum K],
+        offsets np.int64 [B + 1]); ids are uint32 values stored in int32 (N < 2^31 here)."""
+        import torch
+        b, keep = self._batch(user_emb, feat_offsets, feat_keys, feat_mult, k, scan_dtype,
+                              rescore_factor)
+        kq = keep[4]
+        offs = np.zeros(len(kq) + 1, dtype=np.int64)
+        np.cumsum(kq, out=offs[1:])
+        total = int(offs[-1])
+        n = ctypes.c_size_t()
+        _check(load().ebr_workspace_size(self._h, ctypes.byref(b), ctypes.byref(n)),
+               "ebr_workspace_size")
+        ws = self.workspace(n.value)
+        if out is None:
+            ids = torch.empty(max(1, total), dtype=torch.int32, device=self.device)
+            scores = torch.empty(max(1, total), dtype=torch.float32, device=self.device)
+        else:
+            ids, scores = out
+        _check(load().ebr_score_topk(self._h, ctypes.byref(b), ws.data_ptr(), ws.numel(),
+                                     ids.data_ptr(), scores.data_ptr(), _stream(stream)),
+               "ebr_score_topk")
+        return ids[:total], scores[:total], offs
+
+    def score_dense(self, user_emb, feat_offsets, feat_keys, feat_mult=None, stream=None):
+        """Full FP32 deep and wide terms [B, N] as the top-K path computes them."""
+        import torch
+        b, keep = self._batch(user_emb, feat_offsets, feat_keys, feat_mult, None, F32, 0)
+        n = ctypes.c_size_t()
+        # the dense hook needs no selection buffers; size it through the top-K query with K = 0
+        kz = np.zeros(max(1, b.n_queries), np.int32)
+        b2 = Batch(b.n_queries, b.user_emb, b.feat_offsets, b.feat_keys, b.feat_mult,
+                   kz.ctypes.data, F32, 0)
+        _check(load().ebr_workspace_size(self._h, ctypes.byref(b2), ctypes.byref(n)),
+               "ebr_workspace_size")
+        ws = self.workspace(n.value)
+        B = b.n_queries
+        deep = torch.empty((B, self.n_ads), dtype=torch.float32, device=self.device)
+        wide = torch.empty((B, self.n_ads), dtype=torch.float32, device=self.device)
+        _check(load().ebr_score_dense(self._h, ctypes.byref(b), ws.data_ptr(), ws.numel(),
+                                      deep.data_ptr(), wide.data_ptr(), _stream(stream)),
+               "ebr_score_dense")
+        return deep, wide
+
+    def topk_workload(self, wl, qs=None, **kw):
+        """Convenience: run a workloads.Workload batch (or a subset of its queries)."""
+        import torch
+        w = wl if qs is None else wl.subset(qs)
+        U = torch.from_numpy(np.ascontiguousarray(w.user_emb)).to(self.device)
+        return self.score_topk(U, w.feat_offsets, w.feat_keys, w.k, w.feat_mult, **kw)

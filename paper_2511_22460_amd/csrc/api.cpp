@@ -1,0 +1,886 @@
+// Host runtime and C ABI of libebr: input validation, index build (encode + upload into the
+// caller's arena), batch planning, and the launch sequence of one top-K batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+struct ebr_index : ebr::Index {};
+
+namespace ebr {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+const char* last_error() { return g_err.c_str(); }
+
+#define HIP_TRY(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (hipError_t)(expr);                                        \
+        if (e_ != hipSuccess) {                                                    \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));              \
+            return EBR_EDEVICE;                                                    \
+        }                                                                          \
+    } while (0)
+
+// ------------------------------------------------------------------ phase timing
+
+static std::atomic<int> g_timing{0};
+static thread_local ebr_timings g_last_timings{};
+
+// HIP events recorded on the call's stream at phase boundaries (only while timing is on).
+struct PhaseClock {
+    bool on = false;
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> ev;
+    explicit PhaseClock(hipStream_t s) : on(g_timing.load() != 0), st(s) {}
+    ~PhaseClock() { for (hipEvent_t e : ev) (void)hipEventDestroy(e); }
+    int mark() {  // returns the event index, or -1 when timing is off
+        if (!on) return -1;
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { on = false; return -1; }
+        ev.push_back(e);
+        if (hipEventRecord(e, st) != hipSuccess) { on = false; return -1; }
+        return (int)ev.size() - 1;
+    }
+    double ms(int a, int b) const {
+        if (!on || a < 0 || b < 0) return 0.0;
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) return 0.0;
+        return (double)t;
+    }
+};
+
+// ------------------------------------------------------------------ host threading
+
+static int host_threads() {
+    unsigned n = std::thread::hardware_concurrency();
+    if (n == 0) n = 4;
+    return (int)std::min(n, 32u);
+}
+
+// Calls fn(begin, end) on nt contiguous slices of [0, n).
+static void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& fn,
+                         int64_t min_per_thread = 4096) {
+    int nt = host_threads();
+    if (n < min_per_thread * 2) nt = 1;
+    if (nt <= 1) { fn(0, n); return; }
+    std::vector<std::thread> th;
+    int64_t per = (n + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+        int64_t b = t * per, e = std::min(n, b + per);
+        if (b >= e) break;
+        th.emplace_back(fn, b, e);
+    }
+    for (auto& x : th) x.join();
+}
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ------------------------------------------------------------------ index build
+
+struct Measured {
+    std::vector<uint32_t> key_chunk_off;  // V + 1
+    std::vector<uint64_t> key_word_off;   // V + 1
+    ArenaPlan plan;
+};
+
+static bool dim_ok(int32_t d) { return d >= 16 && d <= 128 && d % 16 == 0 && score_dim_supported(d); }
+
+static ebr_status validate_desc(const ebr_build_desc* d) {
+    if (!d) { set_error("desc is NULL"); return EBR_EINVAL; }
+    if (d->n_ads < 1 || d->n_ads > 0xffffffffLL) { set_error("n_ads must be in [1, 2^32)"); return EBR_EINVAL; }
+    if (!dim_ok(d->dim)) { set_error("dim %d unsupported: need a multiple of 16 in [16, 128]", d->dim); return EBR_EINVAL; }
+    if (!d->ad_emb) { set_error("ad_emb is NULL"); return EBR_EINVAL; }
+    if (d->n_keys < 0) { set_error("n_keys < 0"); return EBR_EINVAL; }
+    if (d->n_keys > 0 && !d->key_offsets) { set_error("key_offsets is NULL"); return EBR_EINVAL; }
+    if (d->dtypes & ~1u) { set_error("only the FP32 scan copy is implemented (dtypes=%u)", d->dtypes); return EBR_EUNSUPPORTED; }
+    const int64_t V = d->n_keys;
+    if (V > 0) {
+        if (d->key_offsets[0] != 0) { set_error("key_offsets[0] != 0"); return EBR_EINVAL; }
+        for (int64_t k = 0; k < V; ++k)
+            if (d->key_offsets[k + 1] < d->key_offsets[k]) { set_error("key_offsets decrease at key %lld", (long long)k); return EBR_EINVAL; }
+        const int64_t total = d->key_offsets[V];
+        if (total > 0xffffffffLL - 64) { set_error("more than 2^32 postings"); return EBR_EINVAL; }
+        if (total > 0 && !d->post_ids) { set_error("post_ids is NULL"); return EBR_EINVAL; }
+    }
+    std::atomic<int64_t> bad_key{-1}, bad_w{-1}, bad_row{-1};
+    if (V > 0) {
+        parallel_for(V, [&](int64_t b, int64_t e) {
+            for (int64_t k = b; k < e; ++k) {
+                const int64_t s = d->key_offsets[k], t = d->key_offsets[k + 1];
+                for (int64_t i = s; i < t; ++i) {
+                    if (d->post_ids[i] >= (uint64_t)d->n_ads || (i > s && d->post_ids[i] <= d->post_ids[i - 1])) {
+                        bad_key = k;
+                        break;
+                    }
+                    if (d->post_w && !std::isfinite(d->post_w[i])) { bad_w = k; break; }
+                }
+            }
+        }, 256);
+    }
+    if (bad_key >= 0) { set_error("postings of key %lld are not strictly increasing ids < n_ads", (long long)bad_key.load()); return EBR_EINVAL; }
+    if (bad_w >= 0) { set_error("non-finite weight in key %lld", (long long)bad_w.load()); return EBR_EINVAL; }
+    parallel_for(d->n_ads, [&](int64_t b, int64_t e) {
+        for (int64_t a = b; a < e; ++a)
+            for (int32_t i = 0; i < d->dim; ++i)
+                if (!std::isfinite(d->ad_emb[a * d->dim + i])) { bad_row = a; return; }
+    });
+    if (bad_row >= 0) { set_error("non-finite embedding in ad %lld", (long long)bad_row.load()); return EBR_EINVAL; }
+    return EBR_OK;
+}
+
+static ebr_status measure(const ebr_build_desc* d, Measured* m) {
+    const int64_t V = d->n_keys;
+    std::vector<int64_t> ch(V), wd(V);
+    if (V > 0) {
+        parallel_for(V, [&](int64_t b, int64_t e) {
+            for (int64_t k = b; k < e; ++k) {
+                const int64_t s = d->key_offsets[k], t = d->key_offsets[k + 1];
+                codec_measure(d->post_ids + s, t - s, &ch[k], &wd[k]);
+            }
+        }, 256);
+    }
+    m->key_chunk_off.assign(V + 1, 0);
+    m->key_word_off.assign(V + 1, 0);
+    uint64_t c = 0, w = 0;
+    for (int64_t k = 0; k < V; ++k) {
+        m->key_chunk_off[k] = (uint32_t)c;
+        m->key_word_off[k] = w;
+        c += (uint64_t)ch[k];
+        w += (uint64_t)wd[k];
+        if (c > 0xffffffffull || w > 0xfffffff0ull) { set_error("index too large for 32-bit chunk/word offsets"); return EBR_EINVAL; }
+    }
+    m->key_chunk_off[V] = (uint32_t)c;
+    m->key_word_off[V] = w;
+    ArenaPlan& p = m->plan;
+    const int64_t n_blk = (d->n_ads + kTileAds - 1) / kTileAds;
+    const int64_t n_post = V > 0 ? d->key_offsets[V] : 0;
+    p.n_chunks = (int64_t)c;
+    p.n_words = (int64_t)w;
+    p.bytes_emb_f32 = (size_t)n_blk * kTileAds * d->dim * 4;
+    p.bytes_chunks = std::max<size_t>(16, (size_t)c * 16);
+    p.bytes_words = (size_t)(w + 2) * 4;
+    p.bytes_weights = std::max<size_t>(4, (size_t)n_post * 4);
+    size_t off = 0;
+    p.off_emb_f32 = off; off = align256(off + p.bytes_emb_f32);
+    p.off_chunks = off; off = align256(off + p.bytes_chunks);
+    p.off_words = off; off = align256(off + p.bytes_words);
+    p.off_weights = off; off = align256(off + p.bytes_weights);
+    p.total = off;
+    return EBR_OK;
+}
+
+// FP32 copy in the matrix-core layout (see k_score in kernels.hip).
+static void swizzle_f32(const float* E, int64_t n_ads, int32_t d, float* out) {
+    const int64_t n_blk = (n_ads + kTileAds - 1) / kTileAds;
+    const int NQ = d / 8;
+    parallel_for(n_blk, [&](int64_t b0, int64_t b1) {
+        for (int64_t b = b0; b < b1; ++b) {
+            float* dst = out + b * (int64_t)kTileAds * d;
+            for (int i = 0; i < NQ; ++i)
+                for (int l = 0; l < 64; ++l)
+                    for (int j = 0; j < 4; ++j) {
+                        const int64_t row = b * kTileAds + (l & 31);
+                        const int col = 8 * i + 2 * j + (l >> 5);
+                        dst[((int64_t)i * 64 + l) * 4 + j] = row < n_ads ? E[row * d + col] : 0.0f;
+                    }
+        }
+    }, 64);
+}
+
+}  // namespace ebr
+
+using namespace ebr;
+
+extern "C" {
+
+const char* ebr_last_error(void) { return ebr::last_error(); }
+const char* ebr_version(void) { return "libebr 0.1 (gfx950)"; }
+
+ebr_status ebr_set_timing(int enable) {
+    g_timing.store(enable ? 1 : 0);
+    return EBR_OK;
+}
+
+ebr_status ebr_get_timings(ebr_timings* out) {
+    if (!out) { set_error("out is NULL"); return EBR_EINVAL; }
+    *out = g_last_timings;
+    return EBR_OK;
+}
+
+ebr_status ebr_index_size(const ebr_build_desc* desc, size_t* arena_bytes) {
+    try {
+        if (!arena_bytes) { set_error("arena_bytes is NULL"); return EBR_EINVAL; }
+        ebr_status st = validate_desc(desc);
+        if (st) return st;
+        Measured m;
+        st = measure(desc, &m);
+        if (st) return st;
+        *arena_bytes = m.plan.total;
+        return EBR_OK;
+    } catch (const std::bad_alloc&) {
+        set_error("host out of memory");
+        return EBR_ENOMEM;
+    } catch (...) {
+        set_error("internal error");
+        return EBR_EINVAL;
+    }
+}
+
+ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t arena_bytes,
+                           void* hip_stream, ebr_index** out) {
+    try {
+        if (!out) { set_error("out is NULL"); return EBR_EINVAL; }
+        *out = nullptr;
+        auto t0 = std::chrono::steady_clock::now();
+        ebr_status st = validate_desc(desc);
+        if (st) return st;
+        Measured m;
+        st = measure(desc, &m);
+        if (st) return st;
+        const ArenaPlan& p = m.plan;
+        if (!dev_arena || arena_bytes < p.total) {
+            set_error("arena too small: need %zu bytes, got %zu", p.total, arena_bytes);
+            return EBR_ENOMEM;
+        }
+        if ((uintptr_t)dev_arena & 255) { set_error("arena must be 256-byte aligned"); return EBR_EINVAL; }
+        const int64_t V = desc->n_keys;
+        const int64_t n_post = V > 0 ? desc->key_offsets[V] : 0;
+
+        // encode on the host
+        std::vector<ChunkHdr> hdr((size_t)std::max<int64_t>(1, p.n_chunks));
+        std::vector<uint32_t> words((size_t)p.n_words + 2, 0u);
+        std::vector<float> maxw((size_t)V, 0.0f);
+        if (V > 0) {
+            parallel_for(V, [&](int64_t b, int64_t e) {
+                for (int64_t k = b; k < e; ++k) {
+                    const int64_t s = desc->key_offsets[k], t = desc->key_offsets[k + 1];
+                    codec_encode(desc->post_ids + s, t - s, hdr.data() + m.key_chunk_off[k],
+                                 words.data() + m.key_word_off[k], (uint32_t)m.key_word_off[k],
+                                 (uint32_t)s);
+                    float mx = (t > s) ? 1.0f : 0.0f;
+                    if (desc->post_w) {
+                        mx = 0.0f;
+                        for (int64_t i = s; i < t; ++i) mx = std::max(mx, std::fabs(desc->post_w[i]));
+                    }
+                    maxw[k] = mx;
+                }
+            }, 256);
+        }
+        std::vector<float> emb(p.bytes_emb_f32 / 4);
+        swizzle_f32(desc->ad_emb, desc->n_ads, desc->dim, emb.data());
+        std::vector<float> ones;
+        if (!desc->post_w) ones.assign((size_t)std::max<int64_t>(1, n_post), 1.0f);
+        const double enc_ms = ms_since(t0);
+
+        // upload
+        auto t1 = std::chrono::steady_clock::now();
+        hipStream_t stream = (hipStream_t)hip_stream;
+        char* base = (char*)dev_arena;
+        HIP_TRY(hipMemcpyAsync(base + p.off_emb_f32, emb.data(), p.bytes_emb_f32, hipMemcpyHostToDevice, stream));
+        if (p.n_chunks > 0)
+            HIP_TRY(hipMemcpyAsync(base + p.off_chunks, hdr.data(), (size_t)p.n_chunks * 16, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(base + p.off_words, words.data(), p.bytes_words, hipMemcpyHostToDevice, stream));
+        if (n_post > 0)
+            HIP_TRY(hipMemcpyAsync(base + p.off_weights, desc->post_w ? desc->post_w : ones.data(),
+                                   (size_t)n_post * 4, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        const double up_ms = ms_since(t1);
+
+        ebr_index* ix = new ebr_index();
+        ix->n_ads = desc->n_ads;
+        ix->n_keys = V;
+        ix->n_postings = n_post;
+        ix->n_chunks = p.n_chunks;
+        ix->dim = desc->dim;
+        ix->n_tiles = (desc->n_ads + kTileAds - 1) / kTileAds;
+        ix->dtypes = 1u;
+        ix->emb_f32 = base + p.off_emb_f32;
+        ix->chunks = (const ChunkHdr*)(base + p.off_chunks);
+        ix->words = (const uint32_t*)(base + p.off_words);
+        ix->weights = (const float*)(base + p.off_weights);
+        ix->key_chunk_off = std::move(m.key_chunk_off);
+        ix->key_post_off.assign(desc->key_offsets ? desc->key_offsets : nullptr,
+                                desc->key_offsets ? desc->key_offsets + V + 1 : nullptr);
+        if (ix->key_post_off.empty()) ix->key_post_off.assign(1, 0);
+        ix->key_maxw = std::move(maxw);
+        if (hipGetDevice(&ix->device) != hipSuccess) ix->device = 0;
+        ebr_index_info& s = ix->stats;
+        s.n_ads = ix->n_ads;
+        s.n_keys = V;
+        s.n_postings = n_post;
+        s.n_chunks = p.n_chunks;
+        s.n_tiles = ix->n_tiles;
+        s.dim = ix->dim;
+        s.tile_ads = kTileAds;
+        s.arena_bytes = p.total;
+        s.bytes_emb_f32 = p.bytes_emb_f32;
+        s.bytes_chunk_headers = (uint64_t)p.n_chunks * 16;
+        s.bytes_packed_ids = (uint64_t)p.n_words * 4;
+        s.bytes_weights = (uint64_t)n_post * 4;
+        s.bits_per_id = n_post ? (double)(s.bytes_chunk_headers + s.bytes_packed_ids) * 8.0 / (double)n_post : 0.0;
+        s.bytes_per_posting = n_post ? (double)(s.bytes_chunk_headers + s.bytes_packed_ids + s.bytes_weights) / (double)n_post : 0.0;
+        s.encode_ms = enc_ms;
+        s.upload_ms = up_ms;
+        *out = ix;
+        return EBR_OK;
+    } catch (const std::bad_alloc&) {
+        set_error("host out of memory");
+        return EBR_ENOMEM;
+    }
+}
+
+ebr_status ebr_index_stats(const ebr_index* index, ebr_index_info* out) {
+    if (!index || !out) { set_error("NULL argument"); return EBR_EINVAL; }
+    *out = index->stats;
+    return EBR_OK;
+}
+
+void ebr_free_index(ebr_index* index) { delete index; }
+
+ebr_status ebr_decode_key(const ebr_index* index, int64_t key, uint32_t* ids, float* w,
+                          int64_t cap, int64_t* len, void* hip_stream) {
+    if (!index || !len) { set_error("NULL argument"); return EBR_EINVAL; }
+    if (key < 0 || key >= index->n_keys) { set_error("key %lld out of range", (long long)key); return EBR_EINVAL; }
+    const int64_t n = index->key_post_off[key + 1] - index->key_post_off[key];
+    *len = n;
+    if (cap < n) { set_error("capacity %lld < list length %lld", (long long)cap, (long long)n); return EBR_ENOMEM; }
+    if (n == 0) return EBR_OK;
+    if (!ids || !w) { set_error("NULL output"); return EBR_EINVAL; }
+    const uint32_t c0 = index->key_chunk_off[key], c1 = index->key_chunk_off[key + 1];
+    int rc = launch_decode_key(index->chunks, index->words, index->weights, c0, c1 - c0, ids, w, hip_stream);
+    if (rc) { set_error("decode launch failed: %s", hipGetErrorString((hipError_t)rc)); return EBR_EDEVICE; }
+    HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
+    return EBR_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== batch planning
+
+namespace ebr {
+
+struct Plan {
+    int B = 0, n_qg = 0, nu = 0;
+    int64_t nnz = 0;
+    int kmax = 0;
+    std::vector<uint32_t> uk_chunk_begin, uk_chunk_prefix, users_off, users;
+    std::vector<double> qscale, qinv;
+    std::vector<int32_t> kq, jq;
+    std::vector<int64_t> out_off;
+    std::vector<uint32_t> sample_tiles;
+    int64_t n_sample_valid = 0;
+    uint64_t bucket_n = 0;
+    uint32_t total_chunks = 0;
+    int64_t n_tiles = 0;
+    // workspace layout
+    size_t off_plan = 0, plan_bytes = 0;
+    size_t o_ukb = 0, o_ukp = 0, o_uoff = 0, o_users = 0, o_qs = 0, o_qi = 0, o_kq = 0, o_jq = 0,
+           o_oo = 0, o_st = 0;
+    size_t off_tcnt = 0, off_toff = 0, off_tfill = 0, off_stmp = 0, off_bucket = 0, off_skeys = 0,
+           off_thr = 0, off_status = 0, off_active = 0, off_ccnt = 0, off_unres = 0, off_cand = 0;
+    size_t total = 0;
+};
+
+static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Plan* P) {
+    if (!bt) { set_error("batch is NULL"); return EBR_EINVAL; }
+    const int B = bt->n_queries;
+    if (B < 0) { set_error("n_queries < 0"); return EBR_EINVAL; }
+    if (bt->scan_dtype != EBR_F32) { set_error("scan dtype %d not implemented", (int)bt->scan_dtype); return EBR_EUNSUPPORTED; }
+    P->B = B;
+    P->n_qg = (B + kGroupQueries - 1) / kGroupQueries;
+    P->n_tiles = ix.n_tiles;
+    if (B > 0 && (!bt->user_emb || !bt->feat_offsets || (topk && !bt->k))) { set_error("NULL batch array"); return EBR_EINVAL; }
+    const int64_t nnz = B > 0 ? bt->feat_offsets[B] : 0;
+    if (B > 0 && bt->feat_offsets[0] != 0) { set_error("feat_offsets[0] != 0"); return EBR_EINVAL; }
+    for (int q = 0; q < B; ++q)
+        if (bt->feat_offsets[q + 1] < bt->feat_offsets[q]) { set_error("feat_offsets decrease at query %d", q); return EBR_EINVAL; }
+    if (nnz > 0 && !bt->feat_keys) { set_error("feat_keys is NULL"); return EBR_EINVAL; }
+    P->nnz = nnz;
+    // keys in range, distinct within a query; multipliers finite
+    std::vector<int32_t> tmp;
+    for (int q = 0; q < B; ++q) {
+        const int64_t f0 = bt->feat_offsets[q], f1 = bt->feat_offsets[q + 1];
+        tmp.assign(bt->feat_keys + f0, bt->feat_keys + f1);
+        for (int32_t k : tmp)
+            if (k < 0 || k >= ix.n_keys) { set_error("query %d: key %d out of range [0, %lld)", q, k, (long long)ix.n_keys); return EBR_EINVAL; }
+        std::sort(tmp.begin(), tmp.end());
+        if (std::adjacent_find(tmp.begin(), tmp.end()) != tmp.end()) { set_error("query %d repeats a key", q); return EBR_EINVAL; }
+        if (bt->feat_mult)
+            for (int64_t j = f0; j < f1; ++j)
+                if (!std::isfinite(bt->feat_mult[j])) { set_error("query %d: non-finite multiplier", q); return EBR_EINVAL; }
+    }
+    P->kq.assign(B, 0);
+    P->kmax = 0;
+    if (topk) {
+        const int64_t kcap = std::min<int64_t>(ix.n_ads, kMaxK);
+        for (int q = 0; q < B; ++q) {
+            if (bt->k[q] < 0 || bt->k[q] > kcap) { set_error("query %d: K = %d outside [0, %lld]", q, bt->k[q], (long long)kcap); return EBR_EINVAL; }
+            P->kq[q] = bt->k[q];
+            P->kmax = std::max(P->kmax, bt->k[q]);
+        }
+    }
+    // distinct keys of the batch
+    std::vector<int32_t> uk(bt->feat_keys, bt->feat_keys + nnz);
+    std::sort(uk.begin(), uk.end());
+    uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
+    const int nu = (int)uk.size();
+    if (nu >= (1 << (32 - kTileShift))) { set_error("too many distinct keys in one batch"); return EBR_EINVAL; }
+    P->nu = nu;
+    P->uk_chunk_begin.resize(nu);
+    P->uk_chunk_prefix.assign(nu + 1, 0);
+    uint64_t chunks = 0, posts = 0;
+    for (int u = 0; u < nu; ++u) {
+        const int k = uk[u];
+        P->uk_chunk_begin[u] = ix.key_chunk_off[k];
+        P->uk_chunk_prefix[u] = (uint32_t)chunks;
+        chunks += ix.key_chunk_off[k + 1] - ix.key_chunk_off[k];
+        posts += (uint64_t)(ix.key_post_off[k + 1] - ix.key_post_off[k]);
+    }
+    P->uk_chunk_prefix[nu] = (uint32_t)chunks;
+    P->total_chunks = (uint32_t)chunks;
+    P->bucket_n = posts;
+    // users of each (distinct key, query group), in query order
+    const int nqg = std::max(1, P->n_qg);
+    std::vector<int32_t> slot(nnz);
+    P->users_off.assign((size_t)nu * nqg + 1, 0);
+    for (int q = 0; q < B; ++q)
+        for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
+            const int u = (int)(std::lower_bound(uk.begin(), uk.end(), bt->feat_keys[j]) - uk.begin());
+            slot[j] = u;
+            P->users_off[(size_t)u * nqg + q / kGroupQueries + 1]++;
+        }
+    for (size_t i = 1; i < P->users_off.size(); ++i) P->users_off[i] += P->users_off[i - 1];
+    P->users.assign((size_t)2 * std::max<int64_t>(1, nnz), 0u);
+    {
+        std::vector<uint32_t> fill(P->users_off.begin(), P->users_off.end() - 1);
+        for (int q = 0; q < B; ++q)
+            for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
+                const size_t s = (size_t)slot[j] * nqg + q / kGroupQueries;
+                const uint32_t pos = fill[s]++;
+                const float m = bt->feat_mult ? bt->feat_mult[j] : 1.0f;
+                uint32_t mb;
+                std::memcpy(&mb, &m, 4);
+                P->users[2 * pos] = (uint32_t)(q % kGroupQueries);
+                P->users[2 * pos + 1] = mb;
+            }
+    }
+    // per-query fixed-point scale of the cross term: sum |m| max|w| * 2^S < 2^61
+    P->qscale.assign(B, 1.0);
+    P->qinv.assign(B, 1.0);
+    for (int q = 0; q < B; ++q) {
+        double A = 0.0;
+        for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
+            const double m = bt->feat_mult ? (double)bt->feat_mult[j] : 1.0;
+            A += std::fabs(m) * (double)ix.key_maxw[bt->feat_keys[j]];
+        }
+        int S = 0;
+        if (A > 0.0 && std::isfinite(A)) {
+            int e;
+            std::frexp(A, &e);  // A < 2^e
+            S = 61 - e;
+            S = std::max(-1000, std::min(1000, S));
+        }
+        P->qscale[q] = std::ldexp(1.0, S);
+        P->qinv[q] = std::ldexp(1.0, -S);
+    }
+    // output offsets
+    P->out_off.assign(B + 1, 0);
+    for (int q = 0; q < B; ++q) P->out_off[q + 1] = P->out_off[q] + P->kq[q];
+    // sample tiles for the threshold: spread evenly, at least n_tiles / 64 and 16 * K ads
+    P->jq.assign(B, 0);
+    P->sample_tiles.clear();
+    if (topk && P->kmax > 0) {
+        const int64_t nt = ix.n_tiles;
+        int64_t ns = std::max<int64_t>((nt + 63) / 64, (16LL * P->kmax + kTileAds - 1) / kTileAds);
+        ns = std::min(ns, nt);
+        P->sample_tiles.resize(ns);
+        int64_t valid = 0;
+        for (int64_t i = 0; i < ns; ++i) {
+            const int64_t t = (i * nt) / ns;
+            P->sample_tiles[i] = (uint32_t)t;
+            valid += std::min<int64_t>(kTileAds, ix.n_ads - t * kTileAds);
+        }
+        P->n_sample_valid = valid;
+        const double f = (double)valid / (double)ix.n_ads;
+        for (int q = 0; q < B; ++q) {
+            const int K = P->kq[q];
+            if (K == 0) continue;
+            if (ns == nt) { P->jq[q] = K; continue; }
+            const double x = K * f;
+            int64_t j = (int64_t)std::ceil(x + 8.0 * std::sqrt(x) + 4.0);
+            P->jq[q] = (int32_t)std::min<int64_t>(j, valid);
+        }
+    }
+    // workspace layout
+    size_t off = 0;
+    auto put = [&](size_t bytes) { size_t o = off; off = align256(off + std::max<size_t>(bytes, 4)); return o; };
+    P->off_plan = off;
+    P->o_ukb = put(4 * (size_t)nu);
+    P->o_ukp = put(4 * (size_t)(nu + 1));
+    P->o_uoff = put(4 * P->users_off.size());
+    P->o_users = put(4 * P->users.size());
+    P->o_qs = put(8 * (size_t)B);
+    P->o_qi = put(8 * (size_t)B);
+    P->o_kq = put(4 * (size_t)B);
+    P->o_jq = put(4 * (size_t)B);
+    P->o_oo = put(8 * (size_t)(B + 1));
+    P->o_st = put(4 * P->sample_tiles.size());
+    P->plan_bytes = off - P->off_plan;
+    P->off_tcnt = put(4 * (size_t)(ix.n_tiles + 1));
+    P->off_toff = put(4 * (size_t)(ix.n_tiles + 1));
+    P->off_tfill = put(4 * (size_t)(ix.n_tiles + 1));
+    P->off_stmp = put(4 * (size_t)scan_tmp_words(ix.n_tiles + 1));
+    P->off_bucket = put(8 * (size_t)P->bucket_n);
+    if (topk) {
+        P->off_skeys = put(4 * (size_t)B * P->sample_tiles.size() * kTileAds);
+        P->off_thr = put(8 * (size_t)B);
+        P->off_status = put(4 * (size_t)B);
+        P->off_active = put(4 * (size_t)B);
+        P->off_ccnt = put(4 * (size_t)B);
+        P->off_unres = put(16);
+        P->off_cand = put(8 * (size_t)B * kCandCap);
+    }
+    P->total = off;
+    return EBR_OK;
+}
+
+static std::vector<char> pack_plan(const Plan& P) {
+    std::vector<char> blob(P.plan_bytes, 0);
+    auto cp = [&](size_t o, const void* src, size_t n) { if (n) std::memcpy(blob.data() + o - P.off_plan, src, n); };
+    cp(P.o_ukb, P.uk_chunk_begin.data(), 4 * P.uk_chunk_begin.size());
+    cp(P.o_ukp, P.uk_chunk_prefix.data(), 4 * P.uk_chunk_prefix.size());
+    cp(P.o_uoff, P.users_off.data(), 4 * P.users_off.size());
+    cp(P.o_users, P.users.data(), 4 * P.users.size());
+    cp(P.o_qs, P.qscale.data(), 8 * P.qscale.size());
+    cp(P.o_qi, P.qinv.data(), 8 * P.qinv.size());
+    cp(P.o_kq, P.kq.data(), 4 * P.kq.size());
+    cp(P.o_jq, P.jq.data(), 4 * P.jq.size());
+    cp(P.o_oo, P.out_off.data(), 8 * P.out_off.size());
+    cp(P.o_st, P.sample_tiles.data(), 4 * P.sample_tiles.size());
+    return blob;
+}
+
+static int score_ctas() {
+    static int ctas = 0;
+    if (ctas == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+        ctas = 2 * cus;
+    }
+    return ctas;
+}
+
+#define LAUNCH(expr)                                                                       \
+    do {                                                                                   \
+        int rc_ = (expr);                                                                  \
+        if (rc_) {                                                                         \
+            set_error("%s failed: %s", #expr, hipGetErrorString((hipError_t)rc_));         \
+            return EBR_EDEVICE;                                                            \
+        }                                                                                  \
+    } while (0)
+
+// Upload the plan, decode the batch's lists into tile buckets. Shared by top-K and dense.
+static ebr_status run_decode(const Index& ix, const Plan& P, char* ws, hipStream_t st,
+                             std::vector<char>& blob) {
+    blob = pack_plan(P);
+    HIP_TRY(hipMemcpyAsync(ws + P.off_plan, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
+    uint32_t* tcnt = (uint32_t*)(ws + P.off_tcnt);
+    uint32_t* toff = (uint32_t*)(ws + P.off_toff);
+    uint32_t* tfill = (uint32_t*)(ws + P.off_tfill);
+    LAUNCH(launch_fill_u32(tcnt, 0u, ix.n_tiles + 1, st));
+    LAUNCH(launch_fill_u32(tfill, 0u, ix.n_tiles + 1, st));
+    DecodeArgs d{};
+    d.chunks = ix.chunks;
+    d.words = ix.words;
+    d.weights = ix.weights;
+    d.uk_chunk_begin = (const uint32_t*)(ws + P.o_ukb);
+    d.uk_chunk_prefix = (const uint32_t*)(ws + P.o_ukp);
+    d.n_ukeys = P.nu;
+    d.total_chunks = P.total_chunks;
+    d.tile_cnt = tcnt;
+    d.tile_off = toff;
+    d.tile_fill = tfill;
+    d.bucket = (uint32_t*)(ws + P.off_bucket);
+    LAUNCH(launch_decode(d, 0, st));
+    LAUNCH(launch_excl_scan_u32(tcnt, toff, ix.n_tiles, (uint32_t*)(ws + P.off_stmp), st));
+    LAUNCH(launch_decode(d, 1, st));
+    return EBR_OK;
+}
+
+static ScoreArgs score_args(const Index& ix, const Plan& P, const ebr_batch* bt, char* ws) {
+    ScoreArgs s{};
+    s.emb = ix.emb_f32;
+    s.n_ads = ix.n_ads;
+    s.user = bt->user_emb;
+    s.n_queries = P.B;
+    s.n_qgroups = P.n_qg;
+    s.tile_off = (const uint32_t*)(ws + P.off_toff);
+    s.bucket = (const uint32_t*)(ws + P.off_bucket);
+    s.users_off = (const uint32_t*)(ws + P.o_uoff);
+    s.users = (const uint32_t*)(ws + P.o_users);
+    s.qscale = (const double*)(ws + P.o_qs);
+    s.qinv = (const double*)(ws + P.o_qi);
+    s.n_work = (int32_t)ix.n_tiles;
+    s.tile_list = nullptr;
+    return s;
+}
+
+static ebr_status check_users(const ebr_batch* bt, int B, int dim, hipStream_t st) {
+    if (B == 0) return EBR_OK;
+    std::vector<float> u((size_t)B * dim);
+    HIP_TRY(hipMemcpyAsync(u.data(), bt->user_emb, u.size() * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (size_t i = 0; i < u.size(); ++i)
+        if (!std::isfinite(u[i])) { set_error("query %zu: non-finite user embedding", i / dim); return EBR_EINVAL; }
+    return EBR_OK;
+}
+
+}  // namespace ebr
+
+extern "C" {
+
+ebr_status ebr_workspace_size(const ebr_index* index, const ebr_batch* batch, size_t* bytes) {
+    try {
+        if (!index || !bytes) { set_error("NULL argument"); return EBR_EINVAL; }
+        Plan P;
+        ebr_status st = plan_batch(*index, batch, true, &P);
+        if (st) return st;
+        *bytes = P.total;
+        return EBR_OK;
+    } catch (const std::bad_alloc&) {
+        set_error("host out of memory");
+        return EBR_ENOMEM;
+    }
+}
+
+ebr_status ebr_score_topk(const ebr_index* index, const ebr_batch* batch, void* ws_v,
+                          size_t ws_bytes, uint32_t* out_ids, float* out_scores, void* hip_stream) {
+    try {
+        if (!index) { set_error("index is NULL"); return EBR_EINVAL; }
+        const auto t_host = std::chrono::steady_clock::now();
+        const Index& ix = *index;
+        Plan P;
+        ebr_status st = plan_batch(ix, batch, true, &P);
+        if (st) return st;
+        if (!ws_v || ws_bytes < P.total) { set_error("workspace too small: need %zu bytes, got %zu", P.total, ws_bytes); return EBR_ENOMEM; }
+        if ((uintptr_t)ws_v & 255) { set_error("workspace must be 256-byte aligned"); return EBR_EINVAL; }
+        const int64_t n_out = P.out_off[P.B];
+        if (n_out > 0 && (!out_ids || !out_scores)) { set_error("NULL output"); return EBR_EINVAL; }
+        g_last_timings = ebr_timings{};
+        if (P.B == 0 || P.kmax == 0) return EBR_OK;
+        hipStream_t s = (hipStream_t)hip_stream;
+        st = check_users(batch, P.B, ix.dim, s);
+        if (st) return st;
+        const double host_ms = ms_since(t_host);
+        char* ws = (char*)ws_v;
+        PhaseClock clk(s);
+        const int e_dec0 = clk.mark();
+        std::vector<char> blob;
+        st = run_decode(ix, P, ws, s, blob);
+        if (st) return st;
+        const int e_dec1 = clk.mark();
+
+        const int B = P.B;
+        uint32_t* thr = (uint32_t*)(ws + P.off_thr);
+        int32_t* status = (int32_t*)(ws + P.off_status);
+        uint32_t* active = (uint32_t*)(ws + P.off_active);
+        uint32_t* ccnt = (uint32_t*)(ws + P.off_ccnt);
+        uint32_t* unres = (uint32_t*)(ws + P.off_unres);
+        unsigned long long* cand = (unsigned long long*)(ws + P.off_cand);
+        const int64_t ns = (int64_t)P.sample_tiles.size();
+
+        // sample pass and per-query threshold
+        ScoreArgs sa = score_args(ix, P, batch, ws);
+        sa.n_work = (int32_t)ns;
+        sa.tile_list = (const uint32_t*)(ws + P.o_st);
+        sa.sample_keys = (uint32_t*)(ws + P.off_skeys);
+        sa.sample_ld = ns * kTileAds;
+        LAUNCH(launch_score(sa, ix.dim, 1, score_ctas(), s));
+        SelectArgs se{};
+        se.keys = sa.sample_keys;
+        se.ld = sa.sample_ld;
+        se.n_cols = sa.sample_ld;
+        se.jq = (const int32_t*)(ws + P.o_jq);
+        se.kq = (const int32_t*)(ws + P.o_kq);
+        se.status = status;
+        se.only_status = -1;
+        se.thresh = thr;
+        LAUNCH(launch_select(se, B, s));
+        const int e_smp1 = clk.mark();
+
+        // per-query state: active iff K > 0
+        std::vector<uint32_t> act(B);
+        std::vector<int32_t> stat(B);
+        for (int q = 0; q < B; ++q) {
+            act[q] = P.kq[q] > 0 ? 1u : 0u;
+            stat[q] = P.kq[q] > 0 ? kStatusPending : kStatusDone;
+        }
+        HIP_TRY(hipMemcpyAsync(active, act.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(status, stat.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
+
+        ScoreArgs ca = score_args(ix, P, batch, ws);
+        ca.thresh = thr;
+        ca.active = active;
+        ca.cand = cand;
+        ca.cand_cnt = ccnt;
+        ca.cap = kCandCap;
+        FinalArgs fa{};
+        fa.active = active;
+        fa.kq = (const int32_t*)(ws + P.o_kq);
+        fa.cand_cnt = ccnt;
+        fa.cap = kCandCap;
+        fa.cand = cand;
+        fa.status = status;
+        fa.thresh = thr;
+        fa.unresolved = unres;
+        fa.out_off = (const int64_t*)(ws + P.o_oo);
+        fa.out_ids = out_ids;
+        fa.out_scores = out_scores;
+
+        // queries short of K candidates fall back to the sample's K-th key, which at least K
+        // sample ads reach (or to no threshold when the sample holds fewer than K ads)
+        std::vector<int32_t> jk(B);
+        for (int q = 0; q < B; ++q)
+            jk[q] = P.kq[q] <= P.n_sample_valid ? P.kq[q] : (int32_t)(P.n_sample_valid + 1);
+        std::vector<std::array<int, 3>> round_marks;
+        for (int round = 0;; ++round) {
+            if (round > 0) {
+                HIP_TRY(hipMemcpyAsync(ws + P.o_jq, jk.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
+                se.only_status = kStatusNeedLower;
+                LAUNCH(launch_select(se, B, s));
+            }
+            LAUNCH(launch_fill_u32(ccnt, 0u, B, s));
+            LAUNCH(launch_fill_u32(unres, 0u, 1, s));
+            const int e0 = clk.mark();
+            LAUNCH(launch_score(ca, ix.dim, 0, score_ctas(), s));
+            const int e1 = clk.mark();
+            LAUNCH(launch_finalize(fa, B, s));
+            const int e2 = clk.mark();
+            uint32_t left = 0;
+            HIP_TRY(hipMemcpyAsync(&left, unres, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            round_marks.push_back({e0, e1, e2});
+            if (left == 0) {
+                ebr_timings& t = g_last_timings;
+                t.host_ms = host_ms;
+                t.decode_ms = clk.ms(e_dec0, e_dec1);
+                t.sample_ms = clk.ms(e_dec1, e_smp1);
+                for (const auto& r : round_marks) {
+                    t.score_ms += clk.ms(r[0], r[1]);
+                    t.finalize_ms += clk.ms(r[1], r[2]);
+                }
+                t.rounds = round + 1;
+                break;
+            }
+            if (round >= 64) { set_error("top-K selection did not converge"); return EBR_EDEVICE; }
+        }
+        return EBR_OK;
+    } catch (const std::bad_alloc&) {
+        set_error("host out of memory");
+        return EBR_ENOMEM;
+    }
+}
+
+ebr_status ebr_score_dense(const ebr_index* index, const ebr_batch* batch, void* ws_v,
+                           size_t ws_bytes, float* deep, float* wide, void* hip_stream) {
+    try {
+        if (!index) { set_error("index is NULL"); return EBR_EINVAL; }
+        const Index& ix = *index;
+        Plan P;
+        ebr_status st = plan_batch(ix, batch, false, &P);
+        if (st) return st;
+        if (!ws_v || ws_bytes < P.total) { set_error("workspace too small: need %zu bytes, got %zu", P.total, ws_bytes); return EBR_ENOMEM; }
+        if ((uintptr_t)ws_v & 255) { set_error("workspace must be 256-byte aligned"); return EBR_EINVAL; }
+        if (P.B == 0) return EBR_OK;
+        if (!deep || !wide) { set_error("NULL output"); return EBR_EINVAL; }
+        hipStream_t s = (hipStream_t)hip_stream;
+        st = check_users(batch, P.B, ix.dim, s);
+        if (st) return st;
+        char* ws = (char*)ws_v;
+        std::vector<char> blob;
+        st = run_decode(ix, P, ws, s, blob);
+        if (st) return st;
+        ScoreArgs a = score_args(ix, P, batch, ws);
+        a.deep_out = deep;
+        a.wide_out = wide;
+        LAUNCH(launch_score(a, ix.dim, 2, score_ctas(), s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return EBR_OK;
+    } catch (const std::bad_alloc&) {
+        set_error("host out of memory");
+        return EBR_ENOMEM;
+    }
+}
+
+// ---------------------------------------------------------------- codec (host)
+
+ebr_status ebr_codec_size(const uint32_t* ids, int64_t n, size_t* bytes) {
+    if (!bytes || n < 0 || (n > 0 && !ids)) { set_error("bad argument"); return EBR_EINVAL; }
+    for (int64_t i = 1; i < n; ++i)
+        if (ids[i] <= ids[i - 1]) { set_error("ids not strictly increasing at %lld", (long long)i); return EBR_EINVAL; }
+    int64_t c, w;
+    codec_measure(ids, n, &c, &w);
+    *bytes = (size_t)c * 16 + (size_t)w * 4;
+    return EBR_OK;
+}
+
+ebr_status ebr_codec_encode(const uint32_t* ids, int64_t n, void* out, size_t cap, size_t* used) {
+    size_t need;
+    ebr_status st = ebr_codec_size(ids, n, &need);
+    if (st) return st;
+    if (!out || cap < need) { set_error("output too small: need %zu", need); return EBR_ENOMEM; }
+    int64_t c, w;
+    codec_measure(ids, n, &c, &w);
+    std::vector<ChunkHdr> hdr((size_t)c);
+    std::vector<uint32_t> words((size_t)w + 1, 0u);
+    codec_encode(ids, n, hdr.data(), words.data(), 0, 0);
+    std::memcpy(out, hdr.data(), (size_t)c * 16);
+    std::memcpy((char*)out + (size_t)c * 16, words.data(), (size_t)w * 4);
+    if (used) *used = need;
+    return EBR_OK;
+}
+
+ebr_status ebr_codec_decode(const void* in, size_t bytes, int64_t n, uint32_t* ids) {
+    if (n < 0 || (n > 0 && (!in || !ids))) { set_error("bad argument"); return EBR_EINVAL; }
+    const int64_t c = (n + kChunk - 1) / kChunk;
+    if (bytes < (size_t)c * 16 || (bytes - (size_t)c * 16) % 4) { set_error("malformed encoding size"); return EBR_EINVAL; }
+    std::vector<ChunkHdr> hdr((size_t)c);
+    std::memcpy(hdr.data(), in, (size_t)c * 16);
+    const int64_t nw = (int64_t)((bytes - (size_t)c * 16) / 4);
+    std::vector<uint32_t> words((size_t)nw + 1, 0u);
+    std::memcpy(words.data(), (const char*)in + (size_t)c * 16, (size_t)nw * 4);
+    if (!codec_decode(hdr.data(), c, words.data(), nw, n, ids)) { set_error("malformed encoding"); return EBR_EINVAL; }
+    return EBR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal declarations shared by the host runtime and the gfx950 kernels of libebr.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ebr.h"
+
+namespace ebr {
+
+// ---------------------------------------------------------------- layout constants
+
+// Ads per tile: one 32-wide column block of the 32x32 matrix-core tile, and the
+// unit of the tile-major posting buckets built per batch.
+constexpr int kTileAds = 32;
+constexpr int kTileShift = 5;
+// Queries per query group: 8 waves x one 32-row block each.
+constexpr int kGroupQueries = 256;
+// Postings per compressed chunk: one per lane of a 64-wide wavefront.
+constexpr int kChunk = 64;
+// Candidate slots per query in the selection buffer (sorted in LDS at the end).
+constexpr int kCandCap = 16384;
+// Largest K a query may ask for.
+constexpr int kMaxK = 8192;
+
+// One compressed chunk of up to 64 postings of one key.
+//  first_id  id of posting 0
+//  info      bits 0..5: gap width b (0..32); bits 8..14: count (1..64)
+//  word_off  first 32-bit word of the packed gaps in the index's word array
+//  post_off  index of posting 0 in the weight array
+// Gaps g_i = id_i - id_{i-1} - 1 (i = 1..count-1) are stored LSB-first, b bits
+// each, starting at bit 0 of word word_off.
+struct ChunkHdr {
+    uint32_t first_id;
+    uint32_t info;
+    uint32_t word_off;
+    uint32_t post_off;
+};
+static_assert(sizeof(ChunkHdr) == 16, "chunk header is 16 bytes");
+
+inline int hdr_bits(uint32_t info) { return (int)(info & 63u); }
+inline int hdr_count(uint32_t info) { return (int)((info >> 8) & 127u); }
+
+// ---------------------------------------------------------------- host-side index
+
+struct Index {
+    int64_t n_ads = 0, n_keys = 0, n_postings = 0, n_chunks = 0;
+    int32_t dim = 0;
+    int64_t n_tiles = 0;      // ceil(n_ads / 32)
+    uint32_t dtypes = 0;
+    // device pointers into the caller's arena
+    const void* emb_f32 = nullptr;   // swizzled, see kernels.hip
+    const ChunkHdr* chunks = nullptr;
+    const uint32_t* words = nullptr;
+    const float* weights = nullptr;
+    // host copies for planning
+    std::vector<uint32_t> key_chunk_off;  // V + 1
+    std::vector<int64_t> key_post_off;    // V + 1
+    std::vector<float> key_maxw;          // V, max |w| of each list
+    ebr_index_info stats{};
+    int device = 0;
+};
+
+// Arena plan: byte offsets of each section (256-byte aligned).
+struct ArenaPlan {
+    size_t off_emb_f32 = 0, off_chunks = 0, off_words = 0, off_weights = 0, total = 0;
+    size_t bytes_emb_f32 = 0, bytes_chunks = 0, bytes_words = 0, bytes_weights = 0;
+    int64_t n_chunks = 0, n_words = 0;
+};
+
+// ---------------------------------------------------------------- error plumbing
+
+void set_error(const char* fmt, ...);
+const char* last_error();
+
+// ---------------------------------------------------------------- codec (host)
+
+// Number of chunks and packed words a list of n ids occupies.
+void codec_measure(const uint32_t* ids, int64_t n, int64_t* chunks, int64_t* words);
+// Encode one list: hdr receives ceil(n/64) headers (word_off relative to
+// word_base, post_off relative to post_base), words receives the packed gaps.
+void codec_encode(const uint32_t* ids, int64_t n, ChunkHdr* hdr, uint32_t* words,
+                  uint32_t word_base, uint32_t post_base);
+// Decode one list encoded with word_base = post_base = 0.
+bool codec_decode(const ChunkHdr* hdr, int64_t n_chunks, const uint32_t* words,
+                  int64_t n_words, int64_t n, uint32_t* ids);
+
+// ---------------------------------------------------------------- kernels
+
+// Every launcher returns hipSuccess or the first HIP error (as int).
+struct ScoreArgs;
+
+int launch_swizzle_f32(const float* src_rows, int64_t n_rows, int64_t row0, int32_t dim,
+                       void* dst, void* stream);
+
+}  // namespace ebr

@@ -1,0 +1,93 @@
+// Kernel argument blocks and launchers of libebr (host <-> device interface).
+#pragma once
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace ebr {
+
+constexpr int kStatusDone = 0;
+constexpr int kStatusPending = 1;
+constexpr int kStatusNeedLower = 2;
+constexpr int kStatusOverflow = 3;
+
+struct DecodeArgs {
+    const ChunkHdr* chunks;
+    const uint32_t* words;
+    const float* weights;
+    const uint32_t* uk_chunk_begin;   // per distinct key: its first chunk in the index
+    const uint32_t* uk_chunk_prefix;  // n_ukeys + 1 prefix sums of chunk counts
+    int32_t n_ukeys;
+    uint32_t total_chunks;
+    uint32_t* tile_cnt;               // count pass
+    const uint32_t* tile_off;         // place pass
+    uint32_t* tile_fill;              // place pass
+    uint32_t* bucket;                 // place pass: pairs (slot << 5 | ad & 31, weight bits)
+};
+
+struct ScoreArgs {
+    const void* emb;                  // swizzled FP32 embeddings
+    int64_t n_ads;
+    const float* user;                // B x D
+    int32_t n_queries;
+    int32_t n_qgroups;
+    const uint32_t* tile_off;         // n_tiles + 1
+    const uint32_t* bucket;           // pairs
+    const uint32_t* users_off;        // n_ukeys * n_qgroups + 1
+    const uint32_t* users;            // pairs (query within group, multiplier bits)
+    const double* qscale;             // 2^S per query
+    const double* qinv;               // 2^-S per query
+    int32_t n_work;                   // tiles to visit
+    const uint32_t* tile_list;        // null: tile = work index
+    // collect mode
+    const uint32_t* thresh;           // pairs (key hi, ~id lo) per query
+    const uint32_t* active;           // per query
+    unsigned long long* cand;         // B x cap
+    uint32_t* cand_cnt;               // B
+    int32_t cap;
+    // sample mode
+    uint32_t* sample_keys;
+    int64_t sample_ld;
+    // dense mode
+    float* deep_out;
+    float* wide_out;
+};
+
+struct SelectArgs {
+    const uint32_t* keys;
+    int64_t ld;
+    int64_t n_cols;
+    const int32_t* jq;
+    const int32_t* kq;
+    const int32_t* status;
+    int32_t only_status;              // -1: every query with K > 0
+    uint32_t* thresh;
+};
+
+struct FinalArgs {
+    uint32_t* active;
+    const int32_t* kq;
+    const uint32_t* cand_cnt;
+    int32_t cap;
+    const unsigned long long* cand;
+    int32_t* status;
+    uint32_t* thresh;
+    uint32_t* unresolved;
+    const int64_t* out_off;
+    uint32_t* out_ids;
+    float* out_scores;
+};
+
+int launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, void* stream);
+int64_t scan_tmp_words(int64_t n);
+int launch_excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, void* stream);
+int launch_decode(const DecodeArgs& a, int place, void* stream);
+int launch_decode_key(const ChunkHdr* chunks, const uint32_t* words, const float* weights,
+                      uint32_t chunk0, uint32_t n_chunks, uint32_t* ids, float* w, void* stream);
+bool score_dim_supported(int dim);
+int launch_score(const ScoreArgs& a, int dim, int mode, int ctas, void* stream);
+int launch_select(const SelectArgs& a, int n_queries, void* stream);
+int launch_finalize(const FinalArgs& a, int n_queries, void* stream);
+
+}  // namespace ebr

@@ -1,0 +1,231 @@
+"""GPU parity of libebr against the FP64 oracle (through the C ABI).
+
+Every case compares the library's top-K (ids, FP32 scores) with the oracle's FP64
+scores of all ads under the criteria in parity.py: scores within 1e-5 relative,
+the id set exact up to ties inside the tolerance band, ordering by (score desc,
+id asc). Tests whose scores are exact in FP32 use a zero band (exact ids and
+order). Sizes span many 32-ad tiles, ragged tails and two 256-query groups.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import check_topk
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+E = pytest.importorskip("paper_2511_22460_amd")
+
+REL = 1e-5
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def run(ix, wl, **kw):
+    ids, sc, offs = ix.topk_workload(wl, **kw)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy().view(np.uint32), sc.cpu().numpy(), offs
+
+
+def check_all(wl, ids, sc, offs, qs=None, exact=False, cond=False, label=""):
+    oix = oracle.Index.of(wl)
+    recalls = []
+    for q in (range(wl.n_queries) if qs is None else qs):
+        mult = None if wl.feat_mult is None else wl.query_mults(q)
+        deep, wide, c = oracle.scores(oix, wl.user_emb[q], wl.query_keys(q), mult)
+        a, b = offs[q], offs[q + 1]
+        recalls.append(check_topk(ids[a:b], sc[a:b], int(wl.k[q]), deep + wide, rel_tol=REL,
+                                  cond_all=c if cond else None, exact=exact,
+                                  label=f"{label} query {q}"))
+    assert min(recalls) == 1.0
+    return recalls
+
+
+def small_wl(**kw):
+    base = dict(n_ads=20_017, dim=64, n_keys=600, lengths=("zipf_draw", 1.2, 5, 6000),
+                n_queries=300, feats=(0, 24), key_draw=("uniform",), k=(0, 300))
+    base.update(kw)
+    return W.make("c1", **base)
+
+
+@pytest.fixture(scope="module")
+def small():
+    dev()
+    wl = small_wl()
+    return wl, E.Index.from_workload(wl)
+
+
+# ----------------------------------------------------------------------------- decode
+
+def test_decode_every_key_bit_exact(small):
+    wl, ix = small
+    for k in range(wl.n_keys):
+        ids, w = ix.decode_key(k)
+        s, e = wl.key_offsets[k], wl.key_offsets[k + 1]
+        assert np.array_equal(ids.cpu().numpy().view(np.uint32), wl.post_ids[s:e]), k
+        assert np.array_equal(w.cpu().numpy().view(np.uint32), wl.post_w[s:e].view(np.uint32)), k
+    st = ix.stats()
+    assert st["n_postings"] == wl.n_postings and st["bytes_per_posting"] < 6.0
+
+
+# ----------------------------------------------------------------------------- dense terms
+
+@pytest.mark.parametrize("dim", [16, 48, 64, 128])
+def test_dense_terms_match_oracle(dim):
+    wl = small_wl(dim=dim, n_ads=3001, n_queries=40, feats=(0, 12))
+    rng = np.random.default_rng(dim)
+    wl.feat_mult = rng.normal(0, 3, size=len(wl.feat_keys)).astype(np.float32)
+    ix = E.Index.from_workload(wl)
+    U = torch.from_numpy(wl.user_emb).to(dev())
+    deep, wide = ix.score_dense(U, wl.feat_offsets, wl.feat_keys, wl.feat_mult)
+    deep, wide = deep.cpu().numpy().astype(np.float64), wide.cpu().numpy().astype(np.float64)
+    oix = oracle.Index.of(wl)
+    for q in range(wl.n_queries):
+        d, w, c = oracle.scores(oix, wl.user_emb[q], wl.query_keys(q), wl.query_mults(q))
+        assert np.all(np.abs(deep[q] - d) <= 1e-6 * (np.abs(wl.user_emb[q]).sum() + 1e-30) + 0)
+        assert np.all(np.abs(wide[q] - w) <= 2 ** -23 * np.abs(w) + 1e-12)
+    # additivity: the wide term does not depend on u, the deep term not on the features
+    deep0, wide0 = ix.score_dense(torch.zeros_like(U), wl.feat_offsets, wl.feat_keys, wl.feat_mult)
+    nof = np.zeros(wl.n_queries + 1, np.int64)
+    deep1, wide1 = ix.score_dense(U, nof, np.zeros(0, np.int32))
+    assert torch.equal(wide0.cpu(), torch.from_numpy(wide.astype(np.float32)))
+    assert torch.equal(deep1.cpu(), torch.from_numpy(deep.astype(np.float32)))
+    assert (deep0.cpu() == 0).all() and (wide1.cpu() == 0).all()
+
+
+# ----------------------------------------------------------------------------- top-K
+
+def test_topk_small_ragged_two_groups(small):
+    wl, ix = small
+    ids, sc, offs = run(ix, wl)
+    assert offs[-1] == int(wl.k.sum())
+    check_all(wl, ids, sc, offs, label="small")
+
+
+def test_topk_is_deterministic_and_same_alone_as_in_a_mix(small):
+    wl, ix = small
+    ids1, sc1, offs = run(ix, wl)
+    ids2, sc2, _ = run(ix, wl)
+    assert np.array_equal(ids1, ids2) and np.array_equal(sc1.view(np.uint32), sc2.view(np.uint32))
+    for q in (3, 150, 299):
+        a_ids, a_sc, _ = run(ix, wl, qs=[q])
+        a, b = offs[q], offs[q + 1]
+        assert np.array_equal(a_ids, ids1[a:b]), q
+        assert np.array_equal(a_sc.view(np.uint32), sc1[a:b].view(np.uint32)), q
+
+
+def test_topk_c1_config():
+    dev()
+    wl = W.make("c1")
+    ix = E.Index.from_workload(wl)
+    ids, sc, offs = run(ix, wl)
+    check_all(wl, ids, sc, offs, label="c1")
+
+
+@pytest.mark.parametrize("dim", [16, 32, 96])
+def test_topk_other_dims(dim):
+    wl = small_wl(dim=dim, n_ads=5000, n_queries=20, k=(1, 64))
+    ix = E.Index.from_workload(wl)
+    ids, sc, offs = run(ix, wl)
+    check_all(wl, ids, sc, offs, label=f"d={dim}")
+
+
+def test_topk_k_edge_cases():
+    # K = N returns every ad, including those whose deep and wide terms cancel to near zero;
+    # there the score tolerance is relative to the condition magnitude (sum of |terms|).
+    wl = small_wl(n_ads=3000, n_queries=5, k=1)
+    wl.k = np.array([0, 1, 3000, 2999, 17], np.int32)
+    ix = E.Index.from_workload(wl)
+    ids, sc, offs = run(ix, wl)
+    check_all(wl, ids, sc, offs, cond=True, label="k edge")
+    wl.k = np.zeros(5, np.int32)
+    ids, sc, offs = ix.topk_workload(wl)
+    assert offs[-1] == 0
+
+
+def test_topk_exact_ties_integer_counts():
+    # u = 0 and unit weights: every score is an integer hit count, exact in FP32; massive ties
+    # are broken by the smaller ad id, so the result must equal the oracle's exactly.
+    wl = small_wl(n_ads=40_000, n_keys=50, lengths=("zipf_draw", 1.05, 2000, 30000),
+                  n_queries=12, feats=(4, 20), k=(100, 2000))
+    wl.post_w = np.ones_like(wl.post_w)
+    wl.user_emb = np.zeros_like(wl.user_emb)
+    ix = E.Index.from_workload(wl)
+    ids, sc, offs = run(ix, wl)
+    check_all(wl, ids, sc, offs, exact=True, label="ties")
+
+
+def test_topk_duplicated_rows_tie_to_lower_id():
+    wl = small_wl(n_ads=8192, n_queries=6, feats=0, k=(50, 500))
+    base = wl.ad_emb[:1024].copy()
+    wl.ad_emb = np.ascontiguousarray(np.repeat(base, 8, axis=0))   # 8 identical rows each
+    ix = E.Index.from_workload(wl)
+    ids, sc, offs = run(ix, wl)
+    check_all(wl, ids, sc, offs, label="dup rows")
+    for q in range(wl.n_queries):
+        r = ids[offs[q]:offs[q + 1]].astype(np.int64)
+        s = sc[offs[q]:offs[q + 1]]
+        for i in range(len(r) - 1):
+            if s[i] == s[i + 1]:
+                assert r[i] < r[i + 1]
+
+
+def test_topk_cancellation_uses_condition_tolerance():
+    # large opposite multipliers make s << cond for many ads
+    wl = small_wl(n_ads=6000, n_queries=10, feats=(2, 10), k=(10, 200))
+    rng = np.random.default_rng(9)
+    wl.feat_mult = (rng.choice([-1, 1], size=len(wl.feat_keys)) * 50).astype(np.float32)
+    ix = E.Index.from_workload(wl)
+    ids, sc, offs = run(ix, wl)
+    check_all(wl, ids, sc, offs, cond=True, label="cancel")
+
+
+def test_batch_input_errors(small):
+    wl, ix = small
+    U = torch.from_numpy(wl.user_emb[:2]).to(dev())
+    offs = np.array([0, 2, 3], np.int64)
+    with pytest.raises(E.EbrError) as ei:
+        ix.score_topk(U, offs, np.array([1, 1, 2], np.int32), np.array([5, 5], np.int32))
+    assert ei.value.status == E.EBR_EINVAL                      # repeated key
+    with pytest.raises(E.EbrError):
+        ix.score_topk(U, offs, np.array([1, 2, wl.n_keys], np.int32), np.array([5, 5], np.int32))
+    with pytest.raises(E.EbrError):
+        ix.score_topk(U, offs, np.array([1, 2, 3], np.int32), np.array([5, wl.n_ads + 1], np.int32))
+    Ubad = U.clone()
+    Ubad[1, 3] = float("nan")
+    with pytest.raises(E.EbrError):
+        ix.score_topk(Ubad, offs, np.array([1, 2, 3], np.int32), np.array([5, 5], np.int32))
+
+
+# ----------------------------------------------------------------------------- full size
+
+@pytest.fixture(scope="module")
+def c2():
+    dev()
+    wl = W.make("c2")
+    ix = E.Index.from_workload(wl)
+    return wl, ix
+
+
+def test_c2_full_size_sampled_queries(c2):
+    """10M ads, ~4e8 postings, 256 queries x 32 keys, K = 1000, the benchmark's launch.
+    Four sampled queries are checked in full against the oracle."""
+    wl, ix = c2
+    ids, sc, offs = run(ix, wl)
+    assert offs[-1] == 256 * 1000
+    check_all(wl, ids, sc, offs, qs=[0, 77, 154, 255], label="c2")
+
+
+def test_c2_decode_sampled_keys_bit_exact(c2):
+    wl, ix = c2
+    for k in [0, 1, 2, 17, 500, 12_345, 999_999]:
+        ids, w = ix.decode_key(k)
+        s, e = wl.key_offsets[k], wl.key_offsets[k + 1]
+        assert np.array_equal(ids.cpu().numpy().view(np.uint32), wl.post_ids[s:e]), k
+        assert np.array_equal(w.cpu().numpy().view(np.uint32), wl.post_w[s:e].view(np.uint32)), k
