@@ -332,6 +332,15 @@ ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t a
                                 desc->key_offsets ? desc->key_offsets + V + 1 : nullptr);
         if (ix->key_post_off.empty()) ix->key_post_off.assign(1, 0);
         ix->key_maxw = std::move(maxw);
+        // per-key weight scale: |w| * 2^Sw < 2^30 with max |w| * 2^Sw >= 2^29
+        ix->key_wshift.assign((size_t)V, 0);
+        for (int64_t k = 0; k < V; ++k) {
+            if (ix->key_maxw[k] > 0.0f) {
+                int e;
+                std::frexp((double)ix->key_maxw[k], &e);  // max|w| < 2^e
+                ix->key_wshift[k] = (int8_t)std::max(-120, std::min(120, 30 - e));
+            }
+        }
         if (hipGetDevice(&ix->device) != hipSuccess) ix->device = 0;
         ebr_index_info& s = ix->stats;
         s.n_ads = ix->n_ads;
@@ -389,11 +398,13 @@ ebr_status ebr_decode_key(const ebr_index* index, int64_t key, uint32_t* ids, fl
 namespace ebr {
 
 struct Plan {
-    int B = 0, n_qg = 0, nu = 0;
+    int B = 0, gq = 256, n_qg = 0, nu = 0;
+    bool packed = false;  // bucket entries carry users ranges: one query group, < 2^19 features
     int64_t nnz = 0;
     int kmax = 0;
     std::vector<uint32_t> uk_chunk_begin, uk_chunk_prefix, users_off, users;
-    std::vector<double> qscale, qinv;
+    std::vector<int32_t> uk_wshift;
+    std::vector<double> qinv;
     std::vector<int32_t> kq, jq;
     std::vector<int64_t> out_off;
     std::vector<uint32_t> sample_tiles;
@@ -403,7 +414,7 @@ struct Plan {
     int64_t n_tiles = 0;
     // workspace layout
     size_t off_plan = 0, plan_bytes = 0;
-    size_t o_ukb = 0, o_ukp = 0, o_uoff = 0, o_users = 0, o_qs = 0, o_qi = 0, o_kq = 0, o_jq = 0,
+    size_t o_ukb = 0, o_ukp = 0, o_ukw = 0, o_uoff = 0, o_users = 0, o_qi = 0, o_kq = 0, o_jq = 0,
            o_oo = 0, o_st = 0;
     size_t off_tcnt = 0, off_toff = 0, off_tfill = 0, off_stmp = 0, off_bucket = 0, off_skeys = 0,
            off_thr = 0, off_status = 0, off_active = 0, off_ccnt = 0, off_unres = 0, off_cand = 0;
@@ -416,7 +427,8 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     if (B < 0) { set_error("n_queries < 0"); return EBR_EINVAL; }
     if (bt->scan_dtype != EBR_F32) { set_error("scan dtype %d not implemented", (int)bt->scan_dtype); return EBR_EUNSUPPORTED; }
     P->B = B;
-    P->n_qg = (B + kGroupQueries - 1) / kGroupQueries;
+    P->gq = score_group_queries(ix.dim);
+    P->n_qg = (B + P->gq - 1) / P->gq;
     P->n_tiles = ix.n_tiles;
     if (B > 0 && (!bt->user_emb || !bt->feat_offsets || (topk && !bt->k))) { set_error("NULL batch array"); return EBR_EINVAL; }
     const int64_t nnz = B > 0 ? bt->feat_offsets[B] : 0;
@@ -425,6 +437,7 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         if (bt->feat_offsets[q + 1] < bt->feat_offsets[q]) { set_error("feat_offsets decrease at query %d", q); return EBR_EINVAL; }
     if (nnz > 0 && !bt->feat_keys) { set_error("feat_keys is NULL"); return EBR_EINVAL; }
     P->nnz = nnz;
+    if (nnz >= (1LL << 31)) { set_error("more than 2^31 features in one batch"); return EBR_EINVAL; }
     // keys in range, distinct within a query; multipliers finite
     std::vector<int32_t> tmp;
     for (int q = 0; q < B; ++q) {
@@ -455,13 +468,16 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     const int nu = (int)uk.size();
     if (nu >= (1 << (32 - kTileShift))) { set_error("too many distinct keys in one batch"); return EBR_EINVAL; }
     P->nu = nu;
+    P->packed = P->n_qg == 1 && nnz < (1LL << 19);
     P->uk_chunk_begin.resize(nu);
     P->uk_chunk_prefix.assign(nu + 1, 0);
+    P->uk_wshift.resize(nu);
     uint64_t chunks = 0, posts = 0;
     for (int u = 0; u < nu; ++u) {
         const int k = uk[u];
         P->uk_chunk_begin[u] = ix.key_chunk_off[k];
         P->uk_chunk_prefix[u] = (uint32_t)chunks;
+        P->uk_wshift[u] = ix.key_wshift[k];
         chunks += ix.key_chunk_off[k + 1] - ix.key_chunk_off[k];
         posts += (uint64_t)(ix.key_post_off[k + 1] - ix.key_post_off[k]);
     }
@@ -476,25 +492,11 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
             const int u = (int)(std::lower_bound(uk.begin(), uk.end(), bt->feat_keys[j]) - uk.begin());
             slot[j] = u;
-            P->users_off[(size_t)u * nqg + q / kGroupQueries + 1]++;
+            P->users_off[(size_t)u * nqg + q / P->gq + 1]++;
         }
     for (size_t i = 1; i < P->users_off.size(); ++i) P->users_off[i] += P->users_off[i - 1];
-    P->users.assign((size_t)2 * std::max<int64_t>(1, nnz), 0u);
-    {
-        std::vector<uint32_t> fill(P->users_off.begin(), P->users_off.end() - 1);
-        for (int q = 0; q < B; ++q)
-            for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
-                const size_t s = (size_t)slot[j] * nqg + q / kGroupQueries;
-                const uint32_t pos = fill[s]++;
-                const float m = bt->feat_mult ? bt->feat_mult[j] : 1.0f;
-                uint32_t mb;
-                std::memcpy(&mb, &m, 4);
-                P->users[2 * pos] = (uint32_t)(q % kGroupQueries);
-                P->users[2 * pos + 1] = mb;
-            }
-    }
-    // per-query fixed-point scale of the cross term: sum |m| max|w| * 2^S < 2^61
-    P->qscale.assign(B, 1.0);
+    // per-query fixed-point scale of the cross term: sum_j |m_j| max|W[k_j,:]| * 2^S < 2^60
+    std::vector<int> Sq(B, 0);
     P->qinv.assign(B, 1.0);
     for (int q = 0; q < B; ++q) {
         double A = 0.0;
@@ -506,11 +508,36 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         if (A > 0.0 && std::isfinite(A)) {
             int e;
             std::frexp(A, &e);  // A < 2^e
-            S = 61 - e;
-            S = std::max(-1000, std::min(1000, S));
+            S = std::max(-900, std::min(900, 60 - e));
         }
-        P->qscale[q] = std::ldexp(1.0, S);
+        // every multiplier must also fit its int32 field: |m| 2^(S - Sw_k) < 2^31
+        double mx = 0.0;
+        for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
+            const double m = bt->feat_mult ? (double)bt->feat_mult[j] : 1.0;
+            mx = std::max(mx, std::ldexp(std::fabs(m), S - ix.key_wshift[bt->feat_keys[j]]));
+        }
+        if (mx >= 2147483520.0) {
+            int e;
+            std::frexp(mx, &e);  // mx < 2^e
+            S -= e - 30;
+        }
+        Sq[q] = S;
         P->qinv[q] = std::ldexp(1.0, -S);
+    }
+    // users: (query within its group, m_fix = round(m * 2^(S_q - Sw_k))), in query order
+    P->users.assign((size_t)2 * std::max<int64_t>(1, nnz), 0u);
+    {
+        std::vector<uint32_t> fill(P->users_off.begin(), P->users_off.end() - 1);
+        for (int q = 0; q < B; ++q)
+            for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
+                const size_t s = (size_t)slot[j] * nqg + q / P->gq;
+                const uint32_t pos = fill[s]++;
+                const double m = bt->feat_mult ? (double)bt->feat_mult[j] : 1.0;
+                const int sw = ix.key_wshift[bt->feat_keys[j]];
+                const long long mf = std::llrint(std::ldexp(m, Sq[q] - sw));
+                P->users[2 * pos] = (uint32_t)(q % P->gq);
+                P->users[2 * pos + 1] = (uint32_t)(int32_t)mf;
+            }
     }
     // output offsets
     P->out_off.assign(B + 1, 0);
@@ -546,9 +573,9 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     P->off_plan = off;
     P->o_ukb = put(4 * (size_t)nu);
     P->o_ukp = put(4 * (size_t)(nu + 1));
+    P->o_ukw = put(4 * (size_t)nu);
     P->o_uoff = put(4 * P->users_off.size());
     P->o_users = put(4 * P->users.size());
-    P->o_qs = put(8 * (size_t)B);
     P->o_qi = put(8 * (size_t)B);
     P->o_kq = put(4 * (size_t)B);
     P->o_jq = put(4 * (size_t)B);
@@ -580,7 +607,7 @@ static std::vector<char> pack_plan(const Plan& P) {
     cp(P.o_ukp, P.uk_chunk_prefix.data(), 4 * P.uk_chunk_prefix.size());
     cp(P.o_uoff, P.users_off.data(), 4 * P.users_off.size());
     cp(P.o_users, P.users.data(), 4 * P.users.size());
-    cp(P.o_qs, P.qscale.data(), 8 * P.qscale.size());
+    cp(P.o_ukw, P.uk_wshift.data(), 4 * P.uk_wshift.size());
     cp(P.o_qi, P.qinv.data(), 8 * P.qinv.size());
     cp(P.o_kq, P.kq.data(), 4 * P.kq.size());
     cp(P.o_jq, P.jq.data(), 4 * P.jq.size());
@@ -595,7 +622,7 @@ static int score_ctas() {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-        ctas = 2 * cus;
+        ctas = cus;  // one scoring work-group per compute unit (it holds ~150 KiB of LDS)
     }
     return ctas;
 }
@@ -625,12 +652,15 @@ static ebr_status run_decode(const Index& ix, const Plan& P, char* ws, hipStream
     d.weights = ix.weights;
     d.uk_chunk_begin = (const uint32_t*)(ws + P.o_ukb);
     d.uk_chunk_prefix = (const uint32_t*)(ws + P.o_ukp);
+    d.uk_wshift = (const int32_t*)(ws + P.o_ukw);
     d.n_ukeys = P.nu;
     d.total_chunks = P.total_chunks;
     d.tile_cnt = tcnt;
     d.tile_off = toff;
     d.tile_fill = tfill;
     d.bucket = (uint32_t*)(ws + P.off_bucket);
+    // one query group: bucket entries carry their key's users range directly
+    d.users_off = P.packed ? (const uint32_t*)(ws + P.o_uoff) : nullptr;
     LAUNCH(launch_decode(d, 0, st));
     LAUNCH(launch_excl_scan_u32(tcnt, toff, ix.n_tiles, (uint32_t*)(ws + P.off_stmp), st));
     LAUNCH(launch_decode(d, 1, st));
@@ -644,11 +674,11 @@ static ScoreArgs score_args(const Index& ix, const Plan& P, const ebr_batch* bt,
     s.user = bt->user_emb;
     s.n_queries = P.B;
     s.n_qgroups = P.n_qg;
+    s.packed = P.packed ? 1 : 0;
     s.tile_off = (const uint32_t*)(ws + P.off_toff);
     s.bucket = (const uint32_t*)(ws + P.off_bucket);
     s.users_off = (const uint32_t*)(ws + P.o_uoff);
     s.users = (const uint32_t*)(ws + P.o_users);
-    s.qscale = (const double*)(ws + P.o_qs);
     s.qinv = (const double*)(ws + P.o_qi);
     s.n_work = (int32_t)ix.n_tiles;
     s.tile_list = nullptr;
@@ -772,10 +802,14 @@ ebr_status ebr_score_topk(const ebr_index* index, const ebr_batch* batch, void* 
         std::vector<int32_t> jk(B);
         for (int q = 0; q < B; ++q)
             jk[q] = P.kq[q] <= P.n_sample_valid ? P.kq[q] : (int32_t)(P.n_sample_valid + 1);
+        // a query still short after that takes no threshold at all (every ad is a candidate;
+        // the overflow rule then narrows it)
+        std::vector<int32_t> jall(B, (int32_t)(P.n_sample_valid + 1));
         std::vector<std::array<int, 3>> round_marks;
         for (int round = 0;; ++round) {
             if (round > 0) {
-                HIP_TRY(hipMemcpyAsync(ws + P.o_jq, jk.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
+                HIP_TRY(hipMemcpyAsync(ws + P.o_jq, (round == 1 ? jk : jall).data(), 4 * (size_t)B,
+                                       hipMemcpyHostToDevice, s));
                 se.only_status = kStatusNeedLower;
                 LAUNCH(launch_select(se, B, s));
             }

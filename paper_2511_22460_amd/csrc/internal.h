@@ -16,8 +16,6 @@ namespace ebr {
 // unit of the tile-major posting buckets built per batch.
 constexpr int kTileAds = 32;
 constexpr int kTileShift = 5;
-// Queries per query group: 8 waves x one 32-row block each.
-constexpr int kGroupQueries = 256;
 // Postings per compressed chunk: one per lane of a 64-wide wavefront.
 constexpr int kChunk = 64;
 // Candidate slots per query in the selection buffer (sorted in LDS at the end).
@@ -59,6 +57,7 @@ struct Index {
     std::vector<uint32_t> key_chunk_off;  // V + 1
     std::vector<int64_t> key_post_off;    // V + 1
     std::vector<float> key_maxw;          // V, max |w| of each list
+    std::vector<int8_t> key_wshift;       // V, Sw_k: weights of key k enter sums as round(w * 2^Sw_k)
     ebr_index_info stats{};
     int device = 0;
 };

@@ -18,12 +18,14 @@ struct DecodeArgs {
     const float* weights;
     const uint32_t* uk_chunk_begin;   // per distinct key: its first chunk in the index
     const uint32_t* uk_chunk_prefix;  // n_ukeys + 1 prefix sums of chunk counts
+    const int32_t* uk_wshift;         // per distinct key: Sw_k, weights become round(w * 2^Sw_k)
     int32_t n_ukeys;
     uint32_t total_chunks;
     uint32_t* tile_cnt;               // count pass
     const uint32_t* tile_off;         // place pass
     uint32_t* tile_fill;              // place pass
-    uint32_t* bucket;                 // place pass: pairs (slot << 5 | ad & 31, weight bits)
+    const uint32_t* users_off;        // non-null: entries carry their key's users range
+    uint32_t* bucket;                 // place pass: pairs (users range or slot | ad & 31, w_fix)
 };
 
 struct ScoreArgs {
@@ -32,11 +34,11 @@ struct ScoreArgs {
     const float* user;                // B x D
     int32_t n_queries;
     int32_t n_qgroups;
+    int32_t packed;                   // bucket entries carry users ranges (one query group)
     const uint32_t* tile_off;         // n_tiles + 1
     const uint32_t* bucket;           // pairs
     const uint32_t* users_off;        // n_ukeys * n_qgroups + 1
-    const uint32_t* users;            // pairs (query within group, multiplier bits)
-    const double* qscale;             // 2^S per query
+    const uint32_t* users;            // pairs (query within group, m_fix)
     const double* qinv;               // 2^-S per query
     int32_t n_work;                   // tiles to visit
     const uint32_t* tile_list;        // null: tile = work index
@@ -86,6 +88,8 @@ int launch_decode(const DecodeArgs& a, int place, void* stream);
 int launch_decode_key(const ChunkHdr* chunks, const uint32_t* words, const float* weights,
                       uint32_t chunk0, uint32_t n_chunks, uint32_t* ids, float* w, void* stream);
 bool score_dim_supported(int dim);
+// Queries per query group of the scoring kernel for this embedding width.
+int score_group_queries(int dim);
 int launch_score(const ScoreArgs& a, int dim, int mode, int ctas, void* stream);
 int launch_select(const SelectArgs& a, int n_queries, void* stream);
 int launch_finalize(const FinalArgs& a, int n_queries, void* stream);
