@@ -72,7 +72,9 @@ typedef struct ebr_index ebr_index; /* opaque; immutable after build */
  *  post_w       FP32 cross weights per posting, or NULL for unit weights
  *               (the paper's binary L).
  *  dtypes       bitmask of (1u << ebr_dtype) scan copies to build; FP32 is
- *               always built (it is also the exact rescore source).
+ *               always built (it is also the exact rescore source). BF16 is
+ *               round-to-nearest-even; FP8 is OCP e4m3fn with one FP32 scale per
+ *               ad (max |e| / 448), round-to-nearest-even, saturating.
  * EBR_EINVAL: unsorted or duplicate postings, ids >= N, non-finite embeddings
  * or weights, d not a supported multiple of 16, totals out of range.
  */
@@ -93,6 +95,8 @@ typedef struct {
     uint64_t arena_bytes;
     uint64_t bytes_emb_f32, bytes_emb_bf16, bytes_emb_fp8;
     uint64_t bytes_chunk_headers, bytes_packed_ids, bytes_weights;
+    double max_err_bf16;     /* max over ads of ||e_a - bf16(e_a)||_2 (0 if not built) */
+    double max_err_fp8;      /* max over ads of ||e_a - scale_a * fp8(e_a / scale_a)||_2 */
     double bits_per_id;      /* packed delta bits + header bits, per posting */
     double bytes_per_posting;/* whole posting store (headers + ids + weights) */
     double encode_ms;        /* host encode time of the last build */
@@ -136,8 +140,15 @@ void ebr_free_index(ebr_index* index);
  *  feat_mult     host FP32 multiplier per feature (the paper's w_hat), or NULL
  *                for 1.0.
  *  k             host, per-query K, 0 <= K_q <= min(N, 8192).
- *  scan_dtype    EBR_F32 (this build); others return EBR_EUNSUPPORTED.
- *  rescore_factor  reserved for the reduced-precision scans; ignored for F32.
+ *  scan_dtype    EBR_F32: exact FP32 scan. EBR_BF16 / EBR_FP8E4M3: the scan streams that
+ *                copy of the embeddings (EBR_EUNSUPPORTED if the index has none), keeps
+ *                the rescore_factor * K_q best approximate candidates, rescores them
+ *                exactly in FP32 and returns the top K_q; a per-query recall certificate
+ *                (the K-th exact score exceeds every outsider's best possible exact score)
+ *                is checked on the GPU, and a query that fails it is rerun with the FP32
+ *                scan, so results always equal the FP32 path's up to tolerance ties.
+ *  rescore_factor  candidates per result for reduced-precision scans (<= 0: 4);
+ *                rescore_factor * K_q <= 8192. Ignored for F32.
  * Results of query q occupy positions [sum_{p<q} K_p, sum_{p<=q} K_p).
  */
 typedef struct {
@@ -186,11 +197,15 @@ ebr_status ebr_score_dense(const ebr_index* index, const ebr_batch* batch, void*
  *  score_ms     the fused scoring kernel over the whole inventory (all rounds)
  *  finalize_ms  candidate sort and output (all rounds)
  *  host_ms      host validation and planning
+ *  score_first_ms  the fused scoring kernel of the first round alone
+ *  rescore_ms   exact FP32 rescore of the candidates (reduced-precision scans)
  *  rounds       scoring rounds (1 unless a threshold had to be revised)
+ *  uncertified  queries of a reduced-precision scan whose recall certificate failed and
+ *               that were therefore rerun with the FP32 scan
  */
 typedef struct {
-    double decode_ms, sample_ms, score_ms, finalize_ms, host_ms;
-    int32_t rounds;
+    double decode_ms, sample_ms, score_ms, finalize_ms, host_ms, score_first_ms, rescore_ms;
+    int32_t rounds, uncertified;
 } ebr_timings;
 
 ebr_status ebr_set_timing(int enable);
@@ -209,6 +224,17 @@ ebr_status ebr_codec_size(const uint32_t* ids, int64_t n, size_t* bytes);
 ebr_status ebr_codec_encode(const uint32_t* ids, int64_t n, void* out, size_t cap,
                             size_t* used);
 ebr_status ebr_codec_decode(const void* in, size_t bytes, int64_t n, uint32_t* ids);
+
+/* ------------------------------------------------------------------------ quantisers */
+
+/*
+ * Host reference of the index's reduced-precision encodings, for tests. BF16: round to
+ * nearest even. FP8: OCP e4m3fn of in[i] / scale, round to nearest even, saturating at
+ * +-448; ebr_dequantize_fp8 decodes codes to FP32 (without the scale).
+ */
+ebr_status ebr_quantize_bf16(const float* in, int64_t n, uint16_t* out);
+ebr_status ebr_quantize_fp8(const float* in, int64_t n, float scale, uint8_t* out);
+ebr_status ebr_dequantize_fp8(const uint8_t* in, int64_t n, float* out);
 
 /* Thread-local text of the last error (never NULL). */
 const char* ebr_last_error(void);

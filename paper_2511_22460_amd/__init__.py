@@ -27,7 +27,8 @@ _STATUS = {0: "EBR_OK", -1: "EBR_EINVAL", -2: "EBR_ENOMEM", -3: "EBR_EDEVICE", -
 EXPORTS = ("ebr_index_size", "ebr_build_index", "ebr_index_stats", "ebr_decode_key",
            "ebr_free_index", "ebr_workspace_size", "ebr_score_topk", "ebr_score_dense",
            "ebr_codec_size", "ebr_codec_encode", "ebr_codec_decode", "ebr_last_error",
-           "ebr_version", "ebr_set_timing", "ebr_get_timings")
+           "ebr_version", "ebr_set_timing", "ebr_get_timings", "ebr_quantize_bf16",
+           "ebr_quantize_fp8", "ebr_dequantize_fp8")
 
 
 class EbrError(RuntimeError):
@@ -50,7 +51,8 @@ class IndexInfo(ctypes.Structure):
                 ("arena_bytes", ctypes.c_uint64), ("bytes_emb_f32", ctypes.c_uint64),
                 ("bytes_emb_bf16", ctypes.c_uint64), ("bytes_emb_fp8", ctypes.c_uint64),
                 ("bytes_chunk_headers", ctypes.c_uint64), ("bytes_packed_ids", ctypes.c_uint64),
-                ("bytes_weights", ctypes.c_uint64), ("bits_per_id", ctypes.c_double),
+                ("bytes_weights", ctypes.c_uint64), ("max_err_bf16", ctypes.c_double),
+                ("max_err_fp8", ctypes.c_double), ("bits_per_id", ctypes.c_double),
                 ("bytes_per_posting", ctypes.c_double), ("encode_ms", ctypes.c_double),
                 ("upload_ms", ctypes.c_double)]
 
@@ -61,7 +63,9 @@ class IndexInfo(ctypes.Structure):
 class Timings(ctypes.Structure):
     _fields_ = [("decode_ms", ctypes.c_double), ("sample_ms", ctypes.c_double),
                 ("score_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double),
-                ("host_ms", ctypes.c_double), ("rounds", ctypes.c_int32)]
+                ("host_ms", ctypes.c_double), ("score_first_ms", ctypes.c_double),
+                ("rescore_ms", ctypes.c_double), ("rounds", ctypes.c_int32),
+                ("uncertified", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -117,6 +121,9 @@ def load():
         "ebr_last_error": ([], ctypes.c_char_p),
         "ebr_version": ([], ctypes.c_char_p),
         "ebr_set_timing": ([ctypes.c_int], st),
+        "ebr_quantize_bf16": ([P, i64, P], st),
+        "ebr_quantize_fp8": ([P, i64, ctypes.c_float, P], st),
+        "ebr_dequantize_fp8": ([P, i64, P], st),
         "ebr_get_timings": ([P], st),
     }
     for name, (args, res) in sig.items():
@@ -148,6 +155,29 @@ def _stream(stream=None) -> int:
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return s.cuda_stream
+
+
+# ------------------------------------------------------------------------------ quantisers (host)
+
+def quantize_bf16(x) -> np.ndarray:
+    x = _np(x, np.float32)
+    out = np.empty(max(1, len(x)), dtype=np.uint16)
+    _check(load().ebr_quantize_bf16(_ptr(x), len(x), out.ctypes.data), "ebr_quantize_bf16")
+    return out[:len(x)]
+
+
+def quantize_fp8(x, scale: float = 1.0) -> np.ndarray:
+    x = _np(x, np.float32)
+    out = np.empty(max(1, len(x)), dtype=np.uint8)
+    _check(load().ebr_quantize_fp8(_ptr(x), len(x), float(scale), out.ctypes.data), "ebr_quantize_fp8")
+    return out[:len(x)]
+
+
+def dequantize_fp8(codes) -> np.ndarray:
+    c = _np(codes, np.uint8)
+    out = np.empty(max(1, len(c)), dtype=np.float32)
+    _check(load().ebr_dequantize_fp8(_ptr(c), len(c), out.ctypes.data), "ebr_dequantize_fp8")
+    return out[:len(c)]
 
 
 # ------------------------------------------------------------------------------ codec (host)
@@ -309,15 +339,16 @@ class Index:
                "ebr_score_topk")
         return ids[:total], scores[:total], offs
 
-    def score_dense(self, user_emb, feat_offsets, feat_keys, feat_mult=None, stream=None):
-        """Full FP32 deep and wide terms [B, N] as the top-K path computes them."""
+    def score_dense(self, user_emb, feat_offsets, feat_keys, feat_mult=None, scan_dtype: int = F32,
+                    stream=None):
+        """Full deep and wide terms [B, N] (FP32 values) as the scan of that dtype computes them."""
         import torch
-        b, keep = self._batch(user_emb, feat_offsets, feat_keys, feat_mult, None, F32, 0)
+        b, keep = self._batch(user_emb, feat_offsets, feat_keys, feat_mult, None, scan_dtype, 0)
         n = ctypes.c_size_t()
         # the dense hook needs no selection buffers; size it through the top-K query with K = 0
         kz = np.zeros(max(1, b.n_queries), np.int32)
         b2 = Batch(b.n_queries, b.user_emb, b.feat_offsets, b.feat_keys, b.feat_mult,
-                   kz.ctypes.data, F32, 0)
+                   kz.ctypes.data, scan_dtype, 0)
         _check(load().ebr_workspace_size(self._h, ctypes.byref(b2), ctypes.byref(n)),
                "ebr_workspace_size")
         ws = self.workspace(n.value)

@@ -121,7 +121,7 @@ static ebr_status validate_desc(const ebr_build_desc* d) {
     if (!d->ad_emb) { set_error("ad_emb is NULL"); return EBR_EINVAL; }
     if (d->n_keys < 0) { set_error("n_keys < 0"); return EBR_EINVAL; }
     if (d->n_keys > 0 && !d->key_offsets) { set_error("key_offsets is NULL"); return EBR_EINVAL; }
-    if (d->dtypes & ~1u) { set_error("only the FP32 scan copy is implemented (dtypes=%u)", d->dtypes); return EBR_EUNSUPPORTED; }
+    if (d->dtypes & ~7u) { set_error("unknown dtype bits in %u", d->dtypes); return EBR_EINVAL; }
     const int64_t V = d->n_keys;
     if (V > 0) {
         if (d->key_offsets[0] != 0) { set_error("key_offsets[0] != 0"); return EBR_EINVAL; }
@@ -191,6 +191,16 @@ static ebr_status measure(const ebr_build_desc* d, Measured* m) {
     p.bytes_weights = std::max<size_t>(4, (size_t)n_post * 4);
     size_t off = 0;
     p.off_emb_f32 = off; off = align256(off + p.bytes_emb_f32);
+    if (d->dtypes & (1u << EBR_BF16)) {
+        p.bytes_emb_bf16 = (size_t)n_blk * kTileAds * d->dim * 2;
+        p.off_emb_bf16 = off; off = align256(off + p.bytes_emb_bf16);
+    }
+    if (d->dtypes & (1u << EBR_FP8E4M3)) {
+        p.bytes_emb_fp8 = (size_t)n_blk * kTileAds * d->dim;
+        p.off_emb_fp8 = off; off = align256(off + p.bytes_emb_fp8);
+        p.bytes_fp8_scale = (size_t)n_blk * kTileAds * 4;
+        p.off_fp8_scale = off; off = align256(off + p.bytes_fp8_scale);
+    }
     p.off_chunks = off; off = align256(off + p.bytes_chunks);
     p.off_words = off; off = align256(off + p.bytes_words);
     p.off_weights = off; off = align256(off + p.bytes_weights);
@@ -299,6 +309,69 @@ ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t a
         swizzle_f32(desc->ad_emb, desc->n_ads, desc->dim, emb.data());
         std::vector<float> ones;
         if (!desc->post_w) ones.assign((size_t)std::max<int64_t>(1, n_post), 1.0f);
+        // reduced-precision copies and their error summaries
+        const bool want_bf16 = desc->dtypes & (1u << EBR_BF16);
+        const bool want_fp8 = desc->dtypes & (1u << EBR_FP8E4M3);
+        std::vector<uint16_t> ebf((size_t)(want_bf16 ? p.bytes_emb_bf16 / 2 : 0), 0);
+        std::vector<uint8_t> ef8((size_t)(want_fp8 ? p.bytes_emb_fp8 : 0), 0);
+        std::vector<float> escale((size_t)(want_fp8 ? p.bytes_fp8_scale / 4 : 0), 1.0f);
+        double q_err2[2] = {0, 0}, q_norm2[2] = {0, 0}, e_norm2 = 0;
+        {
+            const int d = desc->dim;
+            const int nt = host_threads();
+            std::vector<double> t_err[2], t_norm[2], t_e(nt, 0.0);
+            for (int c = 0; c < 2; ++c) { t_err[c].assign(nt, 0.0); t_norm[c].assign(nt, 0.0); }
+            std::vector<std::thread> th;
+            const int64_t per = (desc->n_ads + nt - 1) / nt;
+            for (int t = 0; t < nt; ++t) {
+                th.emplace_back([&, t]() {
+                    const int64_t b = t * per, e = std::min<int64_t>(desc->n_ads, b + per);
+                    for (int64_t a = b; a < e; ++a) {
+                        const float* row = desc->ad_emb + a * d;
+                        double n2 = 0.0, mx = 0.0;
+                        for (int k = 0; k < d; ++k) {
+                            n2 += (double)row[k] * row[k];
+                            mx = std::max(mx, std::fabs((double)row[k]));
+                        }
+                        t_e[t] = std::max(t_e[t], std::sqrt(n2));
+                        if (want_bf16) {
+                            double er = 0.0, nr = 0.0;
+                            for (int k = 0; k < d; ++k) {
+                                const uint16_t h = bf16_rne(row[k]);
+                                ebf[mfma16_index(a, k, d)] = h;
+                                const double q = bf16_to_f32(h);
+                                er += (q - row[k]) * (q - row[k]);
+                                nr += q * q;
+                            }
+                            t_err[0][t] = std::max(t_err[0][t], std::sqrt(er));
+                            t_norm[0][t] = std::max(t_norm[0][t], std::sqrt(nr));
+                        }
+                        if (want_fp8) {
+                            const float sc = mx > 0.0 ? (float)(mx / 448.0) : 1.0f;
+                            escale[a] = sc;
+                            double er = 0.0, nr = 0.0;
+                            for (int k = 0; k < d; ++k) {
+                                const uint8_t c8 = fp8_e4m3_rne(row[k] / sc);
+                                ef8[mfma16_index(a, k, d)] = c8;
+                                const double q = (double)sc * fp8_e4m3_to_f32(c8);
+                                er += (q - row[k]) * (q - row[k]);
+                                nr += q * q;
+                            }
+                            t_err[1][t] = std::max(t_err[1][t], std::sqrt(er));
+                            t_norm[1][t] = std::max(t_norm[1][t], std::sqrt(nr));
+                        }
+                    }
+                });
+            }
+            for (auto& x : th) x.join();
+            for (int t = 0; t < nt; ++t) {
+                e_norm2 = std::max(e_norm2, t_e[t]);
+                for (int c = 0; c < 2; ++c) {
+                    q_err2[c] = std::max(q_err2[c], t_err[c][t]);
+                    q_norm2[c] = std::max(q_norm2[c], t_norm[c][t]);
+                }
+            }
+        }
         const double enc_ms = ms_since(t0);
 
         // upload
@@ -306,6 +379,12 @@ ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t a
         hipStream_t stream = (hipStream_t)hip_stream;
         char* base = (char*)dev_arena;
         HIP_TRY(hipMemcpyAsync(base + p.off_emb_f32, emb.data(), p.bytes_emb_f32, hipMemcpyHostToDevice, stream));
+        if (want_bf16)
+            HIP_TRY(hipMemcpyAsync(base + p.off_emb_bf16, ebf.data(), p.bytes_emb_bf16, hipMemcpyHostToDevice, stream));
+        if (want_fp8) {
+            HIP_TRY(hipMemcpyAsync(base + p.off_emb_fp8, ef8.data(), p.bytes_emb_fp8, hipMemcpyHostToDevice, stream));
+            HIP_TRY(hipMemcpyAsync(base + p.off_fp8_scale, escale.data(), p.bytes_fp8_scale, hipMemcpyHostToDevice, stream));
+        }
         if (p.n_chunks > 0)
             HIP_TRY(hipMemcpyAsync(base + p.off_chunks, hdr.data(), (size_t)p.n_chunks * 16, hipMemcpyHostToDevice, stream));
         HIP_TRY(hipMemcpyAsync(base + p.off_words, words.data(), p.bytes_words, hipMemcpyHostToDevice, stream));
@@ -322,8 +401,15 @@ ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t a
         ix->n_chunks = p.n_chunks;
         ix->dim = desc->dim;
         ix->n_tiles = (desc->n_ads + kTileAds - 1) / kTileAds;
-        ix->dtypes = 1u;
+        ix->dtypes = 1u | desc->dtypes;
         ix->emb_f32 = base + p.off_emb_f32;
+        if (want_bf16) ix->emb_bf16 = base + p.off_emb_bf16;
+        if (want_fp8) {
+            ix->emb_fp8 = base + p.off_emb_fp8;
+            ix->fp8_scale = (const float*)(base + p.off_fp8_scale);
+        }
+        for (int c = 0; c < 2; ++c) { ix->q_err2[c] = q_err2[c]; ix->q_norm2[c] = q_norm2[c]; }
+        ix->e_norm2 = e_norm2;
         ix->chunks = (const ChunkHdr*)(base + p.off_chunks);
         ix->words = (const uint32_t*)(base + p.off_words);
         ix->weights = (const float*)(base + p.off_weights);
@@ -352,6 +438,10 @@ ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t a
         s.tile_ads = kTileAds;
         s.arena_bytes = p.total;
         s.bytes_emb_f32 = p.bytes_emb_f32;
+        s.bytes_emb_bf16 = p.bytes_emb_bf16;
+        s.bytes_emb_fp8 = p.bytes_emb_fp8 + p.bytes_fp8_scale;
+        s.max_err_bf16 = q_err2[0];
+        s.max_err_fp8 = q_err2[1];
         s.bytes_chunk_headers = (uint64_t)p.n_chunks * 16;
         s.bytes_packed_ids = (uint64_t)p.n_words * 4;
         s.bytes_weights = (uint64_t)n_post * 4;
@@ -398,7 +488,12 @@ ebr_status ebr_decode_key(const ebr_index* index, int64_t key, uint32_t* ids, fl
 namespace ebr {
 
 struct Plan {
+    int dtype = 0;        // scan copy: 0 FP32, 1 BF16, 2 FP8
+    int factor = 1;       // approximate scans: candidates rescored per result
     int B = 0, gq = 256, n_qg = 0, nu = 0;
+    std::vector<int32_t> kcnt;  // per query: K (FP32 scan) or K' = min(N, factor K)
+    int kcmax = 0;
+    std::vector<double> aq;     // per query: sum_j |m_j| max|W[k_j,:]|
     bool packed = false;  // bucket entries carry users ranges: one query group, < 2^19 features
     int64_t nnz = 0;
     int kmax = 0;
@@ -414,9 +509,13 @@ struct Plan {
     int64_t n_tiles = 0;
     // workspace layout
     size_t off_plan = 0, plan_bytes = 0;
+    size_t o_kc = 0, off_cwide = 0, off_rid = 0, off_rwide = 0, off_rst = 0, off_eps = 0,
+           off_unc = 0, off_fb_users = 0, off_fb_ids = 0, off_fb_scores = 0, fb_limit = 0;
     size_t o_ukb = 0, o_ukp = 0, o_ukw = 0, o_uoff = 0, o_users = 0, o_qi = 0, o_kq = 0, o_jq = 0,
            o_oo = 0, o_st = 0;
-    size_t off_tcnt = 0, off_toff = 0, off_tfill = 0, off_stmp = 0, off_bucket = 0, off_skeys = 0,
+    int64_t n_super = 0;
+    size_t off_stcnt = 0, off_stoff = 0, off_stfill = 0, off_stage = 0;
+    size_t off_toff = 0, off_stmp = 0, off_bucket = 0, off_skeys = 0,
            off_thr = 0, off_status = 0, off_active = 0, off_ccnt = 0, off_unres = 0, off_cand = 0;
     size_t total = 0;
 };
@@ -425,7 +524,17 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     if (!bt) { set_error("batch is NULL"); return EBR_EINVAL; }
     const int B = bt->n_queries;
     if (B < 0) { set_error("n_queries < 0"); return EBR_EINVAL; }
-    if (bt->scan_dtype != EBR_F32) { set_error("scan dtype %d not implemented", (int)bt->scan_dtype); return EBR_EUNSUPPORTED; }
+    if (bt->scan_dtype != EBR_F32 && bt->scan_dtype != EBR_BF16 && bt->scan_dtype != EBR_FP8E4M3) {
+        set_error("unknown scan dtype %d", (int)bt->scan_dtype);
+        return EBR_EINVAL;
+    }
+    P->dtype = (int)bt->scan_dtype;
+    if ((P->dtype == EBR_BF16 && !ix.emb_bf16) || (P->dtype == EBR_FP8E4M3 && !ix.emb_fp8)) {
+        set_error("the index holds no %s copy (build it with that dtype bit)",
+                  P->dtype == EBR_BF16 ? "BF16" : "FP8");
+        return EBR_EUNSUPPORTED;
+    }
+    P->factor = P->dtype == EBR_F32 ? 1 : (bt->rescore_factor > 0 ? bt->rescore_factor : 4);
     P->B = B;
     P->gq = score_group_queries(ix.dim);
     P->n_qg = (B + P->gq - 1) / P->gq;
@@ -461,12 +570,20 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
             P->kmax = std::max(P->kmax, bt->k[q]);
         }
     }
+    P->kcnt.assign(B, 0);
+    P->kcmax = 0;
+    for (int q = 0; q < B; ++q) {
+        const int64_t kc = P->kq[q] == 0 ? 0 : std::min<int64_t>(ix.n_ads, (int64_t)P->factor * P->kq[q]);
+        if (kc > kMaxK) { set_error("query %d: rescore_factor x K = %lld exceeds %d", q, (long long)kc, kMaxK); return EBR_EINVAL; }
+        P->kcnt[q] = (int32_t)kc;
+        P->kcmax = std::max(P->kcmax, (int)kc);
+    }
     // distinct keys of the batch
     std::vector<int32_t> uk(bt->feat_keys, bt->feat_keys + nnz);
     std::sort(uk.begin(), uk.end());
     uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
     const int nu = (int)uk.size();
-    if (nu >= (1 << (32 - kTileShift))) { set_error("too many distinct keys in one batch"); return EBR_EINVAL; }
+    if (nu >= (1 << (32 - kSuperShift))) { set_error("too many distinct keys in one batch"); return EBR_EINVAL; }
     P->nu = nu;
     P->packed = P->n_qg == 1 && nnz < (1LL << 19);
     P->uk_chunk_begin.resize(nu);
@@ -498,12 +615,14 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     // per-query fixed-point scale of the cross term: sum_j |m_j| max|W[k_j,:]| * 2^S < 2^60
     std::vector<int> Sq(B, 0);
     P->qinv.assign(B, 1.0);
+    P->aq.assign(B, 0.0);
     for (int q = 0; q < B; ++q) {
         double A = 0.0;
         for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
             const double m = bt->feat_mult ? (double)bt->feat_mult[j] : 1.0;
             A += std::fabs(m) * (double)ix.key_maxw[bt->feat_keys[j]];
         }
+        P->aq[q] = A;
         int S = 0;
         if (A > 0.0 && std::isfinite(A)) {
             int e;
@@ -547,7 +666,7 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     P->sample_tiles.clear();
     if (topk && P->kmax > 0) {
         const int64_t nt = ix.n_tiles;
-        int64_t ns = std::max<int64_t>((nt + 63) / 64, (16LL * P->kmax + kTileAds - 1) / kTileAds);
+        int64_t ns = std::max<int64_t>((nt + 63) / 64, (16LL * P->kcmax + kTileAds - 1) / kTileAds);
         ns = std::min(ns, nt);
         P->sample_tiles.resize(ns);
         int64_t valid = 0;
@@ -559,7 +678,7 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         P->n_sample_valid = valid;
         const double f = (double)valid / (double)ix.n_ads;
         for (int q = 0; q < B; ++q) {
-            const int K = P->kq[q];
+            const int K = P->kcnt[q];
             if (K == 0) continue;
             if (ns == nt) { P->jq[q] = K; continue; }
             const double x = K * f;
@@ -579,13 +698,17 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     P->o_qi = put(8 * (size_t)B);
     P->o_kq = put(4 * (size_t)B);
     P->o_jq = put(4 * (size_t)B);
+    P->o_kc = put(4 * (size_t)B);
     P->o_oo = put(8 * (size_t)(B + 1));
     P->o_st = put(4 * P->sample_tiles.size());
     P->plan_bytes = off - P->off_plan;
-    P->off_tcnt = put(4 * (size_t)(ix.n_tiles + 1));
+    P->n_super = (ix.n_ads + kSuperAds - 1) / kSuperAds;
+    P->off_stcnt = put(4 * (size_t)(P->n_super + 1));
+    P->off_stoff = put(4 * (size_t)(P->n_super + 1));
+    P->off_stfill = put(4 * (size_t)(P->n_super + 1));
+    P->off_stmp = put(4 * (size_t)scan_tmp_words(P->n_super + 1));
+    P->off_stage = put(8 * (size_t)P->bucket_n);
     P->off_toff = put(4 * (size_t)(ix.n_tiles + 1));
-    P->off_tfill = put(4 * (size_t)(ix.n_tiles + 1));
-    P->off_stmp = put(4 * (size_t)scan_tmp_words(ix.n_tiles + 1));
     P->off_bucket = put(8 * (size_t)P->bucket_n);
     if (topk) {
         P->off_skeys = put(4 * (size_t)B * P->sample_tiles.size() * kTileAds);
@@ -595,6 +718,19 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         P->off_ccnt = put(4 * (size_t)B);
         P->off_unres = put(16);
         P->off_cand = put(8 * (size_t)B * kCandCap);
+        if (P->dtype != EBR_F32) {
+            // everything below the fallback region is enough for an FP32 run of any subset
+            P->fb_limit = off;
+            P->off_cwide = put(4 * (size_t)B * kCandCap);
+            P->off_rid = put(4 * (size_t)B * std::max(1, P->kcmax));
+            P->off_rwide = put(4 * (size_t)B * std::max(1, P->kcmax));
+            P->off_rst = put(4 * (size_t)B);
+            P->off_eps = put(4 * (size_t)B);
+            P->off_unc = put(16);
+            P->off_fb_users = put(4 * (size_t)B * ix.dim);
+            P->off_fb_ids = put(4 * (size_t)std::max<int64_t>(1, P->out_off.empty() ? 0 : P->out_off[B]));
+            P->off_fb_scores = put(4 * (size_t)std::max<int64_t>(1, P->out_off.empty() ? 0 : P->out_off[B]));
+        }
     }
     P->total = off;
     return EBR_OK;
@@ -611,6 +747,7 @@ static std::vector<char> pack_plan(const Plan& P) {
     cp(P.o_qi, P.qinv.data(), 8 * P.qinv.size());
     cp(P.o_kq, P.kq.data(), 4 * P.kq.size());
     cp(P.o_jq, P.jq.data(), 4 * P.jq.size());
+    cp(P.o_kc, P.kcnt.data(), 4 * P.kcnt.size());
     cp(P.o_oo, P.out_off.data(), 8 * P.out_off.size());
     cp(P.o_st, P.sample_tiles.data(), 4 * P.sample_tiles.size());
     return blob;
@@ -641,11 +778,11 @@ static ebr_status run_decode(const Index& ix, const Plan& P, char* ws, hipStream
                              std::vector<char>& blob) {
     blob = pack_plan(P);
     HIP_TRY(hipMemcpyAsync(ws + P.off_plan, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
-    uint32_t* tcnt = (uint32_t*)(ws + P.off_tcnt);
-    uint32_t* toff = (uint32_t*)(ws + P.off_toff);
-    uint32_t* tfill = (uint32_t*)(ws + P.off_tfill);
-    LAUNCH(launch_fill_u32(tcnt, 0u, ix.n_tiles + 1, st));
-    LAUNCH(launch_fill_u32(tfill, 0u, ix.n_tiles + 1, st));
+    uint32_t* stcnt = (uint32_t*)(ws + P.off_stcnt);
+    uint32_t* stoff = (uint32_t*)(ws + P.off_stoff);
+    uint32_t* stfill = (uint32_t*)(ws + P.off_stfill);
+    LAUNCH(launch_fill_u32(stcnt, 0u, P.n_super + 1, st));
+    LAUNCH(launch_fill_u32(stfill, 0u, P.n_super + 1, st));
     DecodeArgs d{};
     d.chunks = ix.chunks;
     d.words = ix.words;
@@ -655,21 +792,28 @@ static ebr_status run_decode(const Index& ix, const Plan& P, char* ws, hipStream
     d.uk_wshift = (const int32_t*)(ws + P.o_ukw);
     d.n_ukeys = P.nu;
     d.total_chunks = P.total_chunks;
-    d.tile_cnt = tcnt;
-    d.tile_off = toff;
-    d.tile_fill = tfill;
-    d.bucket = (uint32_t*)(ws + P.off_bucket);
+    d.n_tiles = ix.n_tiles;
+    d.n_super = P.n_super;
+    d.st_cnt = stcnt;
+    d.st_off = stoff;
+    d.st_fill = stfill;
+    d.stage = (uint32_t*)(ws + P.off_stage);
     // one query group: bucket entries carry their key's users range directly
     d.users_off = P.packed ? (const uint32_t*)(ws + P.o_uoff) : nullptr;
+    d.tile_off = (uint32_t*)(ws + P.off_toff);
+    d.bucket = (uint32_t*)(ws + P.off_bucket);
     LAUNCH(launch_decode(d, 0, st));
-    LAUNCH(launch_excl_scan_u32(tcnt, toff, ix.n_tiles, (uint32_t*)(ws + P.off_stmp), st));
+    LAUNCH(launch_excl_scan_u32(stcnt, stoff, P.n_super, (uint32_t*)(ws + P.off_stmp), st));
     LAUNCH(launch_decode(d, 1, st));
+    LAUNCH(launch_refine(d, st));
     return EBR_OK;
 }
 
 static ScoreArgs score_args(const Index& ix, const Plan& P, const ebr_batch* bt, char* ws) {
     ScoreArgs s{};
-    s.emb = ix.emb_f32;
+    s.dtype = P.dtype;
+    s.emb = P.dtype == EBR_BF16 ? ix.emb_bf16 : (P.dtype == EBR_FP8E4M3 ? ix.emb_fp8 : ix.emb_f32);
+    s.fp8_scale = ix.fp8_scale;
     s.n_ads = ix.n_ads;
     s.user = bt->user_emb;
     s.n_queries = P.B;
@@ -685,13 +829,261 @@ static ScoreArgs score_args(const Index& ix, const Plan& P, const ebr_batch* bt,
     return s;
 }
 
-static ebr_status check_users(const ebr_batch* bt, int B, int dim, hipStream_t st) {
+static ebr_status check_users(const ebr_batch* bt, int B, int dim, hipStream_t st,
+                              std::vector<float>* host = nullptr) {
     if (B == 0) return EBR_OK;
-    std::vector<float> u((size_t)B * dim);
+    std::vector<float> local;
+    std::vector<float>& u = host ? *host : local;
+    u.resize((size_t)B * dim);
     HIP_TRY(hipMemcpyAsync(u.data(), bt->user_emb, u.size() * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     for (size_t i = 0; i < u.size(); ++i)
         if (!std::isfinite(u[i])) { set_error("query %zu: non-finite user embedding", i / dim); return EBR_EINVAL; }
+    return EBR_OK;
+}
+
+// Bound on |approximate score - exact score| of any ad for a query with FP32 user row u
+// (see k_rescore): quantisation of u and of the ad rows, FP32 accumulation of both dot
+// products (d terms each), the FP8 scale product, and the two FP32 additions of the cross
+// term (|cross term| <= A_q).
+static float approx_eps(const Index& ix, int dtype, const float* u, double aq) {
+    const int d = ix.dim;
+    const int c = dtype == EBR_BF16 ? 0 : 1;
+    double nu = 0, nh = 0, du = 0;
+    for (int k = 0; k < d; ++k) {
+        const double x = u[k], h = bf16_to_f32(bf16_rne(u[k]));
+        nu += x * x;
+        nh += h * h;
+        du += (h - x) * (h - x);
+    }
+    nu = std::sqrt(nu);
+    nh = std::sqrt(nh);
+    du = std::sqrt(du);
+    const double gamma = d * std::ldexp(1.0, -24) * 1.01;
+    const double R = ix.q_err2[c], Eh = ix.q_norm2[c], E = ix.e_norm2;
+    double eps = du * Eh + nu * R + gamma * (nh * Eh + nu * E) + std::ldexp(1.0, -24) * nh * Eh +
+                 std::ldexp(1.0, -22) * (std::max(nu * E, nh * Eh) + aq);
+    eps = eps * 1.001 + 1e-30;
+    return std::nextafter((float)eps, INFINITY);
+}
+
+static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, size_t ws_bytes,
+                            uint32_t* out_ids, float* out_scores, hipStream_t s, ebr_timings* tm) {
+    const auto t_host = std::chrono::steady_clock::now();
+    Plan P;
+    ebr_status st = plan_batch(ix, batch, true, &P);
+    if (st) return st;
+    if (!ws || ws_bytes < P.total) { set_error("workspace too small: need %zu bytes, got %zu", P.total, ws_bytes); return EBR_ENOMEM; }
+    if ((uintptr_t)ws & 255) { set_error("workspace must be 256-byte aligned"); return EBR_EINVAL; }
+    const int64_t n_out = P.out_off[P.B];
+    if (n_out > 0 && (!out_ids || !out_scores)) { set_error("NULL output"); return EBR_EINVAL; }
+    if (P.B == 0 || P.kmax == 0) return EBR_OK;
+    std::vector<float> uhost;
+    st = check_users(batch, P.B, ix.dim, s, &uhost);
+    if (st) return st;
+    const bool approx = P.dtype != EBR_F32;
+    std::vector<float> eps;
+    if (approx) {
+        eps.resize(P.B);
+        for (int q = 0; q < P.B; ++q) eps[q] = approx_eps(ix, P.dtype, &uhost[(size_t)q * ix.dim], P.aq[q]);
+    }
+    const double host_ms = ms_since(t_host);
+    PhaseClock clk(s);
+    const int e_dec0 = clk.mark();
+    std::vector<char> blob;
+    st = run_decode(ix, P, ws, s, blob);
+    if (st) return st;
+    const int e_dec1 = clk.mark();
+
+    const int B = P.B;
+    uint32_t* thr = (uint32_t*)(ws + P.off_thr);
+    int32_t* status = (int32_t*)(ws + P.off_status);
+    uint32_t* active = (uint32_t*)(ws + P.off_active);
+    uint32_t* ccnt = (uint32_t*)(ws + P.off_ccnt);
+    uint32_t* unres = (uint32_t*)(ws + P.off_unres);
+    unsigned long long* cand = (unsigned long long*)(ws + P.off_cand);
+    const int64_t ns = (int64_t)P.sample_tiles.size();
+
+    // sample pass and per-query threshold (for K' candidates on approximate scans)
+    ScoreArgs sa = score_args(ix, P, batch, ws);
+    sa.n_work = (int32_t)ns;
+    sa.tile_list = (const uint32_t*)(ws + P.o_st);
+    sa.sample_keys = (uint32_t*)(ws + P.off_skeys);
+    sa.sample_ld = ns * kTileAds;
+    LAUNCH(launch_score(sa, ix.dim, 1, score_ctas(), s));
+    SelectArgs se{};
+    se.keys = sa.sample_keys;
+    se.ld = sa.sample_ld;
+    se.n_cols = sa.sample_ld;
+    se.jq = (const int32_t*)(ws + P.o_jq);
+    se.kq = (const int32_t*)(ws + P.o_kq);
+    se.status = status;
+    se.only_status = -1;
+    se.thresh = thr;
+    LAUNCH(launch_select(se, B, s));
+    const int e_smp1 = clk.mark();
+
+    // per-query state: active iff K > 0
+    std::vector<uint32_t> act(B);
+    std::vector<int32_t> stat(B);
+    for (int q = 0; q < B; ++q) {
+        act[q] = P.kq[q] > 0 ? 1u : 0u;
+        stat[q] = P.kq[q] > 0 ? kStatusPending : kStatusDone;
+    }
+    HIP_TRY(hipMemcpyAsync(active, act.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(status, stat.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
+    if (approx) HIP_TRY(hipMemcpyAsync(ws + P.off_eps, eps.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
+
+    ScoreArgs ca = score_args(ix, P, batch, ws);
+    ca.thresh = thr;
+    ca.active = active;
+    ca.cand = cand;
+    ca.cand_wide = approx ? (float*)(ws + P.off_cwide) : nullptr;
+    ca.cand_cnt = ccnt;
+    ca.cap = kCandCap;
+    FinalArgs fa{};
+    fa.active = active;
+    fa.kq = (const int32_t*)(ws + P.o_kq);
+    fa.kcnt = (const int32_t*)(ws + P.o_kc);
+    fa.cand_cnt = ccnt;
+    fa.cap = kCandCap;
+    fa.cand = cand;
+    fa.cand_wide = ca.cand_wide;
+    fa.status = status;
+    fa.thresh = thr;
+    fa.unresolved = unres;
+    fa.prep = approx ? 1 : 0;
+    fa.out_off = (const int64_t*)(ws + P.o_oo);
+    fa.out_ids = out_ids;
+    fa.out_scores = out_scores;
+    if (approx) {
+        fa.r_id = (uint32_t*)(ws + P.off_rid);
+        fa.r_wide = (float*)(ws + P.off_rwide);
+        fa.r_stilde = (float*)(ws + P.off_rst);
+        fa.r_ld = std::max(1, P.kcmax);
+    }
+
+    // queries short of K' candidates fall back to the sample's K'-th key, which at least K'
+    // sample ads reach (or to no threshold when the sample holds fewer than K' ads)
+    std::vector<int32_t> jk(B);
+    for (int q = 0; q < B; ++q)
+        jk[q] = P.kcnt[q] <= P.n_sample_valid ? P.kcnt[q] : (int32_t)(P.n_sample_valid + 1);
+    // a query still short after that takes no threshold at all (every ad is a candidate;
+    // the overflow rule then narrows it)
+    std::vector<int32_t> jall(B, (int32_t)(P.n_sample_valid + 1));
+    std::vector<std::array<int, 3>> round_marks;
+    for (int round = 0;; ++round) {
+        if (round > 0) {
+            HIP_TRY(hipMemcpyAsync(ws + P.o_jq, (round == 1 ? jk : jall).data(), 4 * (size_t)B,
+                                   hipMemcpyHostToDevice, s));
+            se.only_status = kStatusNeedLower;
+            LAUNCH(launch_select(se, B, s));
+        }
+        LAUNCH(launch_fill_u32(ccnt, 0u, B, s));
+        LAUNCH(launch_fill_u32(unres, 0u, 1, s));
+        const int e0 = clk.mark();
+        LAUNCH(launch_score(ca, ix.dim, 0, score_ctas(), s));
+        const int e1 = clk.mark();
+        LAUNCH(launch_finalize(fa, B, s));
+        const int e2 = clk.mark();
+        uint32_t left = 0;
+        HIP_TRY(hipMemcpyAsync(&left, unres, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        round_marks.push_back({e0, e1, e2});
+        if (left == 0) break;
+        if (round >= 64) { set_error("top-K selection did not converge"); return EBR_EDEVICE; }
+    }
+
+    int e_rs0 = -1, e_rs1 = -1;
+    int n_unc = 0;
+    if (approx) {
+        // exact FP32 rescore of the K' candidates, top K, recall certificate
+        uint32_t* unc = (uint32_t*)(ws + P.off_unc);
+        LAUNCH(launch_fill_u32(unc, 0u, 1, s));
+        RescoreArgs ra{};
+        ra.emb = ix.emb_f32;
+        ra.user = batch->user_emb;
+        ra.n_ads = ix.n_ads;
+        ra.kq = fa.kq;
+        ra.kcnt = fa.kcnt;
+        ra.status = status;
+        ra.uncertified = unc;
+        ra.r_id = fa.r_id;
+        ra.r_wide = fa.r_wide;
+        ra.r_stilde = fa.r_stilde;
+        ra.eps = (const float*)(ws + P.off_eps);
+        ra.r_ld = fa.r_ld;
+        ra.out_off = fa.out_off;
+        ra.out_ids = out_ids;
+        ra.out_scores = out_scores;
+        e_rs0 = clk.mark();
+        LAUNCH(launch_rescore(ra, ix.dim, B, s));
+        e_rs1 = clk.mark();
+        uint32_t nunc = 0;
+        HIP_TRY(hipMemcpyAsync(&nunc, unc, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        n_unc = (int)nunc;
+    }
+    if (tm) {
+        tm->host_ms = host_ms;
+        tm->decode_ms = clk.ms(e_dec0, e_dec1);
+        tm->sample_ms = clk.ms(e_dec1, e_smp1);
+        for (const auto& r : round_marks) {
+            tm->score_ms += clk.ms(r[0], r[1]);
+            tm->finalize_ms += clk.ms(r[1], r[2]);
+        }
+        tm->score_first_ms = clk.ms(round_marks[0][0], round_marks[0][1]);
+        tm->rescore_ms = clk.ms(e_rs0, e_rs1);
+        tm->rounds = (int32_t)round_marks.size();
+        tm->uncertified = n_unc;
+    }
+    if (n_unc > 0) {
+        // queries whose certificate failed: exact FP32 scan of just those queries
+        std::vector<int32_t> sv(B);
+        HIP_TRY(hipMemcpyAsync(sv.data(), status, 4 * (size_t)B, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        std::vector<int> fq;
+        for (int q = 0; q < B; ++q)
+            if (sv[q] == kStatusUncertified) fq.push_back(q);
+        const int nb = (int)fq.size();
+        float* fu = (float*)(ws + P.off_fb_users);
+        uint32_t* fids = (uint32_t*)(ws + P.off_fb_ids);
+        float* fsc = (float*)(ws + P.off_fb_scores);
+        std::vector<int64_t> foff(nb + 1, 0);
+        std::vector<int32_t> fkeys, fk(nb);
+        std::vector<float> fmult;
+        for (int i = 0; i < nb; ++i) {
+            const int q = fq[i];
+            HIP_TRY(hipMemcpyAsync(fu + (size_t)i * ix.dim, batch->user_emb + (size_t)q * ix.dim,
+                                   4 * (size_t)ix.dim, hipMemcpyDeviceToDevice, s));
+            for (int64_t j = batch->feat_offsets[q]; j < batch->feat_offsets[q + 1]; ++j) {
+                fkeys.push_back(batch->feat_keys[j]);
+                if (batch->feat_mult) fmult.push_back(batch->feat_mult[j]);
+            }
+            foff[i + 1] = (int64_t)fkeys.size();
+            fk[i] = P.kq[q];
+        }
+        ebr_batch fb{};
+        fb.n_queries = nb;
+        fb.user_emb = fu;
+        fb.feat_offsets = foff.data();
+        fb.feat_keys = fkeys.data();
+        fb.feat_mult = batch->feat_mult ? fmult.data() : nullptr;
+        fb.k = fk.data();
+        fb.scan_dtype = EBR_F32;
+        fb.rescore_factor = 0;
+        st = topk_impl(ix, &fb, ws, P.fb_limit, fids, fsc, s, nullptr);
+        if (st) return st;
+        int64_t pos = 0;
+        for (int i = 0; i < nb; ++i) {
+            const int q = fq[i];
+            const size_t n = (size_t)P.kq[q];
+            HIP_TRY(hipMemcpyAsync(out_ids + P.out_off[q], fids + pos, 4 * n, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(out_scores + P.out_off[q], fsc + pos, 4 * n, hipMemcpyDeviceToDevice, s));
+            pos += (int64_t)n;
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     return EBR_OK;
 }
 
@@ -717,128 +1109,9 @@ ebr_status ebr_score_topk(const ebr_index* index, const ebr_batch* batch, void* 
                           size_t ws_bytes, uint32_t* out_ids, float* out_scores, void* hip_stream) {
     try {
         if (!index) { set_error("index is NULL"); return EBR_EINVAL; }
-        const auto t_host = std::chrono::steady_clock::now();
-        const Index& ix = *index;
-        Plan P;
-        ebr_status st = plan_batch(ix, batch, true, &P);
-        if (st) return st;
-        if (!ws_v || ws_bytes < P.total) { set_error("workspace too small: need %zu bytes, got %zu", P.total, ws_bytes); return EBR_ENOMEM; }
-        if ((uintptr_t)ws_v & 255) { set_error("workspace must be 256-byte aligned"); return EBR_EINVAL; }
-        const int64_t n_out = P.out_off[P.B];
-        if (n_out > 0 && (!out_ids || !out_scores)) { set_error("NULL output"); return EBR_EINVAL; }
         g_last_timings = ebr_timings{};
-        if (P.B == 0 || P.kmax == 0) return EBR_OK;
-        hipStream_t s = (hipStream_t)hip_stream;
-        st = check_users(batch, P.B, ix.dim, s);
-        if (st) return st;
-        const double host_ms = ms_since(t_host);
-        char* ws = (char*)ws_v;
-        PhaseClock clk(s);
-        const int e_dec0 = clk.mark();
-        std::vector<char> blob;
-        st = run_decode(ix, P, ws, s, blob);
-        if (st) return st;
-        const int e_dec1 = clk.mark();
-
-        const int B = P.B;
-        uint32_t* thr = (uint32_t*)(ws + P.off_thr);
-        int32_t* status = (int32_t*)(ws + P.off_status);
-        uint32_t* active = (uint32_t*)(ws + P.off_active);
-        uint32_t* ccnt = (uint32_t*)(ws + P.off_ccnt);
-        uint32_t* unres = (uint32_t*)(ws + P.off_unres);
-        unsigned long long* cand = (unsigned long long*)(ws + P.off_cand);
-        const int64_t ns = (int64_t)P.sample_tiles.size();
-
-        // sample pass and per-query threshold
-        ScoreArgs sa = score_args(ix, P, batch, ws);
-        sa.n_work = (int32_t)ns;
-        sa.tile_list = (const uint32_t*)(ws + P.o_st);
-        sa.sample_keys = (uint32_t*)(ws + P.off_skeys);
-        sa.sample_ld = ns * kTileAds;
-        LAUNCH(launch_score(sa, ix.dim, 1, score_ctas(), s));
-        SelectArgs se{};
-        se.keys = sa.sample_keys;
-        se.ld = sa.sample_ld;
-        se.n_cols = sa.sample_ld;
-        se.jq = (const int32_t*)(ws + P.o_jq);
-        se.kq = (const int32_t*)(ws + P.o_kq);
-        se.status = status;
-        se.only_status = -1;
-        se.thresh = thr;
-        LAUNCH(launch_select(se, B, s));
-        const int e_smp1 = clk.mark();
-
-        // per-query state: active iff K > 0
-        std::vector<uint32_t> act(B);
-        std::vector<int32_t> stat(B);
-        for (int q = 0; q < B; ++q) {
-            act[q] = P.kq[q] > 0 ? 1u : 0u;
-            stat[q] = P.kq[q] > 0 ? kStatusPending : kStatusDone;
-        }
-        HIP_TRY(hipMemcpyAsync(active, act.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(status, stat.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
-
-        ScoreArgs ca = score_args(ix, P, batch, ws);
-        ca.thresh = thr;
-        ca.active = active;
-        ca.cand = cand;
-        ca.cand_cnt = ccnt;
-        ca.cap = kCandCap;
-        FinalArgs fa{};
-        fa.active = active;
-        fa.kq = (const int32_t*)(ws + P.o_kq);
-        fa.cand_cnt = ccnt;
-        fa.cap = kCandCap;
-        fa.cand = cand;
-        fa.status = status;
-        fa.thresh = thr;
-        fa.unresolved = unres;
-        fa.out_off = (const int64_t*)(ws + P.o_oo);
-        fa.out_ids = out_ids;
-        fa.out_scores = out_scores;
-
-        // queries short of K candidates fall back to the sample's K-th key, which at least K
-        // sample ads reach (or to no threshold when the sample holds fewer than K ads)
-        std::vector<int32_t> jk(B);
-        for (int q = 0; q < B; ++q)
-            jk[q] = P.kq[q] <= P.n_sample_valid ? P.kq[q] : (int32_t)(P.n_sample_valid + 1);
-        // a query still short after that takes no threshold at all (every ad is a candidate;
-        // the overflow rule then narrows it)
-        std::vector<int32_t> jall(B, (int32_t)(P.n_sample_valid + 1));
-        std::vector<std::array<int, 3>> round_marks;
-        for (int round = 0;; ++round) {
-            if (round > 0) {
-                HIP_TRY(hipMemcpyAsync(ws + P.o_jq, (round == 1 ? jk : jall).data(), 4 * (size_t)B,
-                                       hipMemcpyHostToDevice, s));
-                se.only_status = kStatusNeedLower;
-                LAUNCH(launch_select(se, B, s));
-            }
-            LAUNCH(launch_fill_u32(ccnt, 0u, B, s));
-            LAUNCH(launch_fill_u32(unres, 0u, 1, s));
-            const int e0 = clk.mark();
-            LAUNCH(launch_score(ca, ix.dim, 0, score_ctas(), s));
-            const int e1 = clk.mark();
-            LAUNCH(launch_finalize(fa, B, s));
-            const int e2 = clk.mark();
-            uint32_t left = 0;
-            HIP_TRY(hipMemcpyAsync(&left, unres, 4, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            round_marks.push_back({e0, e1, e2});
-            if (left == 0) {
-                ebr_timings& t = g_last_timings;
-                t.host_ms = host_ms;
-                t.decode_ms = clk.ms(e_dec0, e_dec1);
-                t.sample_ms = clk.ms(e_dec1, e_smp1);
-                for (const auto& r : round_marks) {
-                    t.score_ms += clk.ms(r[0], r[1]);
-                    t.finalize_ms += clk.ms(r[1], r[2]);
-                }
-                t.rounds = round + 1;
-                break;
-            }
-            if (round >= 64) { set_error("top-K selection did not converge"); return EBR_EDEVICE; }
-        }
-        return EBR_OK;
+        return topk_impl(*index, batch, (char*)ws_v, ws_bytes, out_ids, out_scores,
+                         (hipStream_t)hip_stream, &g_last_timings);
     } catch (const std::bad_alloc&) {
         set_error("host out of memory");
         return EBR_ENOMEM;

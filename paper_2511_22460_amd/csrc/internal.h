@@ -16,6 +16,10 @@ namespace ebr {
 // unit of the tile-major posting buckets built per batch.
 constexpr int kTileAds = 32;
 constexpr int kTileShift = 5;
+// Ads per super-tile: the unit of the first bucketing pass of a batch's postings.
+constexpr int kSuperAds = 1024;
+constexpr int kSuperShift = 10;
+constexpr int kTilesPerSuper = kSuperAds / kTileAds;
 // Postings per compressed chunk: one per lane of a 64-wide wavefront.
 constexpr int kChunk = 64;
 // Candidate slots per query in the selection buffer (sorted in LDS at the end).
@@ -50,6 +54,12 @@ struct Index {
     uint32_t dtypes = 0;
     // device pointers into the caller's arena
     const void* emb_f32 = nullptr;   // swizzled, see kernels.hip
+    const void* emb_bf16 = nullptr;  // 32x32x16 BF16 operand layout (optional)
+    const void* emb_fp8 = nullptr;   // same element order, e4m3fn codes (optional)
+    const float* fp8_scale = nullptr;  // per ad row (optional)
+    // quantisation error summaries for the recall certificate, per copy (0 = BF16, 1 = FP8):
+    // max_a ||e_a - e^_a||_2 and max_a ||e^_a||_2; and max_a ||e_a||_2 of the FP32 rows
+    double q_err2[2] = {0.0, 0.0}, q_norm2[2] = {0.0, 0.0}, e_norm2 = 0.0;
     const ChunkHdr* chunks = nullptr;
     const uint32_t* words = nullptr;
     const float* weights = nullptr;
@@ -66,6 +76,8 @@ struct Index {
 struct ArenaPlan {
     size_t off_emb_f32 = 0, off_chunks = 0, off_words = 0, off_weights = 0, total = 0;
     size_t bytes_emb_f32 = 0, bytes_chunks = 0, bytes_words = 0, bytes_weights = 0;
+    size_t off_emb_bf16 = 0, off_emb_fp8 = 0, off_fp8_scale = 0;
+    size_t bytes_emb_bf16 = 0, bytes_emb_fp8 = 0, bytes_fp8_scale = 0;
     int64_t n_chunks = 0, n_words = 0;
 };
 
@@ -85,6 +97,15 @@ void codec_encode(const uint32_t* ids, int64_t n, ChunkHdr* hdr, uint32_t* words
 // Decode one list encoded with word_base = post_base = 0.
 bool codec_decode(const ChunkHdr* hdr, int64_t n_chunks, const uint32_t* words,
                   int64_t n_words, int64_t n, uint32_t* ids);
+
+// ---------------------------------------------------------------- quantisers (quant.cpp)
+
+uint16_t bf16_rne(float x);
+float bf16_to_f32(uint16_t h);
+uint8_t fp8_e4m3_rne(float x);
+float fp8_e4m3_to_f32(uint8_t c);
+// position of element (row a, dim k) in the 32x32x16 BF16 operand layout (elements)
+size_t mfma16_index(int64_t a, int k, int d);
 
 // ---------------------------------------------------------------- kernels
 

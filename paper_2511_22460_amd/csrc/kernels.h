@@ -11,6 +11,7 @@ constexpr int kStatusDone = 0;
 constexpr int kStatusPending = 1;
 constexpr int kStatusNeedLower = 2;
 constexpr int kStatusOverflow = 3;
+constexpr int kStatusUncertified = 4;
 
 struct DecodeArgs {
     const ChunkHdr* chunks;
@@ -21,15 +22,21 @@ struct DecodeArgs {
     const int32_t* uk_wshift;         // per distinct key: Sw_k, weights become round(w * 2^Sw_k)
     int32_t n_ukeys;
     uint32_t total_chunks;
-    uint32_t* tile_cnt;               // count pass
-    const uint32_t* tile_off;         // place pass
-    uint32_t* tile_fill;              // place pass
-    const uint32_t* users_off;        // non-null: entries carry their key's users range
-    uint32_t* bucket;                 // place pass: pairs (users range or slot | ad & 31, w_fix)
+    int64_t n_tiles;
+    int64_t n_super;                  // 1024-ad super-tiles
+    uint32_t* st_cnt;                 // count pass: postings per super-tile
+    const uint32_t* st_off;           // n_super + 1 exclusive prefix
+    uint32_t* st_fill;                // place pass: running fill per super-tile
+    uint32_t* stage;                  // place pass: pairs ((slot << 10) | ad & 1023, w_fix)
+    const uint32_t* users_off;        // non-null: final entries carry their key's users range
+    uint32_t* tile_off;               // refine: n_tiles + 1 offsets into bucket
+    uint32_t* bucket;                 // refine: pairs (users range or slot | ad & 31, w_fix)
 };
 
 struct ScoreArgs {
-    const void* emb;                  // swizzled FP32 embeddings
+    const void* emb;                  // the scanned embedding copy (layout per dtype)
+    const float* fp8_scale;           // FP8 copy: per-ad scales
+    int32_t dtype;                    // 0 FP32, 1 BF16, 2 FP8
     int64_t n_ads;
     const float* user;                // B x D
     int32_t n_queries;
@@ -46,6 +53,7 @@ struct ScoreArgs {
     const uint32_t* thresh;           // pairs (key hi, ~id lo) per query
     const uint32_t* active;           // per query
     unsigned long long* cand;         // B x cap
+    float* cand_wide;                 // B x cap cross-term values (approximate scans), or null
     uint32_t* cand_cnt;               // B
     int32_t cap;
     // sample mode
@@ -69,13 +77,38 @@ struct SelectArgs {
 
 struct FinalArgs {
     uint32_t* active;
-    const int32_t* kq;
+    const int32_t* kq;                // K per query
+    const int32_t* kcnt;              // candidates to keep: K (output mode) or K' (prep mode)
     const uint32_t* cand_cnt;
     int32_t cap;
     const unsigned long long* cand;
+    const float* cand_wide;           // prep mode
     int32_t* status;
     uint32_t* thresh;
     uint32_t* unresolved;
+    int32_t prep;                     // 0: write the top K; 1: stage the top K' for the rescore
+    const int64_t* out_off;
+    uint32_t* out_ids;
+    float* out_scores;
+    uint32_t* r_id;                   // prep: B x r_ld ids in approximate rank order
+    float* r_wide;                    // prep: their cross-term values
+    float* r_stilde;                  // prep: the K'-th approximate score per query
+    int32_t r_ld;
+};
+
+struct RescoreArgs {
+    const void* emb;                  // FP32 copy (32x32x2 layout)
+    const float* user;                // B x D
+    int64_t n_ads;
+    const int32_t* kq;
+    const int32_t* kcnt;
+    int32_t* status;
+    uint32_t* uncertified;
+    const uint32_t* r_id;
+    const float* r_wide;
+    const float* r_stilde;
+    const float* eps;                 // per query: bound on |approximate - exact| score
+    int32_t r_ld;
     const int64_t* out_off;
     uint32_t* out_ids;
     float* out_scores;
@@ -85,6 +118,7 @@ int launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, void* stream);
 int64_t scan_tmp_words(int64_t n);
 int launch_excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, void* stream);
 int launch_decode(const DecodeArgs& a, int place, void* stream);
+int launch_refine(const DecodeArgs& a, void* stream);
 int launch_decode_key(const ChunkHdr* chunks, const uint32_t* words, const float* weights,
                       uint32_t chunk0, uint32_t n_chunks, uint32_t* ids, float* w, void* stream);
 bool score_dim_supported(int dim);
@@ -93,5 +127,6 @@ int score_group_queries(int dim);
 int launch_score(const ScoreArgs& a, int dim, int mode, int ctas, void* stream);
 int launch_select(const SelectArgs& a, int n_queries, void* stream);
 int launch_finalize(const FinalArgs& a, int n_queries, void* stream);
+int launch_rescore(const RescoreArgs& a, int dim, int n_queries, void* stream);
 
 }  // namespace ebr

@@ -166,8 +166,9 @@ __device__ __forceinline__ uint32_t decode_chunk_lane(const ChunkHdr* chunks, co
 constexpr int kChunksPerWave = 8;
 
 // One wavefront decodes kChunksPerWave consecutive chunks of the batch's distinct keys and
-// counts (place == 0) or places (place == 1) their postings into 32-ad tile buckets. Runs
-// of postings in the same tile are aggregated into one atomic per run.
+// counts (place == 0) or places (place == 1) their postings into 1024-ad super-tile buckets.
+// Runs of postings in the same super-tile are aggregated into one atomic per run. A placed
+// entry is ((slot << 10) | ad & 1023, w_fix); k_refine orders each super-tile by 32-ad tile.
 __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
     const int lane = lane_id();
     const uint32_t gw = blockIdx.x * 4u + (threadIdx.x >> 6);
@@ -188,36 +189,73 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
         uint32_t post_off;
         const uint32_t id = decode_chunk_lane(a.chunks, a.words, chunk, &count, &post_off);
         const bool valid = lane < count;
-        const uint32_t tile = id >> kTileShift;
-        const uint32_t prev = __shfl_up(tile, 1, 64);
-        const bool head = valid && (lane == 0 || tile != prev);
+        const uint32_t st = id >> kSuperShift;
+        const uint32_t prev = __shfl_up(st, 1, 64);
+        const bool head = valid && (lane == 0 || st != prev);
         const uint64_t heads = __ballot(head);
         const uint64_t above = (lane == 63) ? 0ull : (heads & (~0ull << (lane + 1)));
         const int next = above ? (int)__builtin_ctzll(above) : count;
         const int run = next - lane;
         if (!place) {
-            if (head) atomicAdd(&a.tile_cnt[tile], (uint32_t)run);
+            if (head) atomicAdd(&a.st_cnt[st], (uint32_t)run);
             continue;
         }
-        // entry word x: the key's users range when the batch is one query group, else its
-        // slot; the low five bits take the ad's offset in its tile
-        uint32_t entry_x = u << kTileShift;
-        if (a.users_off) {
-            const uint32_t u0 = a.users_off[u];
-            entry_x = (u0 << 13) | ((a.users_off[u + 1] - u0 - 1u) << kTileShift);
-        }
         uint32_t base = 0;
-        if (head) base = atomicAdd(&a.tile_fill[tile], (uint32_t)run);
+        if (head) base = atomicAdd(&a.st_fill[st], (uint32_t)run);
         const uint64_t upto = (lane == 63) ? heads : (heads & ((2ull << lane) - 1ull));
         const int my_head = upto ? 63 - (int)__builtin_clzll(upto) : 0;
         base = __shfl(base, my_head, 64);
         if (valid) {
-            const uint32_t pos = a.tile_off[tile] + base + (uint32_t)(lane - my_head);
+            const uint32_t pos = a.st_off[st] + base + (uint32_t)(lane - my_head);
             const float w = a.weights[post_off + lane];
             const int wfix = __double2int_rn(ldexp((double)w, a.uk_wshift[u]));
-            reinterpret_cast<uint2*>(a.bucket)[pos] =
-                make_uint2(entry_x | (id & (kTileAds - 1)), (uint32_t)wfix);
+            reinterpret_cast<uint2*>(a.stage)[pos] =
+                make_uint2((u << kSuperShift) | (id & (kSuperAds - 1)), (uint32_t)wfix);
         }
+    }
+}
+
+// One work-group per super-tile: counting sort of its entries by 32-ad tile (LDS counters),
+// the tile offsets, and the final entry format read by k_score: x = (u0 << 13) |
+// ((cnt - 1) << 5) | ad & 31 when the batch is one query group (users[u0, u0 + cnt) are the
+// key's users), else (slot << 5) | ad & 31; y = w_fix.
+__global__ __launch_bounds__(256) void k_refine(DecodeArgs a) {
+    __shared__ uint32_t s_cnt[kTilesPerSuper], s_off[kTilesPerSuper];
+    const uint32_t st = blockIdx.x;
+    const uint32_t beg = a.st_off[st], end = a.st_off[st + 1];
+    const int tid = (int)threadIdx.x;
+    if (tid < kTilesPerSuper) s_cnt[tid] = 0u;
+    __syncthreads();
+    const uint2* in = reinterpret_cast<const uint2*>(a.stage);
+    for (uint32_t i = beg + (uint32_t)tid; i < end; i += 256u)
+        atomicAdd(&s_cnt[(in[i].x >> kTileShift) & (kTilesPerSuper - 1)], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = beg;
+        for (int t = 0; t < kTilesPerSuper; ++t) {
+            s_off[t] = run;
+            run += s_cnt[t];
+            s_cnt[t] = 0u;
+        }
+    }
+    __syncthreads();
+    if (tid < kTilesPerSuper) {
+        const uint64_t tile = (uint64_t)st * kTilesPerSuper + (uint64_t)tid;
+        if (tile < (uint64_t)a.n_tiles) a.tile_off[tile] = s_off[tid];
+    }
+    if (st == gridDim.x - 1 && tid == 0) a.tile_off[a.n_tiles] = end;
+    uint2* out = reinterpret_cast<uint2*>(a.bucket);
+    for (uint32_t i = beg + (uint32_t)tid; i < end; i += 256u) {
+        const uint2 e = in[i];
+        const uint32_t t = (e.x >> kTileShift) & (kTilesPerSuper - 1);
+        const uint32_t pos = s_off[t] + atomicAdd(&s_cnt[t], 1u);
+        const uint32_t u = e.x >> kSuperShift, o = e.x & (kTileAds - 1);
+        uint32_t x = (u << kTileShift) | o;
+        if (a.users_off) {
+            const uint32_t u0 = a.users_off[u];
+            x = (u0 << 13) | ((a.users_off[u + 1] - u0 - 1u) << kTileShift) | o;
+        }
+        out[pos] = make_uint2(x, e.y);
     }
 }
 
@@ -269,16 +307,27 @@ template <int D> struct ScoreShape {
     static constexpr int NT = 64 * (CW + kProducerWaves);
 };
 
-__device__ __forceinline__ int acc_idx(int q, int o) { return q * kTileAds + (o ^ (q & 31)); }
+// Accumulator cell of (query row q, ad offset o): rows are grouped by four so that the four
+// consecutive rows one lane of the 32x32 matrix-core tile owns are adjacent (two 16-byte
+// LDS reads); the ad column is XOR-swizzled by the row group so that the users of one posting
+// (same ad, many rows) spread over the banks.
+__device__ __forceinline__ int acc_idx(int q, int o) {
+    return (((q >> 2) * kTileAds + (o ^ ((q >> 2) & 31))) << 2) | (q & 3);
+}
 
 // Rare path of the selection epilogue: append one survivor to its query's candidate buffer.
 // Kept out of line so that the per-row buffer addresses are not hoisted into registers.
+// The candidate's cross-term value is kept beside it when the scan is approximate, for the
+// exact rescore.
 __device__ __attribute__((noinline)) void append_candidate(unsigned long long* cand,
-                                                           uint32_t* cand_cnt, int cap, int q,
-                                                           uint32_t key, uint32_t idk) {
+                                                           uint32_t* cand_cnt, float* cand_wide,
+                                                           int cap, int q, uint32_t key,
+                                                           uint32_t idk, float wide) {
     const uint32_t pos = atomicAdd(&cand_cnt[q], 1u);
-    if (pos < (uint32_t)cap)
+    if (pos < (uint32_t)cap) {
         cand[(int64_t)q * cap + pos] = ((unsigned long long)key << 32) | (unsigned long long)idk;
+        if (cand_wide) cand_wide[(int64_t)q * cap + pos] = wide;
+    }
 }
 
 // Dense test hook: store one (query, ad) pair of terms (out of line, as above).
@@ -387,17 +436,61 @@ __device__ __forceinline__ void prod_tile(const ScoreArgs& a, int g, int pw, con
 // consumers score tile it from LDS buffers [it & 1] (and clear the accumulators they read)
 // while the producers fill buffers [(it + 1) & 1] with tile it + 1 and prefetch the entries
 // of tile it + 2. Every wave executes exactly 1 + n_it barriers.
-template <int D, int MODE>
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// One e4m3fn code -> the BF16 bits of the same value (exact: every e4m3 value is a BF16 value).
+__device__ __forceinline__ uint32_t fp8_to_bf16_bits(uint32_t c) {
+    const uint32_t sgn = (c & 0x80u) << 8, e = (c >> 3) & 15u, m = c & 7u;
+    if (e != 0u) return sgn | ((e + 120u) << 7) | (m << 4);
+    if (m == 0u) return sgn;
+    const uint32_t p = 31u - __builtin_clz(m);  // m = 2^p (1 + f), value m 2^-9
+    return sgn | ((p + 118u) << 7) | ((m - (1u << p)) << (7u - p));
+}
+
+// Eight e4m3fn codes (little-endian in v) -> eight BF16 values packed as one 16-byte operand.
+__device__ __forceinline__ f32x4 fp8x8_to_bf16x8(uint2 v) {
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t src = i < 2 ? v.x : v.y;
+        const int sh = (i & 1) * 16;
+        w[i] = fp8_to_bf16_bits((src >> sh) & 0xffu) | (fp8_to_bf16_bits((src >> (sh + 8)) & 0xffu) << 16);
+    }
+    return f32x4{__uint_as_float(w[0]), __uint_as_float(w[1]), __uint_as_float(w[2]), __uint_as_float(w[3])};
+}
+
+// Embedding copies the scan can stream (DT): 0 = FP32 (32x32x2 layout), 1 = BF16 and
+// 2 = FP8 (both in the 32x32x16 BF16 operand layout; FP8 is expanded to BF16 in LDS and its
+// per-ad scale applied to the finished dot product).
+template <int D, int DT> struct EmbStage {
+    static constexpr int UNITS = DT == 0 ? (D / 8) * 64 : (D / 16) * 64;  // 16-byte LDS units
+    static constexpr int PER = (UNITS + 64 * kProducerWaves - 1) / (64 * kProducerWaves);
+};
+
+// Persistent over tiles blockIdx.x, blockIdx.x + gridDim.x, ...; iteration `it` has the
+// consumers score tile it from LDS buffers [it & 1] (and clear the accumulators they read)
+// while the producers fill buffers [(it + 1) & 1] with tile it + 1 and prefetch ahead. Every
+// wave executes exactly 2 + n_it barriers.
+template <int D, int MODE, int DT>
 __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
-    constexpr int NQ = D / 8;  // quads per lane
+    constexpr int NQ = D / 8;
     constexpr int GQ = ScoreShape<D>::GQ;
     constexpr int CW = ScoreShape<D>::CW;
     constexpr int NT = ScoreShape<D>::NT;
     constexpr int kProdThreads = 64 * kProducerWaves;
-    __shared__ unsigned long long s_acc[2][GQ * kTileAds];
+    constexpr int UNITS = EmbStage<D, DT>::UNITS;
+    constexpr int PER = EmbStage<D, DT>::PER;
+    __shared__ __attribute__((aligned(16))) unsigned long long s_acc[2][GQ * kTileAds];
     __shared__ f32x4 s_emb[2][NQ * 64];
-    __shared__ double s_inv[GQ];
-    __shared__ float s_thr[GQ];
+    __shared__ float s_escale[2][kTileAds];
+    __shared__ __attribute__((aligned(16))) double s_inv[GQ];
+    __shared__ __attribute__((aligned(16))) float s_thr[GQ];
     __shared__ uint32_t s_thr_hi[GQ];
     __shared__ uint32_t s_thr_lo[GQ];
     __shared__ uint32_t s_live[GQ];
@@ -421,13 +514,13 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             const uint32_t hi = in ? a.thresh[2 * q] : 0xffffffffu;
             s_thr_hi[i] = hi;
             s_thr_lo[i] = in ? a.thresh[2 * q + 1] : 0xffffffffu;
-            s_thr[i] = key_score(hi);
-            s_live[i] = (in && a.active[q]) ? 1u : 0u;
+            const bool live = in && a.active[q];
+            s_thr[i] = live ? key_score(hi) : __builtin_nanf("");
+            s_live[i] = live ? 1u : 0u;
         } else {
             s_live[i] = in ? 1u : 0u;
         }
     }
-    const f32x4* emb = reinterpret_cast<const f32x4*>(a.emb);
     auto tile_at = [&](int i) -> uint32_t {
         const int w = first + i * G;
         return a.tile_list ? a.tile_list[w] : (uint32_t)w;
@@ -437,9 +530,37 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     if (producer) {
         const int pw = wave - CW;
         const int ptid = tid - 64 * CW;
-        // pipeline: bucket bounds two tiles ahead, round-0 entries one tile ahead
+        // pipeline: bucket bounds two tiles ahead, round-0 entries one tile ahead, the
+        // embedding block in registers two tiles ahead (written to LDS one tile ahead)
+        struct Raw {
+            f32x4 u[PER];    // FP32 / BF16 units
+            uint2 c[PER];    // FP8 codes
+            float scale;     // FP8: the scale of ad (ptid) of the tile
+        };
+        auto emb_load = [&](uint32_t t, Raw& r) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int j = ptid + k * kProdThreads;
+                if (j < UNITS) {
+                    if (DT == 2) r.c[k] = reinterpret_cast<const uint2*>(a.emb)[(int64_t)t * UNITS + j];
+                    else r.u[k] = reinterpret_cast<const f32x4*>(a.emb)[(int64_t)t * UNITS + j];
+                }
+            }
+            if (DT == 2 && ptid < kTileAds) r.scale = a.fp8_scale[(int64_t)t * kTileAds + ptid];
+        };
+        auto emb_store = [&](int buf, const Raw& r) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int j = ptid + k * kProdThreads;
+                if (j < UNITS) s_emb[buf][j] = DT == 2 ? fp8x8_to_bf16x8(r.c[k]) : r.u[k];
+            }
+            if (DT == 2 && ptid < kTileAds) s_escale[buf][ptid] = r.scale;
+        };
+        Raw e1, e2;
         const uint32_t t0 = tile_at(0);
-        for (int j = ptid; j < NQ * 64; j += kProdThreads) s_emb[0][j] = emb[(int64_t)t0 * NQ * 64 + j];
+        emb_load(t0, e1);
+        if (n_it > 1) emb_load(tile_at(1), e2);
+        emb_store(0, e1);
         prod_tile(a, g, pw, prod_entries(a, prod_bounds(a, t0), pw), s_acc[0]);
         ProdTile p1{};
         uint2 b2 = make_uint2(0u, 0u);
@@ -449,9 +570,8 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         for (int it = 0; it < n_it; ++it) {
             const int nb = (it & 1) ^ 1;
             if (it + 1 < n_it) {
-                const uint32_t tn = tile_at(it + 1);
-                for (int j = ptid; j < NQ * 64; j += kProdThreads)
-                    s_emb[nb][j] = emb[(int64_t)tn * NQ * 64 + j];
+                emb_store(nb, e2);  // tile it + 1, loaded one iteration ago
+                if (it + 2 < n_it) emb_load(tile_at(it + 2), e2);
                 uint2 b3 = make_uint2(0u, 0u);
                 if (it + 3 < n_it) b3 = prod_bounds(a, tile_at(it + 3));
                 ProdTile p2{};
@@ -465,15 +585,35 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         return;
     }
 
-    // consumer: A operand (user rows) of this wave's 32-query block, kept in registers
+    // consumer: A operand (user rows) of this wave's 32-query block, kept in registers:
+    // FP32 pairs for the 32x32x2 FP32 product, or BF16 octets (round to nearest even)
     const int q0 = qbase + wave * 32;
-    float ureg[D / 2];
+    constexpr int NUR = DT == 0 ? D / 2 : 1;
+    constexpr int NUB = DT == 0 ? 1 : D / 16;
+    float ureg[NUR];
+    bf16x8 ubf[NUB];
     {
         const int q = q0 + (lane & 31);
-        const int kofs = lane >> 5;
+        if (DT == 0) {
+            const int kofs = lane >> 5;
 #pragma unroll
-        for (int s = 0; s < D / 2; ++s)
-            ureg[s] = (q < B) ? a.user[(int64_t)q * D + 2 * s + kofs] : 0.0f;
+            for (int s = 0; s < NUR; ++s)
+                ureg[s] = (q < B) ? a.user[(int64_t)q * D + 2 * s + kofs] : 0.0f;
+        } else {
+            const int kofs = 8 * (lane >> 5);
+#pragma unroll
+            for (int s = 0; s < NUB; ++s) {
+                uint32_t w[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float x0 = (q < B) ? a.user[(int64_t)q * D + 16 * s + kofs + 2 * i] : 0.0f;
+                    const float x1 = (q < B) ? a.user[(int64_t)q * D + 16 * s + kofs + 2 * i + 1] : 0.0f;
+                    w[i] = bf16_bits(x0) | (bf16_bits(x1) << 16);
+                }
+                ubf[s] = __builtin_bit_cast(bf16x8, f32x4{__uint_as_float(w[0]), __uint_as_float(w[1]),
+                                                          __uint_as_float(w[2]), __uint_as_float(w[3])});
+            }
+        }
     }
     bool wave_live = false;
     if (q0 < B) {
@@ -483,20 +623,35 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     }
     __syncthreads();
 
+    // this lane's rows: group g4 (0..3) holds rows rg(g4) .. rg(g4) + 3 of the group's 256
+    auto rg = [&](int g4) { return wave * 32 + 8 * g4 + 4 * (lane >> 5); };
+    const int o = lane & 31;
     for (int it = 0; it < n_it; ++it) {
         const int cur = it & 1;
         unsigned long long* acc = s_acc[cur];
         if (!wave_live) {
             // rows no live wave reads: keep the buffer clear for its next use
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int ql = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                acc[acc_idx(ql, lane & 31)] = 0ull;
+            for (int g4 = 0; g4 < 4; ++g4) {
+                ulonglong2* p = reinterpret_cast<ulonglong2*>(acc + acc_idx(rg(g4), o));
+                p[0] = make_ulonglong2(0ull, 0ull);
+                p[1] = make_ulonglong2(0ull, 0ull);
             }
-        } else {
-            const uint32_t tile = tile_at(it);
-            f32x16 c = {};
-            const f32x4* eb = s_emb[cur];
+            __syncthreads();
+            continue;
+        }
+        // cross term of this lane's 16 cells (issued before the dot products)
+        ulonglong2 av[8];
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+            const ulonglong2* p = reinterpret_cast<const ulonglong2*>(acc + acc_idx(rg(g4), o));
+            av[2 * g4] = p[0];
+            av[2 * g4 + 1] = p[1];
+        }
+        const uint32_t tile = tile_at(it);
+        f32x16 c = {};
+        const f32x4* eb = s_emb[cur];
+        if (DT == 0) {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 const f32x4 e4 = eb[i * 64 + lane];
@@ -504,39 +659,66 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
                 for (int j = 0; j < 4; ++j)
                     c = __builtin_amdgcn_mfma_f32_32x32x2f32(ureg[4 * i + j], e4[j], c, 0, 0, 0);
             }
-            const int64_t ad = (int64_t)tile * kTileAds + (lane & 31);
-            const bool ad_ok = ad < a.n_ads;
-            uint32_t* skeys = nullptr;
-            uint32_t scol = 0;
-            if (MODE == 1) {
-                skeys = a.sample_keys + (int64_t)q0 * a.sample_ld;
-                scol = (uint32_t)(first + it * G) * kTileAds + (uint32_t)(lane & 31);
-            }
+        } else {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int ql = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int q = qbase + ql;
-                const int idx = acc_idx(ql, lane & 31);
-                const long long v = (long long)acc[idx];
-                acc[idx] = 0ull;
-                const float wide = (float)((double)v * s_inv[ql]);
-                const float deep = c[r];
+            for (int s2 = 0; s2 < NUB; ++s2)
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ubf[s2], __builtin_bit_cast(bf16x8, eb[s2 * 64 + lane]),
+                                                            c, 0, 0, 0);
+        }
+        const float escale = DT == 2 ? s_escale[cur][o] : 1.0f;
+        // clear the cells for the buffer's next use
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+            ulonglong2* p = reinterpret_cast<ulonglong2*>(acc + acc_idx(rg(g4), o));
+            p[0] = make_ulonglong2(0ull, 0ull);
+            p[1] = make_ulonglong2(0ull, 0ull);
+        }
+        const int64_t ad = (int64_t)tile * kTileAds + o;
+        const bool ad_ok = ad < a.n_ads;
+        float sc[16], wd[16];
+        bool pass = false;
+        // sample pass: row base of this wave's block plus a 32-bit offset per row
+        uint32_t* skeys = MODE == 1 ? a.sample_keys + (int64_t)q0 * a.sample_ld : nullptr;
+        const uint32_t scol = (uint32_t)(first + it * G) * kTileAds + (uint32_t)o;
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+            const int r0 = rg(g4);
+            const double2 iv01 = *reinterpret_cast<const double2*>(s_inv + r0);
+            const double2 iv23 = *reinterpret_cast<const double2*>(s_inv + r0 + 2);
+            const f32x4 th = *reinterpret_cast<const f32x4*>(s_thr + r0);
+            const double inv[4] = {iv01.x, iv01.y, iv23.x, iv23.y};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const unsigned long long u = (k & 1) ? av[2 * g4 + (k >> 1)].y : av[2 * g4 + (k >> 1)].x;
+                const long long v = (long long)u;
+                const float wide = (float)((double)v * inv[k]);
+                const float deep = DT == 2 ? c[4 * g4 + k] * escale : c[4 * g4 + k];
                 if (MODE == 2) {
+                    const int q = qbase + r0 + k;
                     if (ad_ok && q < B)
                         store_dense(a.deep_out, a.wide_out, (int64_t)q * a.n_ads + ad, deep, wide);
+                } else if (MODE == 1) {
+                    const int rl = r0 - wave * 32 + k;
+                    if (q0 + rl < B)
+                        skeys[(uint32_t)rl * (uint32_t)a.sample_ld + scol] = ad_ok ? score_key(deep + wide) : 0u;
                 } else {
-                    const float sc = deep + wide;
-                    if (MODE == 1) {
-                        // row base of this wave's 32-query block + a 32-bit offset per row
-                        if (q < B)
-                            skeys[(uint32_t)(ql - wave * 32) * (uint32_t)a.sample_ld + scol] =
-                                ad_ok ? score_key(sc) : 0u;
-                    } else if (ad_ok && sc >= s_thr[ql] && s_live[ql]) {
-                        // rare: exact (key, id) comparison against the threshold
-                        const uint32_t key = score_key(sc);
-                        const uint32_t idk = 0xffffffffu - (uint32_t)ad;
+                    sc[4 * g4 + k] = deep + wide;
+                    wd[4 * g4 + k] = wide;
+                    pass |= sc[4 * g4 + k] >= th[k];  // NaN threshold: never
+                }
+            }
+        }
+        if (MODE == 0 && __ballot(pass && ad_ok) != 0ull) {
+            // rare: exact (key, id) comparison against the threshold, then append
+            if (pass && ad_ok) {
+                const uint32_t idk = 0xffffffffu - (uint32_t)ad;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int ql = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    if (sc[r] >= s_thr[ql]) {
+                        const uint32_t key = score_key(sc[r]);
                         if (key > s_thr_hi[ql] || (key == s_thr_hi[ql] && idk >= s_thr_lo[ql]))
-                            append_candidate(a.cand, a.cand_cnt, a.cap, q, key, idk);
+                            append_candidate(a.cand, a.cand_cnt, a.cand_wide, a.cap, qbase + ql, key, idk, wd[r]);
                     }
                 }
             }
@@ -596,14 +778,23 @@ __global__ __launch_bounds__(1024) void k_select(SelectArgs a) {
 
 // ------------------------------------------------------------------ finalize
 
+// Per query (one work-group): the candidate keys (score key << 32 | ~id) are sorted in LDS;
+// with C candidates and a target of Kc = kcnt[q]:
+//  C < Kc        - too few ads reached the threshold: status NeedLower (revise and rescan)
+//  C > capacity  - overflow: the threshold becomes the Kc-th largest stored key (it strictly
+//                  rises, since keys are distinct) and the query is rescanned
+//  otherwise     - output mode: the first K are the result (ids, FP32 scores);
+//                  prep mode: the first Kc go, in rank order, to the rescore scratch (id and
+//                  the cross-term value carried with the candidate), with the Kc-th
+//                  approximate score for the recall certificate.
 __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
     __shared__ unsigned long long s[kCandCap];
     const int q = (int)blockIdx.x;
     const int tid = (int)threadIdx.x;
     if (!a.active[q]) return;
-    const int K = a.kq[q];
+    const int Kc = a.kcnt[q];
     const uint32_t c = a.cand_cnt[q];
-    if ((int64_t)c < (int64_t)K) {
+    if ((int64_t)c < (int64_t)Kc) {
         if (tid == 0) { a.status[q] = kStatusNeedLower; atomicAdd(a.unresolved, 1u); }
         return;
     }
@@ -628,7 +819,7 @@ __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
     }
     if (c > (uint32_t)a.cap) {
         if (tid == 0) {
-            const unsigned long long t = s[K - 1];
+            const unsigned long long t = s[Kc - 1];
             a.thresh[2 * q] = (uint32_t)(t >> 32);
             a.thresh[2 * q + 1] = (uint32_t)t;
             a.status[q] = kStatusOverflow;
@@ -636,13 +827,115 @@ __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
         }
         return;
     }
+    if (!a.prep) {
+        const int K = a.kq[q];
+        const int64_t o = a.out_off[q];
+        for (int i = tid; i < K; i += 1024) {
+            const unsigned long long t = s[i];
+            a.out_ids[o + i] = 0xffffffffu - (uint32_t)t;
+            a.out_scores[o + i] = key_score((uint32_t)(t >> 32));
+        }
+    } else {
+        // the Kc best by approximate key, in rank order, with their carried cross terms
+        const unsigned long long T = s[Kc - 1];
+        const float* cw = a.cand_wide + (int64_t)q * a.cap;
+        for (int p = tid; p < n; p += 1024) {
+            const unsigned long long key = src[p];
+            if (key >= T) {
+                int lo = 0, hi = Kc - 1;  // s[0..Kc) descending and distinct: find key
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s[mid] > key) lo = mid + 1; else hi = mid;
+                }
+                a.r_id[(int64_t)q * a.r_ld + lo] = 0xffffffffu - (uint32_t)key;
+                a.r_wide[(int64_t)q * a.r_ld + lo] = cw[p];
+            }
+        }
+        if (tid == 0) a.r_stilde[q] = key_score((uint32_t)(T >> 32));
+    }
+    if (tid == 0) { a.status[q] = kStatusDone; a.active[q] = 0u; }
+}
+
+// Exact FP32 rescore of the Kc approximate-best candidates of query q (one work-group): each
+// candidate's FP32 row is gathered from the 32x32x2 layout as D/4 16-byte pieces, one thread
+// per piece, and the dot product is reduced over the pieces in a fixed order; the score adds
+// the carried cross term. The Kc exact keys are sorted and the first K written. Certificate:
+// every ad outside the candidates has an approximate score <= the Kc-th approximate score s~
+// and differs from its exact score by at most eps_q, so s~ + eps_q < (K-th exact score)
+// proves the result is the exact top-K; otherwise the query is marked uncertified.
+template <int D>
+__global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
+    constexpr int NQ = D / 8;
+    constexpr int PC = D / 4;                        // 16-byte pieces per row
+    constexpr int TPC = PC <= 16 ? 16 : 32;          // threads per candidate (power of two)
+    constexpr int CPP = 1024 / TPC;                  // candidates per pass
+    __shared__ unsigned long long s[kMaxK];
+    __shared__ float s_u[D];
+    const int q = (int)blockIdx.x;
+    const int tid = (int)threadIdx.x;
+    const int K = a.kq[q];
+    if (K <= 0 || a.status[q] != kStatusDone) return;
+    const int Kc = a.kcnt[q];
+    for (int i = tid; i < D; i += 1024) s_u[i] = a.user[(int64_t)q * D + i];
+    __syncthreads();
+    const f32x4* emb = reinterpret_cast<const f32x4*>(a.emb);
+    const int piece = tid % TPC;
+    const int i4 = piece >> 1, h = piece & 1;
+    for (int r0 = 0; r0 < Kc; r0 += CPP) {
+        const int r = r0 + tid / TPC;
+        const bool ok = r < Kc;
+        float part = 0.0f;
+        uint32_t id = 0;
+        if (ok) {
+            id = a.r_id[(int64_t)q * a.r_ld + r];
+            if (piece < PC) {
+                const int64_t b = id >> kTileShift;
+                const f32x4 e4 = emb[(b * NQ + i4) * 64 + (int)(id & (kTileAds - 1)) + 32 * h];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) part = fmaf(s_u[8 * i4 + 2 * j + h], e4[j], part);
+            }
+        }
+#pragma unroll
+        for (int m = TPC / 2; m > 0; m >>= 1) part += __shfl_xor(part, m, TPC);
+        if (ok && piece == 0) {
+            const float sc = part + a.r_wide[(int64_t)q * a.r_ld + r];
+            s[r] = ((unsigned long long)score_key(sc) << 32) | (unsigned long long)(0xffffffffu - id);
+        }
+    }
+    int P = 64;
+    while (P < Kc) P <<= 1;
+    for (int i = Kc + tid; i < P; i += 1024) s[i] = 0ull;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < P; i += 1024) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const unsigned long long x = s[i], y = s[ixj];
+                    const bool desc = (i & k) == 0;
+                    if (desc ? (x < y) : (x > y)) { s[i] = y; s[ixj] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
     const int64_t o = a.out_off[q];
     for (int i = tid; i < K; i += 1024) {
         const unsigned long long t = s[i];
         a.out_ids[o + i] = 0xffffffffu - (uint32_t)t;
         a.out_scores[o + i] = key_score((uint32_t)(t >> 32));
     }
-    if (tid == 0) { a.status[q] = kStatusDone; a.active[q] = 0u; }
+    if (tid == 0) {
+        bool cert = (int64_t)Kc >= a.n_ads;
+        if (!cert) {
+            const double sk = (double)key_score((uint32_t)(s[K - 1] >> 32));
+            cert = (double)a.r_stilde[q] + (double)a.eps[q] < sk;
+        }
+        if (!cert) {
+            a.status[q] = kStatusUncertified;
+            atomicAdd(a.uncertified, 1u);
+        }
+    }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -669,6 +962,12 @@ int launch_excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t*
     return last(hipSuccess);
 }
 
+int launch_refine(const DecodeArgs& a, void* stream) {
+    if (a.n_super <= 0) return 0;
+    hipLaunchKernelGGL(k_refine, dim3((unsigned)a.n_super), dim3(256), 0, (hipStream_t)stream, a);
+    return last(hipSuccess);
+}
+
 int launch_decode(const DecodeArgs& a, int place, void* stream) {
     if (a.total_chunks == 0) return 0;
     const uint32_t waves = (a.total_chunks + kChunksPerWave - 1) / kChunksPerWave;
@@ -685,12 +984,19 @@ int launch_decode_key(const ChunkHdr* chunks, const uint32_t* words, const float
     return last(hipSuccess);
 }
 
-template <int D>
-static void launch_score_d(const ScoreArgs& a, int mode, dim3 grid, hipStream_t st) {
+template <int D, int DT>
+static void launch_score_dt(const ScoreArgs& a, int mode, dim3 grid, hipStream_t st) {
     constexpr int NT = ScoreShape<D>::NT;
-    if (mode == 0) hipLaunchKernelGGL((k_score<D, 0>), grid, dim3(NT), 0, st, a);
-    else if (mode == 1) hipLaunchKernelGGL((k_score<D, 1>), grid, dim3(NT), 0, st, a);
-    else hipLaunchKernelGGL((k_score<D, 2>), grid, dim3(NT), 0, st, a);
+    if (mode == 0) hipLaunchKernelGGL((k_score<D, 0, DT>), grid, dim3(NT), 0, st, a);
+    else if (mode == 1) hipLaunchKernelGGL((k_score<D, 1, DT>), grid, dim3(NT), 0, st, a);
+    else hipLaunchKernelGGL((k_score<D, 2, DT>), grid, dim3(NT), 0, st, a);
+}
+
+template <int D>
+static void launch_score_d(const ScoreArgs& a, int mode, int dt, dim3 grid, hipStream_t st) {
+    if (dt == 0) launch_score_dt<D, 0>(a, mode, grid, st);
+    else if (dt == 1) launch_score_dt<D, 1>(a, mode, grid, st);
+    else launch_score_dt<D, 2>(a, mode, grid, st);
 }
 
 int score_group_queries(int dim) { return dim <= 64 ? 256 : 128; }
@@ -707,15 +1013,16 @@ int launch_score(const ScoreArgs& a, int dim, int mode, int ctas, void* stream) 
     const int c = a.n_work < ctas ? a.n_work : ctas;
     dim3 grid((unsigned)c, (unsigned)a.n_qgroups);
     hipStream_t st = (hipStream_t)stream;
+    const int dt = a.dtype;
     switch (dim) {
-        case 16: launch_score_d<16>(a, mode, grid, st); break;
-        case 32: launch_score_d<32>(a, mode, grid, st); break;
-        case 48: launch_score_d<48>(a, mode, grid, st); break;
-        case 64: launch_score_d<64>(a, mode, grid, st); break;
-        case 80: launch_score_d<80>(a, mode, grid, st); break;
-        case 96: launch_score_d<96>(a, mode, grid, st); break;
-        case 112: launch_score_d<112>(a, mode, grid, st); break;
-        case 128: launch_score_d<128>(a, mode, grid, st); break;
+        case 16: launch_score_d<16>(a, mode, dt, grid, st); break;
+        case 32: launch_score_d<32>(a, mode, dt, grid, st); break;
+        case 48: launch_score_d<48>(a, mode, dt, grid, st); break;
+        case 64: launch_score_d<64>(a, mode, dt, grid, st); break;
+        case 80: launch_score_d<80>(a, mode, dt, grid, st); break;
+        case 96: launch_score_d<96>(a, mode, dt, grid, st); break;
+        case 112: launch_score_d<112>(a, mode, dt, grid, st); break;
+        case 128: launch_score_d<128>(a, mode, dt, grid, st); break;
         default: return (int)hipErrorInvalidValue;
     }
     return last(hipSuccess);
@@ -724,6 +1031,24 @@ int launch_score(const ScoreArgs& a, int dim, int mode, int ctas, void* stream) 
 int launch_select(const SelectArgs& a, int n_queries, void* stream) {
     if (n_queries <= 0) return 0;
     hipLaunchKernelGGL(k_select, dim3((unsigned)n_queries), dim3(1024), 0, (hipStream_t)stream, a);
+    return last(hipSuccess);
+}
+
+int launch_rescore(const RescoreArgs& a, int dim, int n_queries, void* stream) {
+    if (n_queries <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    dim3 grid((unsigned)n_queries), block(1024);
+    switch (dim) {
+        case 16: hipLaunchKernelGGL(k_rescore<16>, grid, block, 0, st, a); break;
+        case 32: hipLaunchKernelGGL(k_rescore<32>, grid, block, 0, st, a); break;
+        case 48: hipLaunchKernelGGL(k_rescore<48>, grid, block, 0, st, a); break;
+        case 64: hipLaunchKernelGGL(k_rescore<64>, grid, block, 0, st, a); break;
+        case 80: hipLaunchKernelGGL(k_rescore<80>, grid, block, 0, st, a); break;
+        case 96: hipLaunchKernelGGL(k_rescore<96>, grid, block, 0, st, a); break;
+        case 112: hipLaunchKernelGGL(k_rescore<112>, grid, block, 0, st, a); break;
+        case 128: hipLaunchKernelGGL(k_rescore<128>, grid, block, 0, st, a); break;
+        default: return (int)hipErrorInvalidValue;
+    }
     return last(hipSuccess);
 }
 

@@ -132,8 +132,12 @@ def test_index_validation_errors(mutate, status):
     assert ei.value.status == status
 
 
-def test_unimplemented_dtype_is_reported():
-    E_, offs, ids, w = tiny()
+def test_reduced_precision_copies_grow_the_arena():
+    E_, offs, ids, w = tiny(n_ads=1000, dim=64)
+    base = E.index_size(E_, offs, ids, w)
+    bf = E.index_size(E_, offs, ids, w, dtypes=1 | (1 << E.BF16))
+    f8 = E.index_size(E_, offs, ids, w, dtypes=1 | (1 << E.FP8E4M3))
+    assert bf - base >= 1024 * 64 * 2 and f8 - base >= 1024 * (64 + 4)
     with pytest.raises(E.EbrError) as ei:
-        E.index_size(E_, offs, ids, w, dtypes=1 | (1 << E.BF16))
-    assert ei.value.status == E.EBR_EUNSUPPORTED
+        E.index_size(E_, offs, ids, w, dtypes=1 << 5)
+    assert ei.value.status == E.EBR_EINVAL
