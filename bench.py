@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-queries", type=int, default=-1,
                     help="queries timed on the CPU oracle (-1: about 15 s worth, 0: skip)")
+    ap.add_argument("--precision-steps", type=int, default=10,
+                    help="timed batches of the BF16 and FP8 (+ exact FP32 rescore) scans (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -64,7 +66,8 @@ def main():
     log(f"[bench] generated {args.config}: N={wl.n_ads} V={wl.n_keys} postings={wl.n_postings} "
         f"B={wl.n_queries} in {time.time() - t0:.1f}s")
     t0 = time.time()
-    ix = E.Index.from_workload(wl, device=dev)
+    dtypes = 1 | ((1 << E.BF16) | (1 << E.FP8E4M3) if args.precision_steps > 0 else 0)
+    ix = E.Index.from_workload(wl, device=dev, dtypes=dtypes)
     st = ix.stats()
     log(f"[bench] index built in {time.time() - t0:.1f}s: {st['arena_bytes'] / 1e9:.2f} GB arena, "
         f"{st['bytes_per_posting']:.2f} B/posting, {st['bits_per_id']:.2f} id bits/posting "
@@ -105,6 +108,36 @@ def main():
     rounds = max(t["rounds"] for t in timings)
     flops = 2.0 * B * N * d
     achieved = flops / (score_ms * 1e-3) / 1e12
+
+    # reduced-precision scans of the same batch: BF16 and FP8-e4m3 copies streamed, 4 K
+    # candidates rescored exactly in FP32 (results equal the FP32 path's up to ties)
+    precision = {}
+    if args.precision_steps > 0:
+        for name, dt in (("bf16", E.BF16), ("fp8e4m3", E.FP8E4M3)):
+            for i in range(2):
+                ix.score_topk(U, wl.feat_offsets, wl.feat_keys, wl.k, wl.feat_mult, scan_dtype=dt,
+                              rescore_factor=4, out=out)
+            torch.cuda.synchronize()
+            tt, lat2 = [], []
+            t1 = time.perf_counter()
+            for i in range(args.precision_steps):
+                ts = time.perf_counter()
+                ix.score_topk(U, wl.feat_offsets, wl.feat_keys, wl.k, wl.feat_mult, scan_dtype=dt,
+                              rescore_factor=4, out=out)
+                lat2.append(time.perf_counter() - ts)
+                tt.append(E.last_timings())
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t1
+            q2 = B * args.precision_steps / el
+            precision[name] = {
+                "queries_per_s": q2, "ads_scored_per_s": q2 * N, "ms_per_step": 1000 * el / args.precision_steps,
+                "p99_ms": float(np.percentile(lat2, 99) * 1000), "rescore_factor": 4,
+                "uncertified_queries_per_batch": float(np.mean([t["uncertified"] for t in tt])),
+                "phases_ms": {k: float(np.mean([t[k] for t in tt]))
+                              for k in ("decode_ms", "sample_ms", "score_ms", "finalize_ms", "rescore_ms")},
+                "vs_fp32_queries_per_s": q2 / qps,
+            }
+            log(f"[bench] {name}: {q2:.0f} queries/s ({1000 * el / args.precision_steps:.2f} ms/batch)")
 
     cpu = None
     if args.cpu_queries != 0:
@@ -153,6 +186,7 @@ def main():
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
         "cpu_baseline": cpu,
+        "precision": precision,
     }
     print(json.dumps(res), flush=True)
 

@@ -509,7 +509,7 @@ struct Plan {
     int64_t n_tiles = 0;
     // workspace layout
     size_t off_plan = 0, plan_bytes = 0;
-    size_t o_kc = 0, off_cwide = 0, off_rid = 0, off_rwide = 0, off_rst = 0, off_eps = 0,
+    size_t o_kc = 0, o_aq = 0, off_ctl = 0, off_cwide = 0, off_rid = 0, off_rwide = 0, off_rst = 0, off_eps = 0,
            off_unc = 0, off_fb_users = 0, off_fb_ids = 0, off_fb_scores = 0, fb_limit = 0;
     size_t o_ukb = 0, o_ukp = 0, o_ukw = 0, o_uoff = 0, o_users = 0, o_qi = 0, o_kq = 0, o_jq = 0,
            o_oo = 0, o_st = 0;
@@ -699,6 +699,7 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     P->o_kq = put(4 * (size_t)B);
     P->o_jq = put(4 * (size_t)B);
     P->o_kc = put(4 * (size_t)B);
+    P->o_aq = put(8 * (size_t)B);
     P->o_oo = put(8 * (size_t)(B + 1));
     P->o_st = put(4 * P->sample_tiles.size());
     P->plan_bytes = off - P->off_plan;
@@ -717,6 +718,7 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         P->off_active = put(4 * (size_t)B);
         P->off_ccnt = put(4 * (size_t)B);
         P->off_unres = put(16);
+        P->off_ctl = put(sizeof(Control));
         P->off_cand = put(8 * (size_t)B * kCandCap);
         if (P->dtype != EBR_F32) {
             // everything below the fallback region is enough for an FP32 run of any subset
@@ -748,6 +750,7 @@ static std::vector<char> pack_plan(const Plan& P) {
     cp(P.o_kq, P.kq.data(), 4 * P.kq.size());
     cp(P.o_jq, P.jq.data(), 4 * P.jq.size());
     cp(P.o_kc, P.kcnt.data(), 4 * P.kcnt.size());
+    cp(P.o_aq, P.aq.data(), 8 * P.aq.size());
     cp(P.o_oo, P.out_off.data(), 8 * P.out_off.size());
     cp(P.o_st, P.sample_tiles.data(), 4 * P.sample_tiles.size());
     return blob;
@@ -842,31 +845,6 @@ static ebr_status check_users(const ebr_batch* bt, int B, int dim, hipStream_t s
     return EBR_OK;
 }
 
-// Bound on |approximate score - exact score| of any ad for a query with FP32 user row u
-// (see k_rescore): quantisation of u and of the ad rows, FP32 accumulation of both dot
-// products (d terms each), the FP8 scale product, and the two FP32 additions of the cross
-// term (|cross term| <= A_q).
-static float approx_eps(const Index& ix, int dtype, const float* u, double aq) {
-    const int d = ix.dim;
-    const int c = dtype == EBR_BF16 ? 0 : 1;
-    double nu = 0, nh = 0, du = 0;
-    for (int k = 0; k < d; ++k) {
-        const double x = u[k], h = bf16_to_f32(bf16_rne(u[k]));
-        nu += x * x;
-        nh += h * h;
-        du += (h - x) * (h - x);
-    }
-    nu = std::sqrt(nu);
-    nh = std::sqrt(nh);
-    du = std::sqrt(du);
-    const double gamma = d * std::ldexp(1.0, -24) * 1.01;
-    const double R = ix.q_err2[c], Eh = ix.q_norm2[c], E = ix.e_norm2;
-    double eps = du * Eh + nu * R + gamma * (nh * Eh + nu * E) + std::ldexp(1.0, -24) * nh * Eh +
-                 std::ldexp(1.0, -22) * (std::max(nu * E, nh * Eh) + aq);
-    eps = eps * 1.001 + 1e-30;
-    return std::nextafter((float)eps, INFINITY);
-}
-
 static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, size_t ws_bytes,
                             uint32_t* out_ids, float* out_scores, hipStream_t s, ebr_timings* tm) {
     const auto t_host = std::chrono::steady_clock::now();
@@ -878,15 +856,7 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
     const int64_t n_out = P.out_off[P.B];
     if (n_out > 0 && (!out_ids || !out_scores)) { set_error("NULL output"); return EBR_EINVAL; }
     if (P.B == 0 || P.kmax == 0) return EBR_OK;
-    std::vector<float> uhost;
-    st = check_users(batch, P.B, ix.dim, s, &uhost);
-    if (st) return st;
     const bool approx = P.dtype != EBR_F32;
-    std::vector<float> eps;
-    if (approx) {
-        eps.resize(P.B);
-        for (int q = 0; q < P.B; ++q) eps[q] = approx_eps(ix, P.dtype, &uhost[(size_t)q * ix.dim], P.aq[q]);
-    }
     const double host_ms = ms_since(t_host);
     PhaseClock clk(s);
     const int e_dec0 = clk.mark();
@@ -901,11 +871,31 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
     uint32_t* active = (uint32_t*)(ws + P.off_active);
     uint32_t* ccnt = (uint32_t*)(ws + P.off_ccnt);
     uint32_t* unres = (uint32_t*)(ws + P.off_unres);
+    Control* ctl = (Control*)(ws + P.off_ctl);
     unsigned long long* cand = (unsigned long long*)(ws + P.off_cand);
     const int64_t ns = (int64_t)P.sample_tiles.size();
 
+    // per-query set-up on the device: user rows finite, status / activity, certificate eps
+    LAUNCH(launch_fill_u32((uint32_t*)ctl, 0u, (int64_t)(sizeof(Control) / 4), s));
+    PrepArgs pa{};
+    pa.user = batch->user_emb;
+    pa.n_queries = B;
+    pa.dim = ix.dim;
+    pa.kq = (const int32_t*)(ws + P.o_kq);
+    pa.aq = (const double*)(ws + P.o_aq);
+    pa.status = status;
+    pa.active = active;
+    pa.eps = approx ? (float*)(ws + P.off_eps) : nullptr;
+    const int cq = P.dtype == EBR_BF16 ? 0 : 1;
+    pa.q_err2 = ix.q_err2[cq];
+    pa.q_norm2 = ix.q_norm2[cq];
+    pa.e_norm2 = ix.e_norm2;
+    pa.ctl = ctl;
+    LAUNCH(launch_prep(pa, s));
+
     // sample pass and per-query threshold (for K' candidates on approximate scans)
     ScoreArgs sa = score_args(ix, P, batch, ws);
+    sa.ctl = ctl;
     sa.n_work = (int32_t)ns;
     sa.tile_list = (const uint32_t*)(ws + P.o_st);
     sa.sample_keys = (uint32_t*)(ws + P.off_skeys);
@@ -917,24 +907,17 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
     se.n_cols = sa.sample_ld;
     se.jq = (const int32_t*)(ws + P.o_jq);
     se.kq = (const int32_t*)(ws + P.o_kq);
+    se.kcnt = (const int32_t*)(ws + P.o_kc);
+    se.n_valid = P.n_sample_valid;
     se.status = status;
     se.only_status = -1;
     se.thresh = thr;
+    se.ctl = ctl;
     LAUNCH(launch_select(se, B, s));
     const int e_smp1 = clk.mark();
 
-    // per-query state: active iff K > 0
-    std::vector<uint32_t> act(B);
-    std::vector<int32_t> stat(B);
-    for (int q = 0; q < B; ++q) {
-        act[q] = P.kq[q] > 0 ? 1u : 0u;
-        stat[q] = P.kq[q] > 0 ? kStatusPending : kStatusDone;
-    }
-    HIP_TRY(hipMemcpyAsync(active, act.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(status, stat.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
-    if (approx) HIP_TRY(hipMemcpyAsync(ws + P.off_eps, eps.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
-
     ScoreArgs ca = score_args(ix, P, batch, ws);
+    ca.ctl = ctl;
     ca.thresh = thr;
     ca.active = active;
     ca.cand = cand;
@@ -942,6 +925,7 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
     ca.cand_cnt = ccnt;
     ca.cap = kCandCap;
     FinalArgs fa{};
+    fa.ctl = ctl;
     fa.active = active;
     fa.kq = (const int32_t*)(ws + P.o_kq);
     fa.kcnt = (const int32_t*)(ws + P.o_kc);
@@ -951,7 +935,6 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
     fa.cand_wide = ca.cand_wide;
     fa.status = status;
     fa.thresh = thr;
-    fa.unresolved = unres;
     fa.prep = approx ? 1 : 0;
     fa.out_off = (const int64_t*)(ws + P.o_oo);
     fa.out_ids = out_ids;
@@ -963,35 +946,55 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
         fa.r_ld = std::max(1, P.kcmax);
     }
 
-    // queries short of K' candidates fall back to the sample's K'-th key, which at least K'
-    // sample ads reach (or to no threshold when the sample holds fewer than K' ads)
-    std::vector<int32_t> jk(B);
-    for (int q = 0; q < B; ++q)
-        jk[q] = P.kcnt[q] <= P.n_sample_valid ? P.kcnt[q] : (int32_t)(P.n_sample_valid + 1);
-    // a query still short after that takes no threshold at all (every ad is a candidate;
-    // the overflow rule then narrows it)
-    std::vector<int32_t> jall(B, (int32_t)(P.n_sample_valid + 1));
+    // Selection rounds, enqueued without host synchronisation: round r > 0 runs only if round
+    // r - 1 left a query unresolved. Queries short of K' candidates first take the sample's
+    // K'-th key (which at least K' sample ads reach), then no threshold at all; overflowing
+    // queries take the K'-th largest stored key.
     std::vector<std::array<int, 3>> round_marks;
-    for (int round = 0;; ++round) {
-        if (round > 0) {
-            HIP_TRY(hipMemcpyAsync(ws + P.o_jq, (round == 1 ? jk : jall).data(), 4 * (size_t)B,
-                                   hipMemcpyHostToDevice, s));
+    for (int r = 0; r < kMaxRounds; ++r) {
+        const uint32_t* gate = r == 0 ? nullptr : &ctl->unres[r - 1];
+        if (r > 0) {
+            se.gate = gate;
+            se.round = r;
             se.only_status = kStatusNeedLower;
             LAUNCH(launch_select(se, B, s));
         }
-        LAUNCH(launch_fill_u32(ccnt, 0u, B, s));
-        LAUNCH(launch_fill_u32(unres, 0u, 1, s));
+        LAUNCH(launch_round_reset(ccnt, B, gate, s));
+        ca.gate = gate;
+        fa.gate = gate;
+        fa.unresolved = &ctl->unres[r];
         const int e0 = clk.mark();
         LAUNCH(launch_score(ca, ix.dim, 0, score_ctas(), s));
         const int e1 = clk.mark();
         LAUNCH(launch_finalize(fa, B, s));
         const int e2 = clk.mark();
+        round_marks.push_back({e0, e1, e2});
+    }
+    Control hc{};
+    HIP_TRY(hipMemcpyAsync(&hc, ctl, sizeof(Control), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hc.error & 1u) { set_error("non-finite user embedding in the batch"); return EBR_EINVAL; }
+    int rounds_run = 1;
+    for (int r = 0; r + 1 < kMaxRounds; ++r) rounds_run += hc.unres[r] > 0 ? 1 : 0;
+    // rare: still unresolved after the enqueued rounds; continue round by round
+    for (int r = kMaxRounds; hc.unres[kMaxRounds - 1] > 0; ++r) {
+        if (r >= 64) { set_error("top-K selection did not converge"); return EBR_EDEVICE; }
+        se.gate = nullptr;
+        se.round = 2;
+        se.only_status = kStatusNeedLower;
+        LAUNCH(launch_select(se, B, s));
+        LAUNCH(launch_round_reset(ccnt, B, nullptr, s));
+        ca.gate = nullptr;
+        fa.gate = nullptr;
+        LAUNCH(launch_fill_u32(unres, 0u, 1, s));
+        fa.unresolved = unres;
+        LAUNCH(launch_score(ca, ix.dim, 0, score_ctas(), s));
+        LAUNCH(launch_finalize(fa, B, s));
         uint32_t left = 0;
         HIP_TRY(hipMemcpyAsync(&left, unres, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        round_marks.push_back({e0, e1, e2});
-        if (left == 0) break;
-        if (round >= 64) { set_error("top-K selection did not converge"); return EBR_EDEVICE; }
+        ++rounds_run;
+        hc.unres[kMaxRounds - 1] = left;
     }
 
     int e_rs0 = -1, e_rs1 = -1;
@@ -1001,6 +1004,7 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
         uint32_t* unc = (uint32_t*)(ws + P.off_unc);
         LAUNCH(launch_fill_u32(unc, 0u, 1, s));
         RescoreArgs ra{};
+        ra.ctl = ctl;
         ra.emb = ix.emb_f32;
         ra.user = batch->user_emb;
         ra.n_ads = ix.n_ads;
@@ -1034,7 +1038,7 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
         }
         tm->score_first_ms = clk.ms(round_marks[0][0], round_marks[0][1]);
         tm->rescore_ms = clk.ms(e_rs0, e_rs1);
-        tm->rounds = (int32_t)round_marks.size();
+        tm->rounds = rounds_run;
         tm->uncertified = n_unc;
     }
     if (n_unc > 0) {

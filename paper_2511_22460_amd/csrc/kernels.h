@@ -13,6 +13,18 @@ constexpr int kStatusNeedLower = 2;
 constexpr int kStatusOverflow = 3;
 constexpr int kStatusUncertified = 4;
 
+// Threshold-revision rounds enqueued per batch without host synchronisation; a round whose
+// predecessor left no query unresolved exits at once.
+constexpr int kMaxRounds = 4;
+
+// Per-batch control block (device, in the workspace).
+struct Control {
+    uint32_t error;                   // bit 0: non-finite user row; bit 1: not converged
+    uint32_t unres[kMaxRounds];       // queries left unresolved by round r
+    uint32_t uncertified;             // reduced-precision scans: failed certificates
+    uint32_t pad[10];
+};
+
 struct DecodeArgs {
     const ChunkHdr* chunks;
     const uint32_t* words;
@@ -48,6 +60,7 @@ struct ScoreArgs {
     const uint32_t* users;            // pairs (query within group, m_fix)
     const double* qinv;               // 2^-S per query
     int32_t n_work;                   // tiles to visit
+    int32_t n_ranges;                 // contiguous tile ranges per query group (set at launch)
     const uint32_t* tile_list;        // null: tile = work index
     // collect mode
     const uint32_t* thresh;           // pairs (key hi, ~id lo) per query
@@ -62,6 +75,9 @@ struct ScoreArgs {
     // dense mode
     float* deep_out;
     float* wide_out;
+    // collect mode: run only if gate is null or *gate != 0, and never after an input error
+    const uint32_t* gate;
+    const Control* ctl;
 };
 
 struct SelectArgs {
@@ -73,6 +89,13 @@ struct SelectArgs {
     const int32_t* status;
     int32_t only_status;              // -1: every query with K > 0
     uint32_t* thresh;
+    // revision rounds: run only if gate is null or *gate != 0; round 1 takes the kcnt-th
+    // sample key (if the sample holds that many), later rounds no threshold at all
+    const uint32_t* gate;
+    int32_t round;
+    const int32_t* kcnt;
+    int64_t n_valid;
+    const Control* ctl;
 };
 
 struct FinalArgs {
@@ -90,6 +113,8 @@ struct FinalArgs {
     const int64_t* out_off;
     uint32_t* out_ids;
     float* out_scores;
+    const uint32_t* gate;             // run only if null or *gate != 0
+    const Control* ctl;               // nothing is written after an input error
     uint32_t* r_id;                   // prep: B x r_ld ids in approximate rank order
     float* r_wide;                    // prep: their cross-term values
     float* r_stilde;                  // prep: the K'-th approximate score per query
@@ -108,13 +133,32 @@ struct RescoreArgs {
     const float* r_wide;
     const float* r_stilde;
     const float* eps;                 // per query: bound on |approximate - exact| score
+    const Control* ctl;
     int32_t r_ld;
     const int64_t* out_off;
     uint32_t* out_ids;
     float* out_scores;
 };
 
+// Per-query set-up on the device: user rows must be finite (else ctl->error bit 0), status
+// and activity from K, and for reduced-precision scans the certificate's eps (see k_rescore).
+struct PrepArgs {
+    const float* user;
+    int32_t n_queries;
+    int32_t dim;
+    const int32_t* kq;
+    const double* aq;                 // per query: sum_j |m_j| max|W[k_j,:]|
+    int32_t* status;
+    uint32_t* active;
+    float* eps;                       // null for FP32 scans
+    double q_err2, q_norm2, e_norm2;  // the index's error summaries for the scanned copy
+    Control* ctl;
+};
+
 int launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, void* stream);
+int launch_prep(const PrepArgs& a, void* stream);
+// Zero the candidate counts of round `round` (skipped when the gate is zero).
+int launch_round_reset(uint32_t* cand_cnt, int32_t n, const uint32_t* gate, void* stream);
 int64_t scan_tmp_words(int64_t n);
 int launch_excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, void* stream);
 int launch_decode(const DecodeArgs& a, int place, void* stream);
@@ -124,6 +168,7 @@ int launch_decode_key(const ChunkHdr* chunks, const uint32_t* words, const float
 bool score_dim_supported(int dim);
 // Queries per query group of the scoring kernel for this embedding width.
 int score_group_queries(int dim);
+int score_ranges(int n_work, int n_qgroups, int ctas);
 int launch_score(const ScoreArgs& a, int dim, int mode, int ctas, void* stream);
 int launch_select(const SelectArgs& a, int n_queries, void* stream);
 int launch_finalize(const FinalArgs& a, int n_queries, void* stream);

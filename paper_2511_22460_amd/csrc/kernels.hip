@@ -473,10 +473,14 @@ template <int D, int DT> struct EmbStage {
     static constexpr int PER = (UNITS + 64 * kProducerWaves - 1) / (64 * kProducerWaves);
 };
 
-// Persistent over tiles blockIdx.x, blockIdx.x + gridDim.x, ...; iteration `it` has the
-// consumers score tile it from LDS buffers [it & 1] (and clear the accumulators they read)
-// while the producers fill buffers [(it + 1) & 1] with tile it + 1 and prefetch ahead. Every
-// wave executes exactly 2 + n_it barriers.
+// One work-group per (query group, contiguous range of tiles), persistent over its range;
+// iteration `it` has the consumers score tile it from LDS buffers [it & 1] (and clear the
+// accumulators they read) while the producers fill buffers [(it + 1) & 1] with tile it + 1
+// and prefetch ahead. Every wave executes exactly 2 + n_it barriers.
+//
+// Work-group ids are laid out for the 8 XCDs of the chip (consecutive ids go to consecutive
+// XCDs): all query groups of one tile range run on the same XCD, so the range's embedding
+// blocks and bucket entries are fetched from HBM once and then served by that XCD's L2.
 template <int D, int MODE, int DT>
 __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     constexpr int NQ = D / 8;
@@ -497,13 +501,25 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
 
     const int tid = (int)threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const bool producer = wave >= CW;
-    const int g = (int)blockIdx.y;
+    int g, range;
+    {
+        const int p = (int)blockIdx.x, R = a.n_ranges, nqg = a.n_qgroups;
+        if (R % 8 == 0) {  // XCD-aware: range r lives on XCD r % 8 with all its query groups
+            const int x = p & 7, sl = p >> 3;
+            range = x + 8 * (sl / nqg);
+            g = sl % nqg;
+        } else {
+            range = p % R;
+            g = p / R;
+        }
+    }
+    if (a.gate && *a.gate == 0u) return;
+    if (a.ctl && a.ctl->error) return;
     const int qbase = g * GQ;
     const int B = a.n_queries;
-    const int G = (int)gridDim.x;
-    const int first = (int)blockIdx.x;
-    if (first >= a.n_work) return;
-    const int n_it = (a.n_work - first + G - 1) / G;
+    const int first = (int)(((int64_t)a.n_work * range) / a.n_ranges);
+    const int n_it = (int)(((int64_t)a.n_work * (range + 1)) / a.n_ranges) - first;
+    if (n_it <= 0) return;
 
     for (int i = tid; i < 2 * GQ * kTileAds; i += NT) (&s_acc[0][0])[i] = 0ull;
     for (int i = tid; i < GQ; i += NT) {
@@ -522,7 +538,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         }
     }
     auto tile_at = [&](int i) -> uint32_t {
-        const int w = first + i * G;
+        const int w = first + i;
         return a.tile_list ? a.tile_list[w] : (uint32_t)w;
     };
     __syncthreads();
@@ -679,7 +695,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         bool pass = false;
         // sample pass: row base of this wave's block plus a 32-bit offset per row
         uint32_t* skeys = MODE == 1 ? a.sample_keys + (int64_t)q0 * a.sample_ld : nullptr;
-        const uint32_t scol = (uint32_t)(first + it * G) * kTileAds + (uint32_t)o;
+        const uint32_t scol = (uint32_t)(first + it) * kTileAds + (uint32_t)o;
 #pragma unroll
         for (int g4 = 0; g4 < 4; ++g4) {
             const int r0 = rg(g4);
@@ -737,9 +753,13 @@ __global__ __launch_bounds__(1024) void k_select(SelectArgs a) {
     __shared__ uint32_t s_res[2];
     const int q = (int)blockIdx.x;
     const int tid = (int)threadIdx.x;
+    if (a.gate && *a.gate == 0u) return;
+    if (a.ctl && a.ctl->error) return;
     if (a.only_status >= 0 && a.status[q] != a.only_status) return;
     if (a.kq[q] <= 0) return;
-    const int64_t j = a.jq[q];
+    int64_t j = a.jq[q];
+    if (a.round == 1) j = a.kcnt[q] <= a.n_valid ? a.kcnt[q] : a.n_valid + 1;
+    else if (a.round >= 2) j = a.n_valid + 1;
     if (j > a.n_cols || j <= 0) {
         if (tid == 0) { a.thresh[2 * q] = 0u; a.thresh[2 * q + 1] = 0u; }
         return;
@@ -791,6 +811,8 @@ __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
     __shared__ unsigned long long s[kCandCap];
     const int q = (int)blockIdx.x;
     const int tid = (int)threadIdx.x;
+    if (a.gate && *a.gate == 0u) return;
+    if (a.ctl && a.ctl->error) return;
     if (!a.active[q]) return;
     const int Kc = a.kcnt[q];
     const uint32_t c = a.cand_cnt[q];
@@ -874,6 +896,7 @@ __global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
     const int q = (int)blockIdx.x;
     const int tid = (int)threadIdx.x;
     const int K = a.kq[q];
+    if (a.ctl && a.ctl->error) return;
     if (K <= 0 || a.status[q] != kStatusDone) return;
     const int Kc = a.kcnt[q];
     for (int i = tid; i < D; i += 1024) s_u[i] = a.user[(int64_t)q * D + i];
@@ -938,6 +961,61 @@ __global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
     }
 }
 
+// ------------------------------------------------------------------ per-query set-up
+
+// One wavefront per query: finiteness of the user row, status / activity from K, and the
+// certificate's eps for reduced-precision scans: with u the FP32 row and u^ its BF16 copy,
+//   eps = |u^ - u| Eh + |u| R + g_d (|u^| Eh + |u| E) + 2^-24 |u^| Eh
+//         + 2^-22 (max(|u| E, |u^| Eh) + A_q),
+// where R, Eh, E are the largest row norms of (e - e^), e^ and e, g_d = 1.01 d 2^-24 bounds
+// FP32 accumulation of d products, the 2^-24 term the FP8 scale product and the last term
+// the FP32 additions of the cross term (|cross term| <= A_q); everything is rounded up.
+__global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
+    const int q = (int)(blockIdx.x * 4u + (threadIdx.x >> 6));
+    const int lane = lane_id();
+    if (q >= a.n_queries) return;
+    const float* u = a.user + (int64_t)q * a.dim;
+    bool finite = true;
+    double nu = 0.0, nh = 0.0, du = 0.0;
+    for (int k = lane; k < a.dim; k += 64) {
+        const float x = u[k];
+        finite &= isfinite(x);
+        const double xd = (double)x;
+        const double h = (double)__uint_as_float(bf16_bits(x) << 16);
+        nu += xd * xd;
+        nh += h * h;
+        du += (h - xd) * (h - xd);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        nu += __shfl_xor(nu, off, 64);
+        nh += __shfl_xor(nh, off, 64);
+        du += __shfl_xor(du, off, 64);
+    }
+    const uint64_t bad = __ballot(!finite);
+    if (lane == 0) {
+        if (bad) atomicOr(&a.ctl->error, 1u);
+        const int K = a.kq[q];
+        a.status[q] = K > 0 ? kStatusPending : kStatusDone;
+        a.active[q] = K > 0 ? 1u : 0u;
+        if (a.eps) {
+            nu = sqrt(nu);
+            nh = sqrt(nh);
+            du = sqrt(du);
+            const double gd = 1.01 * a.dim * 0x1p-24;
+            double e = du * a.q_norm2 + nu * a.q_err2 + gd * (nh * a.q_norm2 + nu * a.e_norm2) +
+                       0x1p-24 * nh * a.q_norm2 + 0x1p-22 * (fmax(nu * a.e_norm2, nh * a.q_norm2) + a.aq[q]);
+            e = e * 1.001 + 1e-30;
+            a.eps[q] = __double2float_ru(e);
+        }
+    }
+}
+
+__global__ void k_round_reset(uint32_t* cand_cnt, int32_t n, const uint32_t* gate) {
+    if (gate && *gate == 0u) return;
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += (int)(gridDim.x * blockDim.x))
+        cand_cnt[i] = 0u;
+}
+
 // ------------------------------------------------------------------ launchers
 
 static int last(hipError_t e) { return e == hipSuccess ? (int)hipGetLastError() : (int)e; }
@@ -947,6 +1025,19 @@ int launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, void* stream) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, p, v, n);
+    return last(hipSuccess);
+}
+
+int launch_prep(const PrepArgs& a, void* stream) {
+    if (a.n_queries <= 0) return 0;
+    hipLaunchKernelGGL(k_prep, dim3((unsigned)((a.n_queries + 3) / 4)), dim3(256), 0, (hipStream_t)stream, a);
+    return last(hipSuccess);
+}
+
+int launch_round_reset(uint32_t* cand_cnt, int32_t n, const uint32_t* gate, void* stream) {
+    if (n <= 0) return 0;
+    const int blocks = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
+    hipLaunchKernelGGL(k_round_reset, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, cand_cnt, n, gate);
     return last(hipSuccess);
 }
 
@@ -1008,10 +1099,19 @@ bool score_dim_supported(int dim) {
     }
 }
 
-int launch_score(const ScoreArgs& a, int dim, int mode, int ctas, void* stream) {
-    if (a.n_work <= 0 || a.n_qgroups <= 0) return 0;
-    const int c = a.n_work < ctas ? a.n_work : ctas;
-    dim3 grid((unsigned)c, (unsigned)a.n_qgroups);
+int score_ranges(int n_work, int n_qgroups, int ctas) {
+    int R = ctas / (n_qgroups > 0 ? n_qgroups : 1);
+    if (R >= 8) R -= R % 8;
+    if (R < 1) R = 1;
+    if (R > n_work) R = n_work;
+    return R;
+}
+
+int launch_score(const ScoreArgs& a_in, int dim, int mode, int ctas, void* stream) {
+    if (a_in.n_work <= 0 || a_in.n_qgroups <= 0) return 0;
+    ScoreArgs a = a_in;
+    a.n_ranges = score_ranges(a.n_work, a.n_qgroups, ctas);
+    dim3 grid((unsigned)(a.n_ranges * a.n_qgroups));
     hipStream_t st = (hipStream_t)stream;
     const int dt = a.dtype;
     switch (dim) {
