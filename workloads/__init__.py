@@ -220,6 +220,28 @@ def draw_keys(spec, n_keys: int, counts: np.ndarray, rng: np.random.Generator):
     return out
 
 
+def queries_for(wl: Workload, name: str, **over) -> Workload:
+    """A new query batch drawn with recipe `name` (its query fields: n_queries, feats,
+    key_draw, k, seed) on the index of an existing workload."""
+    spec = dict(CONFIGS[name])
+    spec.update(over)
+    seed = int(spec.get("seed", BASE_SEED + spec["cfg"]))
+    ss = np.random.SeedSequence(seed)
+    _, rng_q, rng_k = [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(3)]
+    B = int(spec["n_queries"])
+    U = normal_rows(seed, 2, B, wl.dim)
+    counts = _draw_count(spec["feats"], rng_q, B)
+    keys = draw_keys(spec["key_draw"], wl.n_keys, counts, rng_q)
+    offs = np.zeros(B + 1, dtype=np.int64)
+    np.cumsum([len(x) for x in keys], out=offs[1:])
+    fk = np.concatenate(keys).astype(np.int32) if B else np.zeros(0, np.int32)
+    kq = np.minimum(_draw_count(spec["k"], rng_k, B), wl.n_ads).astype(np.int32)
+    recipe = dict(wl.recipe)
+    recipe.update({"queries": name, "query_seed": seed, **{k: spec[k] for k in ("n_queries", "feats", "k")}})
+    return Workload(wl.name + "+" + name, wl.n_ads, wl.dim, wl.n_keys, wl.ad_emb, wl.key_offsets,
+                    wl.post_ids, wl.post_w, U, offs, fk, None, kq, recipe)
+
+
 def make(name: str = "c1", **over) -> Workload:
     """Build a workload from a named recipe, with optional overrides of any recipe field.
 
