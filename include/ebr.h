@@ -211,6 +211,113 @@ typedef struct {
 ebr_status ebr_set_timing(int enable);
 ebr_status ebr_get_timings(ebr_timings* out);
 
+/* ------------------------------------------------------------------------ serving */
+
+/*
+ * Serving loop over a resident index. Retrieval answers user requests one at a
+ * time under throughput and latency demands (Section 2 on the retrieval stage;
+ * Section 4.1 takes maximum QPS as an efficiency metric; Section 4.4 runs the
+ * operator online over millions of ads); the GPU is efficient only on batches. A server accepts single queries from any thread (ebr_submit), groups
+ * whatever has arrived into batches under a scratch budget, and keeps up to
+ * `pipeline` batches in flight on as many HIP streams, so that queries arriving
+ * while a batch runs are admitted into the next one without waiting for it
+ * (continuous batching at batch granularity). Every batch runs the same path
+ * as ebr_score_topk, so a query's results are bit-identical whatever batch it
+ * lands in.
+ *
+ * Scratch: a caller-owned device arena of scratch_bytes (256-byte aligned),
+ * split evenly between the pipeline slots. A slot holds one batch's user rows,
+ * outputs and workspace; a batch admits queued queries first-in first-out
+ * while the workspace of the batch so far (computed exactly from its sizes:
+ * distinct keys, their postings, queries, K) fits the slot.
+ * The library allocates pinned host staging (hipHostMalloc) and streams at
+ * create and frees them at destroy; it allocates no device memory.
+ */
+typedef struct ebr_server ebr_server; /* opaque */
+
+/*
+ *  max_batch     queries per batch, 1..4096 (0: 256)
+ *  max_wait_us   how long the oldest queued query may wait for a fuller batch
+ *                before its batch is launched (0: launch at once with what is
+ *                queued; < 0: 0)
+ *  pipeline      batches in flight, 1..4 (0: 2)
+ *  scan_dtype, rescore_factor   as in ebr_batch, for every query
+ */
+typedef struct {
+    int32_t max_batch;
+    int32_t max_wait_us;
+    int32_t pipeline;
+    ebr_dtype scan_dtype;
+    int32_t rescore_factor;
+} ebr_server_opts;
+
+/*
+ * One query, all host memory, copied by ebr_submit:
+ *  user_emb   d FP32 values (finite)
+ *  n_feats    number of features (>= 0)
+ *  feat_keys  n_feats distinct keys < n_keys
+ *  feat_mult  n_feats finite multipliers, or NULL (all 1)
+ *  k          0 <= k <= min(n_ads, 8192 / f), f = 1 for F32, else the rescore factor
+ */
+typedef struct {
+    const float* user_emb;
+    int32_t n_feats;
+    const int32_t* feat_keys;
+    const float* feat_mult;
+    int32_t k;
+} ebr_query;
+
+/*
+ * Latency is per query, from ebr_submit to the moment its results are written
+ * to the caller's buffers (host steady clock); percentiles over every query
+ * completed since create or the last ebr_server_reset_stats.
+ *  submitted, completed, failed   query counts; queued: waiting for a batch now
+ *  batches        batches launched; mean_batch: queries per batch
+ *  p50_ms, p99_ms, max_ms, mean_ms   latency
+ *  elapsed_ms     wall time since create or reset; qps = completed / elapsed
+ *  busy_ms        summed wall time of batches in flight (over slots)
+ */
+typedef struct {
+    uint64_t submitted, completed, failed, queued, batches;
+    double mean_batch, p50_ms, p99_ms, max_ms, mean_ms, elapsed_ms, qps, busy_ms;
+} ebr_server_info;
+
+/*
+ * Start a server on the device current at the call (it must be the index's).
+ * EBR_ENOMEM if one slot cannot hold a batch of one query with K = 1;
+ * EBR_EUNSUPPORTED if the index holds no copy of scan_dtype.
+ */
+ebr_status ebr_server_create(const ebr_index* index, void* scratch, size_t scratch_bytes,
+                             const ebr_server_opts* opts, ebr_server** out);
+
+/*
+ * Queue one query. ids_out (uint32) and scores_out (FP32) are host arrays of
+ * q->k entries that must stay valid until ebr_poll reports the ticket done;
+ * they are written in (score descending, id ascending) order. *ticket
+ * identifies the query for ebr_poll. Thread-safe.
+ * EBR_EINVAL for an invalid query; EBR_ENOMEM if the query alone does not fit
+ * a slot; EBR_ESHUTDOWN once destroy has begun.
+ */
+ebr_status ebr_submit(ebr_server* server, const ebr_query* q, uint32_t* ids_out,
+                      float* scores_out, uint64_t* ticket);
+
+/*
+ * Wait up to timeout_us (< 0: without limit, 0: just look) for a ticket.
+ * EBR_OK: results written, the ticket is retired. EBR_EAGAIN: not done yet.
+ * A failed batch reports its error (the ticket is retired).
+ * EBR_ENOTFOUND: unknown or already retired ticket. Thread-safe.
+ */
+ebr_status ebr_poll(ebr_server* server, uint64_t ticket, int32_t timeout_us);
+
+ebr_status ebr_server_stats(ebr_server* server, ebr_server_info* out);
+ebr_status ebr_server_reset_stats(ebr_server* server);
+
+/*
+ * Stop accepting queries, finish every queued and running one, release the
+ * server's host resources. Results of tickets never polled are still written.
+ */
+ebr_status ebr_server_destroy(ebr_server* server);
+
 /* ------------------------------------------------------------------------ codec */
 
 /*

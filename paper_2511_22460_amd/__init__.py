@@ -28,7 +28,8 @@ EXPORTS = ("ebr_index_size", "ebr_build_index", "ebr_index_stats", "ebr_decode_k
            "ebr_free_index", "ebr_workspace_size", "ebr_score_topk", "ebr_score_dense",
            "ebr_codec_size", "ebr_codec_encode", "ebr_codec_decode", "ebr_last_error",
            "ebr_version", "ebr_set_timing", "ebr_get_timings", "ebr_quantize_bf16",
-           "ebr_quantize_fp8", "ebr_dequantize_fp8")
+           "ebr_quantize_fp8", "ebr_dequantize_fp8", "ebr_server_create", "ebr_submit",
+           "ebr_poll", "ebr_server_stats", "ebr_server_reset_stats", "ebr_server_destroy")
 
 
 class EbrError(RuntimeError):
@@ -88,6 +89,31 @@ class Batch(ctypes.Structure):
                 ("scan_dtype", ctypes.c_int), ("rescore_factor", ctypes.c_int32)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("max_wait_us", ctypes.c_int32),
+                ("pipeline", ctypes.c_int32), ("scan_dtype", ctypes.c_int),
+                ("rescore_factor", ctypes.c_int32)]
+
+
+class Query(ctypes.Structure):
+    _fields_ = [("user_emb", ctypes.c_void_p), ("n_feats", ctypes.c_int32),
+                ("feat_keys", ctypes.c_void_p), ("feat_mult", ctypes.c_void_p),
+                ("k", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("queued", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("mean_batch", ctypes.c_double),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("elapsed_ms", ctypes.c_double), ("qps", ctypes.c_double),
+                ("busy_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 def lib_path() -> str:
     return _build.LIB
 
@@ -125,6 +151,12 @@ def load():
         "ebr_quantize_fp8": ([P, i64, ctypes.c_float, P], st),
         "ebr_dequantize_fp8": ([P, i64, P], st),
         "ebr_get_timings": ([P], st),
+        "ebr_server_create": ([P, P, sz, P, ctypes.POINTER(P)], st),
+        "ebr_submit": ([P, P, P, P, ctypes.POINTER(ctypes.c_uint64)], st),
+        "ebr_poll": ([P, ctypes.c_uint64, i32], st),
+        "ebr_server_stats": ([P, P], st),
+        "ebr_server_reset_stats": ([P], st),
+        "ebr_server_destroy": ([P], st),
     }
     for name, (args, res) in sig.items():
         f = getattr(h, name)
@@ -366,3 +398,76 @@ class Index:
         w = wl if qs is None else wl.subset(qs)
         U = torch.from_numpy(np.ascontiguousarray(w.user_emb)).to(self.device)
         return self.score_topk(U, w.feat_offsets, w.feat_keys, w.k, w.feat_mult, **kw)
+
+
+class Server:
+    """Serving loop over a resident Index (ebr_server_*): submit single queries from host
+    memory, poll for their results. The scratch arena is a torch-owned device buffer."""
+
+    def __init__(self, index: "Index", scratch_bytes: int, max_batch: int = 256,
+                 max_wait_us: int = 200, pipeline: int = 2, scan_dtype: int = F32,
+                 rescore_factor: int = 4):
+        import torch
+        self.index = index
+        self.scratch = torch.empty(max(256, int(scratch_bytes)), dtype=torch.uint8, device=index.device)
+        opts = ServerOpts(max_batch, max_wait_us, pipeline, scan_dtype, rescore_factor)
+        h = ctypes.c_void_p()
+        _check(load().ebr_server_create(index._h, self.scratch.data_ptr(), self.scratch.numel(),
+                                        ctypes.byref(opts), ctypes.byref(h)), "ebr_server_create")
+        self._h = h
+        self._pending = {}
+
+    def submit(self, user_emb, feat_keys, k: int, feat_mult=None) -> int:
+        """Queue one query (host arrays); returns its ticket."""
+        u = _np(user_emb, np.float32)
+        keys = _np(feat_keys, np.int32)
+        mult = _np(feat_mult, np.float32)
+        if u.shape != (self.index.dim,):
+            raise ValueError(f"user_emb must have {self.index.dim} entries")
+        if mult is not None and len(mult) != len(keys):
+            raise ValueError("feat_mult must match feat_keys")
+        ids = np.empty(max(1, k), dtype=np.uint32)
+        sc = np.empty(max(1, k), dtype=np.float32)
+        q = Query(_ptr(u), len(keys), _ptr(keys) if len(keys) else None,
+                  _ptr(mult) if mult is not None and len(mult) else None, int(k))
+        t = ctypes.c_uint64()
+        _check(load().ebr_submit(self._h, ctypes.byref(q), _ptr(ids), _ptr(sc), ctypes.byref(t)),
+               "ebr_submit")
+        self._pending[t.value] = (ids, sc, int(k))
+        return t.value
+
+    def poll(self, ticket: int, timeout_us: int = -1):
+        """(ids, scores) once the ticket is done, None if not done within timeout_us."""
+        rc = load().ebr_poll(self._h, ticket, int(timeout_us))
+        if rc == EBR_EAGAIN:
+            return None
+        ids, sc, k = self._pending.pop(ticket, (None, None, 0))
+        _check(rc, "ebr_poll")
+        return ids[:k], sc[:k]
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().ebr_server_stats(self._h, ctypes.byref(st)), "ebr_server_stats")
+        return st.as_dict()
+
+    def reset_stats(self):
+        _check(load().ebr_server_reset_stats(self._h), "ebr_server_reset_stats")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            rc = load().ebr_server_destroy(self._h)
+            self._h = None
+            self._pending.clear()
+            _check(rc, "ebr_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libebr.so")
-SOURCES = ["api.cpp", "codec.cpp", "quant.cpp", "kernels.hip"]
+SOURCES = ["api.cpp", "codec.cpp", "quant.cpp", "server.cpp", "kernels.hip"]
 ARCH = "gfx950"
 
 

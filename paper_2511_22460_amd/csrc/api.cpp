@@ -19,8 +19,6 @@
 #include "internal.h"
 #include "kernels.h"
 
-struct ebr_index : ebr::Index {};
-
 namespace ebr {
 
 // ------------------------------------------------------------------ errors
@@ -520,6 +518,70 @@ struct Plan {
     size_t total = 0;
 };
 
+// Sample tiles of the threshold pre-pass: at least n_tiles / 64 tiles and 16 K' ads.
+static int64_t sample_tile_count(const Index& ix, int kcmax) {
+    const int64_t nt = ix.n_tiles;
+    const int64_t ns = std::max<int64_t>((nt + 63) / 64, (16LL * kcmax + kTileAds - 1) / kTileAds);
+    return std::min(ns, nt);
+}
+
+// Workspace sections of one batch; depends only on the batch's sizes.
+static void layout(const Index& ix, bool topk, const BatchSizes& z, Plan* P) {
+    const int B = z.B;
+    const int nu = z.nu;
+    const int nqg = std::max(1, (B + P->gq - 1) / P->gq);
+    const size_t n_users_off = (size_t)nu * nqg + 1, n_users = 2 * (size_t)std::max<int64_t>(1, z.nnz);
+    P->bucket_n = z.bucket_n;
+    size_t off = 0;
+    auto put = [&](size_t bytes) { size_t o = off; off = align256(off + std::max<size_t>(bytes, 4)); return o; };
+    P->off_plan = off;
+    P->o_ukb = put(4 * (size_t)nu);
+    P->o_ukp = put(4 * (size_t)(nu + 1));
+    P->o_ukw = put(4 * (size_t)nu);
+    P->o_uoff = put(4 * n_users_off);
+    P->o_users = put(4 * n_users);
+    P->o_qi = put(8 * (size_t)B);
+    P->o_kq = put(4 * (size_t)B);
+    P->o_jq = put(4 * (size_t)B);
+    P->o_kc = put(4 * (size_t)B);
+    P->o_aq = put(8 * (size_t)B);
+    P->o_oo = put(8 * (size_t)(B + 1));
+    P->o_st = put(4 * (size_t)z.n_sample);
+    P->plan_bytes = off - P->off_plan;
+    P->n_super = (ix.n_ads + kSuperAds - 1) / kSuperAds;
+    P->off_stcnt = put(4 * (size_t)(P->n_super + 1));
+    P->off_stoff = put(4 * (size_t)(P->n_super + 1));
+    P->off_stfill = put(4 * (size_t)(P->n_super + 1));
+    P->off_stmp = put(4 * (size_t)scan_tmp_words(P->n_super + 1));
+    P->off_stage = put(8 * (size_t)P->bucket_n);
+    P->off_toff = put(4 * (size_t)(ix.n_tiles + 1));
+    P->off_bucket = put(8 * (size_t)P->bucket_n);
+    if (topk) {
+        P->off_skeys = put(4 * (size_t)B * (size_t)z.n_sample * kTileAds);
+        P->off_thr = put(8 * (size_t)B);
+        P->off_status = put(4 * (size_t)B);
+        P->off_active = put(4 * (size_t)B);
+        P->off_ccnt = put(4 * (size_t)B);
+        P->off_unres = put(16);
+        P->off_ctl = put(sizeof(Control));
+        P->off_cand = put(8 * (size_t)B * kCandCap);
+        if (P->dtype != EBR_F32) {
+            // everything below the fallback region is enough for an FP32 run of any subset
+            P->fb_limit = off;
+            P->off_cwide = put(4 * (size_t)B * kCandCap);
+            P->off_rid = put(4 * (size_t)B * std::max(1, z.kcmax));
+            P->off_rwide = put(4 * (size_t)B * std::max(1, z.kcmax));
+            P->off_rst = put(4 * (size_t)B);
+            P->off_eps = put(4 * (size_t)B);
+            P->off_unc = put(16);
+            P->off_fb_users = put(4 * (size_t)B * ix.dim);
+            P->off_fb_ids = put(4 * (size_t)std::max<int64_t>(1, z.n_out));
+            P->off_fb_scores = put(4 * (size_t)std::max<int64_t>(1, z.n_out));
+        }
+    }
+    P->total = off;
+}
+
 static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Plan* P) {
     if (!bt) { set_error("batch is NULL"); return EBR_EINVAL; }
     const int B = bt->n_queries;
@@ -666,8 +728,7 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     P->sample_tiles.clear();
     if (topk && P->kmax > 0) {
         const int64_t nt = ix.n_tiles;
-        int64_t ns = std::max<int64_t>((nt + 63) / 64, (16LL * P->kcmax + kTileAds - 1) / kTileAds);
-        ns = std::min(ns, nt);
+        const int64_t ns = sample_tile_count(ix, P->kcmax);
         P->sample_tiles.resize(ns);
         int64_t valid = 0;
         for (int64_t i = 0; i < ns; ++i) {
@@ -686,55 +747,15 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
             P->jq[q] = (int32_t)std::min<int64_t>(j, valid);
         }
     }
-    // workspace layout
-    size_t off = 0;
-    auto put = [&](size_t bytes) { size_t o = off; off = align256(off + std::max<size_t>(bytes, 4)); return o; };
-    P->off_plan = off;
-    P->o_ukb = put(4 * (size_t)nu);
-    P->o_ukp = put(4 * (size_t)(nu + 1));
-    P->o_ukw = put(4 * (size_t)nu);
-    P->o_uoff = put(4 * P->users_off.size());
-    P->o_users = put(4 * P->users.size());
-    P->o_qi = put(8 * (size_t)B);
-    P->o_kq = put(4 * (size_t)B);
-    P->o_jq = put(4 * (size_t)B);
-    P->o_kc = put(4 * (size_t)B);
-    P->o_aq = put(8 * (size_t)B);
-    P->o_oo = put(8 * (size_t)(B + 1));
-    P->o_st = put(4 * P->sample_tiles.size());
-    P->plan_bytes = off - P->off_plan;
-    P->n_super = (ix.n_ads + kSuperAds - 1) / kSuperAds;
-    P->off_stcnt = put(4 * (size_t)(P->n_super + 1));
-    P->off_stoff = put(4 * (size_t)(P->n_super + 1));
-    P->off_stfill = put(4 * (size_t)(P->n_super + 1));
-    P->off_stmp = put(4 * (size_t)scan_tmp_words(P->n_super + 1));
-    P->off_stage = put(8 * (size_t)P->bucket_n);
-    P->off_toff = put(4 * (size_t)(ix.n_tiles + 1));
-    P->off_bucket = put(8 * (size_t)P->bucket_n);
-    if (topk) {
-        P->off_skeys = put(4 * (size_t)B * P->sample_tiles.size() * kTileAds);
-        P->off_thr = put(8 * (size_t)B);
-        P->off_status = put(4 * (size_t)B);
-        P->off_active = put(4 * (size_t)B);
-        P->off_ccnt = put(4 * (size_t)B);
-        P->off_unres = put(16);
-        P->off_ctl = put(sizeof(Control));
-        P->off_cand = put(8 * (size_t)B * kCandCap);
-        if (P->dtype != EBR_F32) {
-            // everything below the fallback region is enough for an FP32 run of any subset
-            P->fb_limit = off;
-            P->off_cwide = put(4 * (size_t)B * kCandCap);
-            P->off_rid = put(4 * (size_t)B * std::max(1, P->kcmax));
-            P->off_rwide = put(4 * (size_t)B * std::max(1, P->kcmax));
-            P->off_rst = put(4 * (size_t)B);
-            P->off_eps = put(4 * (size_t)B);
-            P->off_unc = put(16);
-            P->off_fb_users = put(4 * (size_t)B * ix.dim);
-            P->off_fb_ids = put(4 * (size_t)std::max<int64_t>(1, P->out_off.empty() ? 0 : P->out_off[B]));
-            P->off_fb_scores = put(4 * (size_t)std::max<int64_t>(1, P->out_off.empty() ? 0 : P->out_off[B]));
-        }
-    }
-    P->total = off;
+    BatchSizes z;
+    z.B = B;
+    z.nnz = nnz;
+    z.nu = nu;
+    z.bucket_n = P->bucket_n;
+    z.kcmax = P->kcmax;
+    z.n_out = P->out_off[B];
+    z.n_sample = (int64_t)P->sample_tiles.size();
+    layout(ix, topk, z, P);
     return EBR_OK;
 }
 
@@ -757,14 +778,16 @@ static std::vector<char> pack_plan(const Plan& P) {
 }
 
 static int score_ctas() {
-    static int ctas = 0;
-    if (ctas == 0) {
+    static std::atomic<int> ctas{0};
+    int c = ctas.load(std::memory_order_relaxed);
+    if (c == 0) {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-        ctas = cus;  // one scoring work-group per compute unit (it holds ~150 KiB of LDS)
+        c = cus;  // one scoring work-group per compute unit (it holds ~150 KiB of LDS)
+        ctas.store(c, std::memory_order_relaxed);
     }
-    return ctas;
+    return c;
 }
 
 #define LAUNCH(expr)                                                                       \
@@ -1089,6 +1112,20 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
         HIP_TRY(hipStreamSynchronize(s));
     }
     return EBR_OK;
+}
+
+ebr_status run_topk(const Index& ix, const ebr_batch* batch, char* ws, size_t ws_bytes,
+                    uint32_t* out_ids, float* out_scores, void* stream, ebr_timings* tm) {
+    return topk_impl(ix, batch, ws, ws_bytes, out_ids, out_scores, (hipStream_t)stream, tm);
+}
+
+size_t topk_workspace_bytes(const Index& ix, int dtype, BatchSizes z) {
+    Plan P;
+    P.dtype = dtype;
+    P.gq = score_group_queries(ix.dim);
+    z.n_sample = z.n_out > 0 ? sample_tile_count(ix, z.kcmax) : 0;
+    layout(ix, true, z, &P);
+    return P.total;
 }
 
 }  // namespace ebr

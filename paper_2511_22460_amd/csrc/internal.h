@@ -115,4 +115,27 @@ struct ScoreArgs;
 int launch_swizzle_f32(const float* src_rows, int64_t n_rows, int64_t row0, int32_t dim,
                        void* dst, void* stream);
 
+// ---------------------------------------------------------------- batches (api.cpp)
+
+// The sizes a top-K batch's workspace depends on.
+struct BatchSizes {
+    int B = 0;
+    int64_t nnz = 0;        // (query, feature) pairs
+    int nu = 0;             // distinct keys
+    uint64_t bucket_n = 0;  // postings of the distinct keys
+    int kcmax = 0;          // largest K' (K, or the rescore factor times K) of the batch
+    int64_t n_out = 0;      // sum of K
+    int64_t n_sample = 0;   // sample tiles (derived; ignored by topk_workspace_bytes)
+};
+
+// Exact workspace bytes of a top-K batch of these sizes on scan dtype `dtype`.
+size_t topk_workspace_bytes(const Index& ix, int dtype, BatchSizes z);
+
+// ebr_score_topk without the entry point's bookkeeping; stream is a hipStream_t.
+ebr_status run_topk(const Index& ix, const ebr_batch* batch, char* ws, size_t ws_bytes,
+                    uint32_t* out_ids, float* out_scores, void* stream, ebr_timings* tm);
+
 }  // namespace ebr
+
+// The C-ABI handle is the index itself.
+struct ebr_index : ebr::Index {};

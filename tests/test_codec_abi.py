@@ -141,3 +141,18 @@ def test_reduced_precision_copies_grow_the_arena():
     with pytest.raises(E.EbrError) as ei:
         E.index_size(E_, offs, ids, w, dtypes=1 << 5)
     assert ei.value.status == E.EBR_EINVAL
+
+
+def test_server_entry_points_reject_null_handles():
+    lib = E.load()
+    import ctypes
+    opts = E.ServerOpts(0, 0, 0, 0, 0)
+    h = ctypes.c_void_p()
+    assert lib.ebr_server_create(None, None, 0, ctypes.byref(opts), ctypes.byref(h)) == E.EBR_EINVAL
+    t = ctypes.c_uint64()
+    assert lib.ebr_submit(None, None, None, None, ctypes.byref(t)) == E.EBR_EINVAL
+    assert lib.ebr_poll(None, 1, 0) == E.EBR_EINVAL
+    assert lib.ebr_server_stats(None, None) == E.EBR_EINVAL
+    assert lib.ebr_server_reset_stats(None) == E.EBR_EINVAL
+    assert lib.ebr_server_destroy(None) == E.EBR_EINVAL
+    assert "NULL" in lib.ebr_last_error().decode()

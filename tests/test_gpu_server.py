@@ -1,0 +1,164 @@
+"""GPU tests of the serving loop (ebr_server_*): single queries submitted from host memory,
+batched on the device under a scratch budget, results polled back.
+
+Every served result is checked against the FP64 oracle (parity.py rules) and must be
+bit-identical to the same query run alone through ebr_score_topk: the cross term is an
+exact fixed-point sum and the dot product's order does not depend on the batch, so a
+query's scores do not depend on which queries share its batch.
+"""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import check_topk
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+E = pytest.importorskip("paper_2511_22460_amd")
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def served():
+    dev()
+    wl = W.make("c1", n_ads=40_009, dim=64, n_keys=800, lengths=("zipf_draw", 1.2, 5, 8000),
+                n_queries=96, feats=(0, 40), key_draw=("uniform",), k=(0, 400))
+    ix = E.Index.from_workload(wl, dtypes=1 | (1 << E.BF16))
+    return wl, ix
+
+
+def alone(ix, wl, q, **kw):
+    ids, sc, _ = ix.topk_workload(wl, qs=[q], **kw)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy().view(np.uint32), sc.cpu().numpy()
+
+
+def submit_all(srv, wl, qs):
+    return {q: srv.submit(wl.user_emb[q], wl.query_keys(q), int(wl.k[q]),
+                          None if wl.feat_mult is None else wl.query_mults(q)) for q in qs}
+
+
+def check_served(wl, ix, results, kw=None, oracle_qs=None):
+    oix = oracle.Index.of(wl)
+    for q, (ids, sc) in results.items():
+        a_ids, a_sc = alone(ix, wl, q, **(kw or {}))
+        assert np.array_equal(ids, a_ids), f"query {q}: served ids differ from the query alone"
+        assert np.array_equal(sc.view(np.uint32), a_sc.view(np.uint32)), f"query {q}: scores differ"
+        if oracle_qs is None or q in oracle_qs:
+            d, w, _ = oracle.scores(oix, wl.user_emb[q], wl.query_keys(q))
+            assert check_topk(ids, sc, int(wl.k[q]), d + w, label=f"query {q}") == 1.0
+
+
+def test_served_results_equal_alone_and_oracle(served):
+    wl, ix = served
+    with E.Server(ix, scratch_bytes=256 << 20, max_batch=64, max_wait_us=2000) as srv:
+        t = submit_all(srv, wl, range(wl.n_queries))
+        res = {q: srv.poll(tk) for q, tk in t.items()}
+        st = srv.stats()
+    assert st["completed"] == wl.n_queries and st["failed"] == 0
+    assert st["batches"] >= 2 and st["p99_ms"] >= st["p50_ms"] > 0
+    check_served(wl, ix, res)
+
+
+def test_small_scratch_budget_splits_batches(served):
+    wl, ix = served
+    qs = list(range(48))
+    # a slot that holds the largest single query but not the whole set: admission trims
+    U = torch.from_numpy(wl.user_emb).to(ix.device)
+    def ws(sub):
+        w = wl.subset(sub)
+        return ix.workspace_size(U[:len(sub)], w.feat_offsets, w.feat_keys, w.k)
+    slot = max(ws([q]) for q in qs) + (2 << 20)
+    assert ws(qs) > slot
+    with E.Server(ix, scratch_bytes=2 * slot, max_batch=64, max_wait_us=5000, pipeline=2) as srv:
+        t = submit_all(srv, wl, qs)
+        res = {q: srv.poll(tk) for q, tk in t.items()}
+        st = srv.stats()
+    assert st["completed"] == len(qs) and st["mean_batch"] < len(qs)
+    check_served(wl, ix, res, oracle_qs=set(qs[::6]))
+
+
+def test_threads_submit_concurrently(served):
+    wl, ix = served
+    out, errs = {}, []
+    with E.Server(ix, scratch_bytes=256 << 20, max_batch=32, max_wait_us=500, pipeline=3) as srv:
+        def client(qs):
+            try:
+                for q in qs:
+                    tk = srv.submit(wl.user_emb[q], wl.query_keys(q), int(wl.k[q]))
+                    out[q] = srv.poll(tk)
+            except Exception as e:  # reported below
+                errs.append(e)
+        th = [threading.Thread(target=client, args=(range(i, wl.n_queries, 4),)) for i in range(4)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+    assert not errs and len(out) == wl.n_queries
+    check_served(wl, ix, out, oracle_qs=set(range(0, wl.n_queries, 8)))
+
+
+def test_bf16_server_with_rescore(served):
+    wl, ix = served
+    qs = list(range(0, wl.n_queries, 3))
+    kw = dict(scan_dtype=E.BF16, rescore_factor=4)
+    with E.Server(ix, scratch_bytes=512 << 20, max_batch=64, max_wait_us=2000, **kw) as srv:
+        t = submit_all(srv, wl, qs)
+        res = {q: srv.poll(tk) for q, tk in t.items()}
+    check_served(wl, ix, res, kw=kw)
+
+
+def test_submission_errors(served):
+    wl, ix = served
+    u = wl.user_emb[0]
+    with E.Server(ix, scratch_bytes=64 << 20, max_batch=8) as srv:
+        for keys, k, user, code in [([3, 3], 10, u, E.EBR_EINVAL),
+                                    ([wl.n_keys], 10, u, E.EBR_EINVAL),
+                                    ([1], 10, np.full(wl.dim, np.nan, np.float32), E.EBR_EINVAL),
+                                    ([1], 8193, u, E.EBR_EINVAL),
+                                    ([1], -1, u, E.EBR_EINVAL)]:
+            with pytest.raises(E.EbrError) as ei:
+                srv.submit(user, keys, k)
+            assert ei.value.status == code
+        with pytest.raises(E.EbrError) as ei:
+            srv.poll(987654321, 0)
+        assert ei.value.status == E.EBR_ENOTFOUND
+        assert srv.stats()["submitted"] == 0
+    with pytest.raises(E.EbrError) as ei:        # index has no FP8 copy
+        E.Server(ix, scratch_bytes=64 << 20, scan_dtype=E.FP8E4M3)
+    assert ei.value.status == E.EBR_EUNSUPPORTED
+
+
+def test_query_larger_than_a_slot_is_refused(served):
+    wl, ix = served
+    big = np.argsort(-np.diff(wl.key_offsets))[:40].astype(np.int32)   # the longest lists
+    one = ix.workspace_size(torch.zeros(1, wl.dim, device=ix.device), [0, 0], [], [10])
+    with E.Server(ix, scratch_bytes=2 * (one + (1 << 20)), max_batch=8) as srv:
+        with pytest.raises(E.EbrError) as ei:
+            srv.submit(wl.user_emb[0], big, 10)
+        assert ei.value.status == E.EBR_ENOMEM
+        tk = srv.submit(wl.user_emb[0], big[:1], 10)     # a small query still runs
+        ids, sc = srv.poll(tk)
+        assert len(ids) == 10
+
+
+def test_destroy_drains_unpolled_tickets(served):
+    wl, ix = served
+    srv = E.Server(ix, scratch_bytes=128 << 20, max_batch=16, max_wait_us=100000)
+    held = []
+    for q in range(20):
+        t = srv.submit(wl.user_emb[q], wl.query_keys(q), int(wl.k[q]))
+        held.append((q, t, srv._pending[t]))
+    srv.close()                      # waits for every queued query
+    for q, t, (ids, sc, k) in held:
+        a_ids, a_sc = alone(ix, wl, q)
+        assert np.array_equal(ids[:k], a_ids)
