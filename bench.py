@@ -45,6 +45,8 @@ def main():
                     help="queries timed on the CPU oracle (-1: about 15 s worth, 0: skip)")
     ap.add_argument("--precision-steps", type=int, default=10,
                     help="timed batches of the BF16 and FP8 (+ exact FP32 rescore) scans (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark instead: 50M-ad inventory, Poisson arrivals, p50/p99")
     ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000",
@@ -71,6 +73,15 @@ def main():
     dev = torch.device("cuda:0")
     if args.serve:
         return serve_main(args, np, torch, W, E, dev)
+    if args.copy_calibration:
+        n = 1 << 30
+        src = torch.ones(n // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
+        return
     t0 = time.time()
     wl = W.make(args.config)
     log(f"[bench] generated {args.config}: N={wl.n_ads} V={wl.n_keys} postings={wl.n_postings} "
@@ -150,6 +161,26 @@ def main():
                 "vs_fp32_queries_per_s": q2 / qps,
             }
             log(f"[bench] {name}: {q2:.0f} queries/s ({1000 * el / args.precision_steps:.2f} ms/batch)")
+        # per-dtype scan error, reported: |deep~ - deep| and |deep~ - deep| / c (c = sum_i
+        # |u_i e_i|) over a seeded sample of 100k ads for 4 queries, against FP64 products
+        rng = np.random.default_rng(251122460 + 3)
+        sample = np.sort(rng.choice(N, 100_000, replace=False))
+        qe = [0, 1, 2, 3]
+        Ue = U[qe].contiguous()
+        z = np.zeros(len(qe) + 1, np.int64)
+        Es = torch.from_numpy(wl.ad_emb[sample]).to(dev).double()
+        exact = Ue.double() @ Es.T
+        cond = Ue.double().abs() @ Es.abs().T
+        idx = torch.from_numpy(sample).to(dev)
+        for name, dt in (("bf16", E.BF16), ("fp8e4m3", E.FP8E4M3)):
+            deep, _ = ix.score_dense(Ue, z, np.zeros(0, np.int32), scan_dtype=dt)
+            err = (deep[:, idx].double() - exact).abs()
+            rel = err / cond
+            precision[name]["deep_error"] = {
+                "ads": int(len(sample)), "queries": len(qe),
+                "max_abs": float(err.max()), "p99_abs": float(torch.quantile(err.flatten()[:1 << 24].float(), 0.99)),
+                "mean_abs": float(err.mean()), "max_rel_to_c": float(rel.max()), "mean_rel_to_c": float(rel.mean())}
+            del deep
 
     # uneven batching: 4096 queries in one launch on the same index, F ~ U{4..128},
     # K ~ U{100..2000}, BF16 scan with 4 K rescored exactly

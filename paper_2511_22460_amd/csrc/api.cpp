@@ -742,8 +742,11 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
             const int K = P->kcnt[q];
             if (K == 0) continue;
             if (ns == nt) { P->jq[q] = K; continue; }
+            // x = K' f sample ads are expected among the K' best; j sits 5 standard deviations
+            // (Poisson) above, so too few survivors (j - x > 5 sqrt(x)) and more than the
+            // 16384-slot buffer (for K' <= 8192 and f >= 1/64) are both rarer than 1e-5
             const double x = K * f;
-            int64_t j = (int64_t)std::ceil(x + 8.0 * std::sqrt(x) + 4.0);
+            int64_t j = (int64_t)std::ceil(x + 5.0 * std::sqrt(x) + 4.0);
             P->jq[q] = (int32_t)std::min<int64_t>(j, valid);
         }
     }
