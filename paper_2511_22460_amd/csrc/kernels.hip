@@ -276,14 +276,14 @@ __global__ __launch_bounds__(64) void k_decode_key(const ChunkHdr* chunks, const
 
 // ------------------------------------------------------------------ fused scoring
 
-// One work-group (16 wavefronts) scores one 256-query group against a sequence of 32-ad
-// tiles (persistent: tiles blockIdx.x, blockIdx.x + gridDim.x, ...). The waves specialise:
-//   waves 0..7  (consumers) - wave w owns query rows [32w, 32w + 32). Per tile: read and
-//                             clear its 32x32 block of the cross term, run the dot products
-//                             on the matrix cores, add, select.
+// One work-group (16 wavefronts at d <= 64) scores one 256-query group against a contiguous
+// range of 32-ad tiles. The waves specialise:
+//   waves 0..7  (consumers) - wave w owns query rows [32w, 32w + 32). Per tile: read, clear
+//                             and convert its 32x32 block of the cross term, run the dot
+//                             products on the matrix cores, add, select.
 //   waves 8..15 (producers) - one tile ahead: stage the next tile's embedding block in LDS
 //                             and accumulate its cross term into the other LDS buffer.
-// Two barriers per tile hand the double-buffered accumulators and the embedding stage over.
+// One barrier per tile hands the double-buffered accumulators and embedding stage over.
 //
 // Embedding layout (FP32 copy): per 32-ad block, D/8 quads x 64 lanes x 4 floats, where
 // quad i of lane l holds e[32b + (l & 31)][8i + 2j + (l >> 5)] for j = 0..3. Step s = 4i + j
@@ -293,9 +293,7 @@ __global__ __launch_bounds__(64) void k_decode_key(const ChunkHdr* chunks, const
 // Accumulator layout of v_mfma_f32_32x32x2_f32: register r of lane l holds row
 // 8 * (r >> 2) + 4 * (l >> 5) + (r & 3), column l & 31.
 //
-// Cross-term accumulators: int64 per (query, ad) in LDS, column swizzled by the query's low
-// five bits so that the 32 users of one posting (same ad, 32 consecutive queries) and the
-// 32 ads of one accumulator row both fall into distinct banks.
+// Cross-term accumulators: int64 per (query, ad) in LDS (layout: acc_idx below).
 constexpr int kProducerWaves = 8;
 constexpr int kLight = 8;  // entries with at most this many users are expanded per lane
 
@@ -306,6 +304,16 @@ template <int D> struct ScoreShape {
     static constexpr int CW = GQ / 32;
     static constexpr int NT = 64 * (CW + kProducerWaves);
 };
+
+// The cross term's exact fixed-point sum v (|v| < 2^61) times 2^e, in FP32: the high and low
+// 32-bit halves are converted separately, combined by one fused multiply-add and scaled
+// exactly by ldexp. The result is within 2^-23 |v| 2^e + 2^(e+9) of v 2^e, and a fixed
+// function of (v, e), so every pass and every batch produces the same bits.
+__device__ __forceinline__ float fixed_to_f32(long long v, int e) {
+    const int hi = (int)(v >> 32);
+    const uint32_t lo = (uint32_t)v;
+    return ldexpf(fmaf((float)hi, 0x1p32f, (float)lo), e);
+}
 
 // Accumulator cell of (query row q, ad offset o): rows are grouped by four so that the four
 // consecutive rows one lane of the 32x32 matrix-core tile owns are adjacent (two 16-byte
@@ -493,7 +501,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     __shared__ __attribute__((aligned(16))) unsigned long long s_acc[2][GQ * kTileAds];
     __shared__ f32x4 s_emb[2][NQ * 64];
     __shared__ float s_escale[2][kTileAds];
-    __shared__ __attribute__((aligned(16))) double s_inv[GQ];
+    __shared__ __attribute__((aligned(16))) int s_qexp[GQ];
     __shared__ __attribute__((aligned(16))) float s_thr[GQ];
     __shared__ uint32_t s_thr_hi[GQ];
     __shared__ uint32_t s_thr_lo[GQ];
@@ -525,7 +533,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     for (int i = tid; i < GQ; i += NT) {
         const int q = qbase + i;
         const bool in = q < B;
-        s_inv[i] = in ? a.qinv[q] : 0.0;
+        s_qexp[i] = in ? ilogb(a.qinv[q]) : 0;  // qinv = 2^-S_q exactly
         if (MODE == 0) {
             const uint32_t hi = in ? a.thresh[2 * q] : 0xffffffffu;
             s_thr_hi[i] = hi;
@@ -656,42 +664,61 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             __syncthreads();
             continue;
         }
-        // cross term of this lane's 16 cells (issued before the dot products)
-        ulonglong2 av[8];
+        // cross term of this lane's 16 cells, read, cleared for the buffer's next use and
+        // converted to FP32 while the other waves of the SIMD run their products
+        float wd[16];
+        {
+            ulonglong2 av[8];
 #pragma unroll
-        for (int g4 = 0; g4 < 4; ++g4) {
-            const ulonglong2* p = reinterpret_cast<const ulonglong2*>(acc + acc_idx(rg(g4), o));
-            av[2 * g4] = p[0];
-            av[2 * g4 + 1] = p[1];
+            for (int g4 = 0; g4 < 4; ++g4) {
+                const ulonglong2* p = reinterpret_cast<const ulonglong2*>(acc + acc_idx(rg(g4), o));
+                av[2 * g4] = p[0];
+                av[2 * g4 + 1] = p[1];
+            }
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4) {
+                ulonglong2* p = reinterpret_cast<ulonglong2*>(acc + acc_idx(rg(g4), o));
+                p[0] = make_ulonglong2(0ull, 0ull);
+                p[1] = make_ulonglong2(0ull, 0ull);
+            }
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4) {
+                const int4 ex = *reinterpret_cast<const int4*>(s_qexp + rg(g4));
+                const int exk[4] = {ex.x, ex.y, ex.z, ex.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const unsigned long long u = (k & 1) ? av[2 * g4 + (k >> 1)].y : av[2 * g4 + (k >> 1)].x;
+                    wd[4 * g4 + k] = fixed_to_f32((long long)u, exk[k]);
+                }
+            }
         }
         const uint32_t tile = tile_at(it);
         f32x16 c = {};
         const f32x4* eb = s_emb[cur];
         if (DT == 0) {
+            // B operands one quad ahead of the products that use them
+            f32x4 e_next = eb[lane];
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
-                const f32x4 e4 = eb[i * 64 + lane];
+                const f32x4 e4 = e_next;
+                if (i + 1 < NQ) e_next = eb[(i + 1) * 64 + lane];
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     c = __builtin_amdgcn_mfma_f32_32x32x2f32(ureg[4 * i + j], e4[j], c, 0, 0, 0);
             }
         } else {
+            bf16x8 e_next = __builtin_bit_cast(bf16x8, eb[lane]);
 #pragma unroll
-            for (int s2 = 0; s2 < NUB; ++s2)
-                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ubf[s2], __builtin_bit_cast(bf16x8, eb[s2 * 64 + lane]),
-                                                            c, 0, 0, 0);
+            for (int s2 = 0; s2 < NUB; ++s2) {
+                const bf16x8 e8 = e_next;
+                if (s2 + 1 < NUB) e_next = __builtin_bit_cast(bf16x8, eb[(s2 + 1) * 64 + lane]);
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ubf[s2], e8, c, 0, 0, 0);
+            }
         }
         const float escale = DT == 2 ? s_escale[cur][o] : 1.0f;
-        // clear the cells for the buffer's next use
-#pragma unroll
-        for (int g4 = 0; g4 < 4; ++g4) {
-            ulonglong2* p = reinterpret_cast<ulonglong2*>(acc + acc_idx(rg(g4), o));
-            p[0] = make_ulonglong2(0ull, 0ull);
-            p[1] = make_ulonglong2(0ull, 0ull);
-        }
         const int64_t ad = (int64_t)tile * kTileAds + o;
         const bool ad_ok = ad < a.n_ads;
-        float sc[16], wd[16];
+        float sc[16];
         bool pass = false;
         // sample pass: row base of this wave's block plus a 32-bit offset per row
         uint32_t* skeys = MODE == 1 ? a.sample_keys + (int64_t)q0 * a.sample_ld : nullptr;
@@ -699,15 +726,10 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
 #pragma unroll
         for (int g4 = 0; g4 < 4; ++g4) {
             const int r0 = rg(g4);
-            const double2 iv01 = *reinterpret_cast<const double2*>(s_inv + r0);
-            const double2 iv23 = *reinterpret_cast<const double2*>(s_inv + r0 + 2);
             const f32x4 th = *reinterpret_cast<const f32x4*>(s_thr + r0);
-            const double inv[4] = {iv01.x, iv01.y, iv23.x, iv23.y};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const unsigned long long u = (k & 1) ? av[2 * g4 + (k >> 1)].y : av[2 * g4 + (k >> 1)].x;
-                const long long v = (long long)u;
-                const float wide = (float)((double)v * inv[k]);
+                const float wide = wd[4 * g4 + k];
                 const float deep = DT == 2 ? c[4 * g4 + k] * escale : c[4 * g4 + k];
                 if (MODE == 2) {
                     const int q = qbase + r0 + k;
@@ -719,7 +741,6 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
                         skeys[(uint32_t)rl * (uint32_t)a.sample_ld + scol] = ad_ok ? score_key(deep + wide) : 0u;
                 } else {
                     sc[4 * g4 + k] = deep + wide;
-                    wd[4 * g4 + k] = wide;
                     pass |= sc[4 * g4 + k] >= th[k];  // NaN threshold: never
                 }
             }
