@@ -357,18 +357,25 @@ class Index:
         offs = np.zeros(len(kq) + 1, dtype=np.int64)
         np.cumsum(kq, out=offs[1:])
         total = int(offs[-1])
-        n = ctypes.c_size_t()
-        _check(load().ebr_workspace_size(self._h, ctypes.byref(b), ctypes.byref(n)),
-               "ebr_workspace_size")
-        ws = self.workspace(n.value)
         if out is None:
             ids = torch.empty(max(1, total), dtype=torch.int32, device=self.device)
             scores = torch.empty(max(1, total), dtype=torch.float32, device=self.device)
         else:
             ids, scores = out
-        _check(load().ebr_score_topk(self._h, ctypes.byref(b), ws.data_ptr(), ws.numel(),
-                                     ids.data_ptr(), scores.data_ptr(), _stream(stream)),
-               "ebr_score_topk")
+        lib = load()
+        # the kept workspace is tried first; it grows (one sizing call) only when too small
+        ws = self._ws
+        rc = lib.ebr_score_topk(self._h, ctypes.byref(b), ws.data_ptr() if ws is not None else None,
+                                ws.numel() if ws is not None else 0, ids.data_ptr(),
+                                scores.data_ptr(), _stream(stream))
+        if rc == EBR_ENOMEM and lib.ebr_last_error().startswith(b"workspace too small"):
+            n = ctypes.c_size_t()
+            _check(lib.ebr_workspace_size(self._h, ctypes.byref(b), ctypes.byref(n)),
+                   "ebr_workspace_size")
+            ws = self.workspace(n.value)
+            rc = lib.ebr_score_topk(self._h, ctypes.byref(b), ws.data_ptr(), ws.numel(),
+                                    ids.data_ptr(), scores.data_ptr(), _stream(stream))
+        _check(rc, "ebr_score_topk")
         return ids[:total], scores[:total], offs
 
     def score_dense(self, user_emb, feat_offsets, feat_keys, feat_mult=None, scan_dtype: int = F32,

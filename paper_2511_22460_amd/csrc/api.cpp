@@ -518,6 +518,32 @@ struct Plan {
     size_t total = 0;
 };
 
+// Per-thread planner scratch sized to the key space: a stamp per key (duplicate check within a
+// query, one generation per query) and a slot per key (distinct keys of a batch; all -1
+// between calls).
+struct PlanScratch {
+    std::vector<uint32_t> stamp;
+    std::vector<int32_t> slot_of;
+    uint32_t gen = 0;
+    uint32_t next_gen() {
+        if (++gen == 0) {
+            std::fill(stamp.begin(), stamp.end(), 0u);
+            gen = 1;
+        }
+        return gen;
+    }
+};
+
+static PlanScratch& plan_scratch(int64_t n_keys) {
+    static thread_local PlanScratch ps;
+    if ((int64_t)ps.stamp.size() < n_keys) {
+        ps.stamp.assign((size_t)n_keys, 0u);
+        ps.slot_of.assign((size_t)n_keys, -1);
+        ps.gen = 0;
+    }
+    return ps;
+}
+
 // Sample tiles of the threshold pre-pass: at least n_tiles / 64 tiles and 16 K' ads.
 static int64_t sample_tile_count(const Index& ix, int kcmax) {
     const int64_t nt = ix.n_tiles;
@@ -609,15 +635,18 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     if (nnz > 0 && !bt->feat_keys) { set_error("feat_keys is NULL"); return EBR_EINVAL; }
     P->nnz = nnz;
     if (nnz >= (1LL << 31)) { set_error("more than 2^31 features in one batch"); return EBR_EINVAL; }
-    // keys in range, distinct within a query; multipliers finite
-    std::vector<int32_t> tmp;
+    // keys in range, distinct within a query (a per-key stamp of the query being checked);
+    // multipliers finite
+    PlanScratch& ps = plan_scratch(ix.n_keys);
     for (int q = 0; q < B; ++q) {
         const int64_t f0 = bt->feat_offsets[q], f1 = bt->feat_offsets[q + 1];
-        tmp.assign(bt->feat_keys + f0, bt->feat_keys + f1);
-        for (int32_t k : tmp)
+        const uint32_t gen = ps.next_gen();
+        for (int64_t j = f0; j < f1; ++j) {
+            const int32_t k = bt->feat_keys[j];
             if (k < 0 || k >= ix.n_keys) { set_error("query %d: key %d out of range [0, %lld)", q, k, (long long)ix.n_keys); return EBR_EINVAL; }
-        std::sort(tmp.begin(), tmp.end());
-        if (std::adjacent_find(tmp.begin(), tmp.end()) != tmp.end()) { set_error("query %d repeats a key", q); return EBR_EINVAL; }
+            if (ps.stamp[k] == gen) { set_error("query %d repeats a key", q); return EBR_EINVAL; }
+            ps.stamp[k] = gen;
+        }
         if (bt->feat_mult)
             for (int64_t j = f0; j < f1; ++j)
                 if (!std::isfinite(bt->feat_mult[j])) { set_error("query %d: non-finite multiplier", q); return EBR_EINVAL; }
@@ -640,10 +669,20 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         P->kcnt[q] = (int32_t)kc;
         P->kcmax = std::max(P->kcmax, (int)kc);
     }
-    // distinct keys of the batch
-    std::vector<int32_t> uk(bt->feat_keys, bt->feat_keys + nnz);
-    std::sort(uk.begin(), uk.end());
-    uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
+    // distinct keys of the batch, in order of first use, and each feature's key slot
+    std::vector<int32_t> uk;
+    std::vector<int32_t> slot(nnz);
+    for (int64_t j = 0; j < nnz; ++j) {
+        const int32_t k = bt->feat_keys[j];
+        int32_t sl = ps.slot_of[k];
+        if (sl < 0) {
+            sl = (int32_t)uk.size();
+            ps.slot_of[k] = sl;
+            uk.push_back(k);
+        }
+        slot[j] = sl;
+    }
+    for (int32_t k : uk) ps.slot_of[k] = -1;
     const int nu = (int)uk.size();
     if (nu >= (1 << (32 - kSuperShift))) { set_error("too many distinct keys in one batch"); return EBR_EINVAL; }
     P->nu = nu;
@@ -665,14 +704,10 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     P->bucket_n = posts;
     // users of each (distinct key, query group), in query order
     const int nqg = std::max(1, P->n_qg);
-    std::vector<int32_t> slot(nnz);
     P->users_off.assign((size_t)nu * nqg + 1, 0);
     for (int q = 0; q < B; ++q)
-        for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
-            const int u = (int)(std::lower_bound(uk.begin(), uk.end(), bt->feat_keys[j]) - uk.begin());
-            slot[j] = u;
-            P->users_off[(size_t)u * nqg + q / P->gq + 1]++;
-        }
+        for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j)
+            P->users_off[(size_t)slot[j] * nqg + q / P->gq + 1]++;
     for (size_t i = 1; i < P->users_off.size(); ++i) P->users_off[i] += P->users_off[i - 1];
     // per-query fixed-point scale of the cross term: sum_j |m_j| max|W[k_j,:]| * 2^S < 2^60
     std::vector<int> Sq(B, 0);

@@ -295,7 +295,6 @@ __global__ __launch_bounds__(64) void k_decode_key(const ChunkHdr* chunks, const
 //
 // Cross-term accumulators: int64 per (query, ad) in LDS (layout: acc_idx below).
 constexpr int kProducerWaves = 8;
-constexpr int kLight = 8;  // entries with at most this many users are expanded per lane
 
 // Queries per group: 256 (8 consumer waves) up to d = 64, 128 (4 consumer waves) above, so
 // that the U operand and the LDS buffers fit.
@@ -354,8 +353,37 @@ struct ProdTile {
     uint2 e0;           // this lane's round-0 entry (valid if beg + pw + 8 * lane < end)
 };
 
+// Inclusive prefix maximum over the 64 lanes (values >= -1) with DPP moves: shifts by 1, 2, 4
+// and 8 within each row of 16 lanes, then row 15 / row 31 broadcasts into the later rows.
+__device__ __forceinline__ int wave_incl_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return v;
+}
+
+// Inclusive prefix sum over the 64 lanes, same DPP pattern.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+    return v;
+}
+
+// Up to 64 bucket entries of one tile (one per lane) flattened into their (entry, user) pairs,
+// 64 pairs per step: an exclusive scan of the entries' user counts places each entry's pairs;
+// each entry writes its lane into the slot of its first pair in this wave's LDS row `mark`,
+// a running maximum over the row gives every pair its entry, whose fields come from its lane.
+// Each pair costs one users[] load, one 32 x 32 -> 64-bit multiply and one LDS atomic add;
+// four steps are mapped before their loads are issued, so the loads overlap.
 __device__ __forceinline__ void cross_entries(const ScoreArgs& a, int g, uint2 e, bool valid,
-                                              unsigned long long* acc) {
+                                              int* mark, unsigned long long* acc) {
     const int lane = lane_id();
     const uint2* users = reinterpret_cast<const uint2*>(a.users);
     uint32_t cnt = 0, u0 = 0;
@@ -371,41 +399,41 @@ __device__ __forceinline__ void cross_entries(const ScoreArgs& a, int g, uint2 e
     }
     const int o = (int)(e.x & (kTileAds - 1));
     const int w = (int)e.y;
-    // light entries: each lane expands its own users (loads first, then the adds)
-    if (cnt > 0 && cnt <= (uint32_t)kLight) {
-        uint2 ue[kLight];
+    const uint32_t incl = wave_incl_sum(cnt);
+    const uint32_t pre = incl - cnt;
+    const int base = (int)(u0 - pre);  // users index of pair p of this entry: base + p
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    int carry = -1;
+    constexpr int kSteps = 4;
+    for (uint32_t p0 = 0; p0 < total; p0 += 64 * kSteps) {
+        int ub[kSteps], uo[kSteps], uw[kSteps];
 #pragma unroll
-        for (int j = 0; j < kLight; ++j)
-            if ((uint32_t)j < cnt) ue[j] = users[u0 + j];
+        for (int k = 0; k < kSteps; ++k) {
+            const uint32_t s0 = p0 + 64u * k;
+            // LDS operations of one wave complete in order: clear, mark, read back (relaxed
+            // atomics: lanes exchange values through the row, so no access may be elided)
+            __hip_atomic_store(&mark[lane], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            if (cnt > 0u && pre >= s0 && pre < s0 + 64u)
+                __hip_atomic_store(&mark[pre - s0], lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            const int mk = __hip_atomic_load(&mark[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            const int m = max(wave_incl_max(mk), carry);
+            carry = __builtin_amdgcn_readlane(m, 63);
+            ub[k] = __shfl(base, m, 64);
+            uo[k] = __shfl(o, m, 64);
+            uw[k] = __shfl(w, m, 64);
+        }
+        uint2 ue[kSteps];
 #pragma unroll
-        for (int j = 0; j < kLight; ++j)
-            if ((uint32_t)j < cnt)
-                atomicAdd(&acc[acc_idx((int)ue[j].x, o)],
-                          (unsigned long long)((long long)(int)ue[j].y * (long long)w));
-    }
-    // heavy entries: the whole wave expands one entry's users at a time
-    uint64_t heavy = __ballot(cnt > (uint32_t)kLight);
-    while (heavy) {
-        const int h = (int)__builtin_ctzll(heavy);
-        heavy &= heavy - 1;
-        const uint32_t hu0 = (uint32_t)__builtin_amdgcn_readlane((int)u0, h);
-        const uint32_t hcnt = (uint32_t)__builtin_amdgcn_readlane((int)cnt, h);
-        const int ho = __builtin_amdgcn_readlane(o, h);
-        const int hw = __builtin_amdgcn_readlane(w, h);
-        for (uint32_t j0 = 0; j0 < hcnt; j0 += 256) {
-            uint2 ue[4];
+        for (int k = 0; k < kSteps; ++k) {
+            const uint32_t p = p0 + 64u * k + (uint32_t)lane;
+            if (p < total) ue[k] = users[(uint32_t)ub[k] + p];
+        }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const uint32_t j = j0 + (uint32_t)(lane + 64 * r);
-                if (j < hcnt) ue[r] = users[hu0 + j];
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const uint32_t j = j0 + (uint32_t)(lane + 64 * r);
-                if (j < hcnt)
-                    atomicAdd(&acc[acc_idx((int)ue[r].x, ho)],
-                              (unsigned long long)((long long)(int)ue[r].y * (long long)hw));
-            }
+        for (int k = 0; k < kSteps; ++k) {
+            const uint32_t p = p0 + 64u * k + (uint32_t)lane;
+            if (p < total)
+                atomicAdd(&acc[acc_idx((int)ue[k].x, uo[k])],
+                          (unsigned long long)((long long)(int)ue[k].y * (long long)uw[k]));
         }
     }
 }
@@ -425,25 +453,21 @@ __device__ __forceinline__ ProdTile prod_entries(const ScoreArgs& a, uint2 b, in
 
 // Cross term of one tile (this wave's share), round 0 from the prefetched entry.
 __device__ __forceinline__ void prod_tile(const ScoreArgs& a, int g, int pw, const ProdTile& t,
-                                          unsigned long long* acc) {
+                                          int* mark, unsigned long long* acc) {
     const int lane = lane_id();
     const uint2* bucket = reinterpret_cast<const uint2*>(a.bucket);
     constexpr uint32_t kRound = kProducerWaves * 64u;
     const uint32_t first = t.beg + (uint32_t)pw;
     if (first >= t.end) return;
-    cross_entries(a, g, t.e0, first + kProducerWaves * (uint32_t)lane < t.end, acc);
+    cross_entries(a, g, t.e0, first + kProducerWaves * (uint32_t)lane < t.end, mark, acc);
     for (uint32_t base = first + kRound; base < t.end; base += kRound) {
         const uint32_t ei = base + kProducerWaves * (uint32_t)lane;
         const bool ok = ei < t.end;
         const uint2 e = ok ? bucket[ei] : make_uint2(0u, 0u);
-        cross_entries(a, g, e, ok, acc);
+        cross_entries(a, g, e, ok, mark, acc);
     }
 }
 
-// Persistent over tiles blockIdx.x, blockIdx.x + gridDim.x, ...; iteration `it` has the
-// consumers score tile it from LDS buffers [it & 1] (and clear the accumulators they read)
-// while the producers fill buffers [(it + 1) & 1] with tile it + 1 and prefetch the entries
-// of tile it + 2. Every wave executes exactly 1 + n_it barriers.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // FP32 -> BF16 bits, round to nearest even (finite inputs).
@@ -506,6 +530,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     __shared__ uint32_t s_thr_hi[GQ];
     __shared__ uint32_t s_thr_lo[GQ];
     __shared__ uint32_t s_live[GQ];
+    __shared__ int s_mark[kProducerWaves][64];
 
     const int tid = (int)threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const bool producer = wave >= CW;
@@ -585,7 +610,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         emb_load(t0, e1);
         if (n_it > 1) emb_load(tile_at(1), e2);
         emb_store(0, e1);
-        prod_tile(a, g, pw, prod_entries(a, prod_bounds(a, t0), pw), s_acc[0]);
+        prod_tile(a, g, pw, prod_entries(a, prod_bounds(a, t0), pw), s_mark[pw], s_acc[0]);
         ProdTile p1{};
         uint2 b2 = make_uint2(0u, 0u);
         if (n_it > 1) p1 = prod_entries(a, prod_bounds(a, tile_at(1)), pw);
@@ -600,7 +625,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
                 if (it + 3 < n_it) b3 = prod_bounds(a, tile_at(it + 3));
                 ProdTile p2{};
                 if (it + 2 < n_it) p2 = prod_entries(a, b2, pw);
-                prod_tile(a, g, pw, p1, s_acc[nb]);
+                prod_tile(a, g, pw, p1, s_mark[pw], s_acc[nb]);
                 p1 = p2;
                 b2 = b3;
             }
