@@ -380,12 +380,14 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
 // 64 pairs per step: an exclusive scan of the entries' user counts places each entry's pairs;
 // each entry writes its lane into the slot of its first pair in this wave's LDS row `mark`,
 // a running maximum over the row gives every pair its entry, whose fields come from its lane.
-// Each pair costs one users[] load, one 32 x 32 -> 64-bit multiply and one LDS atomic add;
-// four steps are mapped before their loads are issued, so the loads overlap.
-__device__ __forceinline__ void cross_entries(const ScoreArgs& a, int g, uint2 e, bool valid,
-                                              int* mark, unsigned long long* acc) {
-    const int lane = lane_id();
-    const uint2* users = reinterpret_cast<const uint2*>(a.users);
+// Each pair costs one users[] load, one 32 x 32 -> 64-bit multiply and one LDS atomic add.
+struct EntryLanes {
+    uint32_t cnt, pre, total;  // users of this lane's entry, pairs before it, pairs in all
+    int base, o, w;            // users index of pair p is base + p; ad offset; weight
+};
+
+__device__ __forceinline__ EntryLanes entry_lanes(const ScoreArgs& a, int g, uint2 e, bool valid) {
+    EntryLanes t;
     uint32_t cnt = 0, u0 = 0;
     if (valid) {
         if (a.packed) {
@@ -397,45 +399,105 @@ __device__ __forceinline__ void cross_entries(const ScoreArgs& a, int g, uint2 e
             cnt = a.users_off[slot + 1] - u0;
         }
     }
-    const int o = (int)(e.x & (kTileAds - 1));
-    const int w = (int)e.y;
     const uint32_t incl = wave_incl_sum(cnt);
-    const uint32_t pre = incl - cnt;
-    const int base = (int)(u0 - pre);  // users index of pair p of this entry: base + p
-    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    t.cnt = cnt;
+    t.pre = incl - cnt;
+    t.total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    t.base = (int)(u0 - t.pre);
+    t.o = (int)(e.x & (kTileAds - 1));
+    t.w = (int)e.y;
+    return t;
+}
+
+// Entry (lane) of each pair of step s (pairs 64 s .. 64 s + 63); carry is the entry of the
+// step's pair 64 s - 1 on entry (-1 before the first step) and of pair 64 s + 63 on return.
+__device__ __forceinline__ int step_entry(const EntryLanes& t, uint32_t s, int* mark, int& carry) {
+    const int lane = lane_id();
+    const uint32_t s0 = 64u * s;
+    // LDS operations of one wave complete in the order issued: clear, mark, read back. Lanes
+    // exchange values through the row, so the compiler must neither reorder nor elide these
+    // accesses (it sees them as one thread's accesses to unrelated addresses): compiler
+    // barriers between them.
+    mark[lane] = -1;
+    __asm__ __volatile__("" ::: "memory");
+    if (t.cnt > 0u && t.pre >= s0 && t.pre < s0 + 64u) mark[t.pre - s0] = lane;
+    __asm__ __volatile__("" ::: "memory");
+    const int mk = mark[lane];
+    __asm__ __volatile__("" ::: "memory");
+    const int m = max(wave_incl_max(mk), carry);
+    carry = __builtin_amdgcn_readlane(m, 63);
+    return m;
+}
+
+__device__ __forceinline__ void pair_add(unsigned long long* acc, uint2 ue, int o, int w) {
+    atomicAdd(&acc[acc_idx((int)ue.x, o)], (unsigned long long)((long long)(int)ue.y * (long long)w));
+}
+
+// Pairs of steps [s_begin, end) of a set of entries, four steps mapped before their loads.
+__device__ __forceinline__ void cross_steps(const ScoreArgs& a, const EntryLanes& t, uint32_t s_begin,
+                                            int* mark, unsigned long long* acc) {
+    const int lane = lane_id();
+    const uint2* users = reinterpret_cast<const uint2*>(a.users);
+    // entry of pair 64 s_begin - 1: the last lane with a non-empty entry starting before it
     int carry = -1;
+    if (s_begin > 0) {
+        const uint64_t before = __ballot(t.cnt > 0u && t.pre < 64u * s_begin);
+        carry = before ? 63 - (int)__builtin_clzll(before) : -1;
+    }
     constexpr int kSteps = 4;
-    for (uint32_t p0 = 0; p0 < total; p0 += 64 * kSteps) {
+    for (uint32_t s = s_begin; 64u * s < t.total; s += kSteps) {
         int ub[kSteps], uo[kSteps], uw[kSteps];
 #pragma unroll
         for (int k = 0; k < kSteps; ++k) {
-            const uint32_t s0 = p0 + 64u * k;
-            // LDS operations of one wave complete in order: clear, mark, read back (relaxed
-            // atomics: lanes exchange values through the row, so no access may be elided)
-            __hip_atomic_store(&mark[lane], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            if (cnt > 0u && pre >= s0 && pre < s0 + 64u)
-                __hip_atomic_store(&mark[pre - s0], lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            const int mk = __hip_atomic_load(&mark[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            const int m = max(wave_incl_max(mk), carry);
-            carry = __builtin_amdgcn_readlane(m, 63);
-            ub[k] = __shfl(base, m, 64);
-            uo[k] = __shfl(o, m, 64);
-            uw[k] = __shfl(w, m, 64);
+            const int m = step_entry(t, s + k, mark, carry);
+            ub[k] = __shfl(t.base, m, 64);
+            uo[k] = __shfl(t.o, m, 64);
+            uw[k] = __shfl(t.w, m, 64);
         }
         uint2 ue[kSteps];
 #pragma unroll
         for (int k = 0; k < kSteps; ++k) {
-            const uint32_t p = p0 + 64u * k + (uint32_t)lane;
-            if (p < total) ue[k] = users[(uint32_t)ub[k] + p];
+            const uint32_t p = 64u * (s + k) + (uint32_t)lane;
+            if (p < t.total) ue[k] = users[(uint32_t)ub[k] + p];
         }
 #pragma unroll
-        for (int k = 0; k < kSteps; ++k) {
-            const uint32_t p = p0 + 64u * k + (uint32_t)lane;
-            if (p < total)
-                atomicAdd(&acc[acc_idx((int)ue[k].x, uo[k])],
-                          (unsigned long long)((long long)(int)ue[k].y * (long long)uw[k]));
+        for (int k = 0; k < kSteps; ++k)
+            if (64u * (s + k) + (uint32_t)lane < t.total) pair_add(acc, ue[k], uo[k], uw[k]);
+    }
+}
+
+// The first kAheadSteps steps of a tile's round-0 entries, mapped and their users[] loads
+// issued one tile before the adds (the loads' latency then hides behind a whole tile).
+constexpr int kAheadSteps = 6;
+struct PairsAhead {
+    uint2 ue[kAheadSteps];
+    int uo[kAheadSteps], uw[kAheadSteps];
+    uint32_t total;
+};
+
+__device__ __forceinline__ PairsAhead pairs_ahead(const ScoreArgs& a, int g, uint2 e, bool valid,
+                                                  int* mark) {
+    const int lane = lane_id();
+    const uint2* users = reinterpret_cast<const uint2*>(a.users);
+    const EntryLanes t = entry_lanes(a, g, e, valid);
+    PairsAhead pa;
+    pa.total = t.total;
+    int carry = -1;
+#pragma unroll
+    for (int k = 0; k < kAheadSteps; ++k) {
+        pa.uo[k] = 0;
+        pa.uw[k] = 0;
+        pa.ue[k] = make_uint2(0u, 0u);
+        if (64u * k < t.total) {  // wave-uniform
+            const int m = step_entry(t, (uint32_t)k, mark, carry);
+            const int ub = __shfl(t.base, m, 64);
+            pa.uo[k] = __shfl(t.o, m, 64);
+            pa.uw[k] = __shfl(t.w, m, 64);
+            const uint32_t p = 64u * k + (uint32_t)lane;
+            if (p < t.total) pa.ue[k] = users[(uint32_t)ub + p];
         }
     }
+    return pa;
 }
 
 __device__ __forceinline__ uint2 prod_bounds(const ScoreArgs& a, uint32_t tile) {
@@ -451,21 +513,33 @@ __device__ __forceinline__ ProdTile prod_entries(const ScoreArgs& a, uint2 b, in
     return t;
 }
 
-// Cross term of one tile (this wave's share), round 0 from the prefetched entry.
+// Cross term of one tile (this wave's share): the prefetched round-0 pairs, the rest of
+// round 0, then later rounds of entries.
 __device__ __forceinline__ void prod_tile(const ScoreArgs& a, int g, int pw, const ProdTile& t,
-                                          int* mark, unsigned long long* acc) {
+                                          const PairsAhead& pa, int* mark, unsigned long long* acc) {
     const int lane = lane_id();
     const uint2* bucket = reinterpret_cast<const uint2*>(a.bucket);
     constexpr uint32_t kRound = kProducerWaves * 64u;
     const uint32_t first = t.beg + (uint32_t)pw;
     if (first >= t.end) return;
-    cross_entries(a, g, t.e0, first + kProducerWaves * (uint32_t)lane < t.end, mark, acc);
+#pragma unroll
+    for (int k = 0; k < kAheadSteps; ++k)
+        if (64u * k + (uint32_t)lane < pa.total) pair_add(acc, pa.ue[k], pa.uo[k], pa.uw[k]);
+    if (pa.total > 64u * kAheadSteps)
+        cross_steps(a, entry_lanes(a, g, t.e0, first + kProducerWaves * (uint32_t)lane < t.end),
+                    kAheadSteps, mark, acc);
     for (uint32_t base = first + kRound; base < t.end; base += kRound) {
         const uint32_t ei = base + kProducerWaves * (uint32_t)lane;
         const bool ok = ei < t.end;
         const uint2 e = ok ? bucket[ei] : make_uint2(0u, 0u);
-        cross_entries(a, g, e, ok, mark, acc);
+        cross_steps(a, entry_lanes(a, g, e, ok), 0, mark, acc);
     }
+}
+
+__device__ __forceinline__ PairsAhead prod_ahead(const ScoreArgs& a, int g, int pw, const ProdTile& t,
+                                                 int* mark) {
+    const uint32_t first = t.beg + (uint32_t)pw;
+    return pairs_ahead(a, g, t.e0, first + kProducerWaves * (uint32_t)lane_id() < t.end, mark);
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -610,24 +684,32 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         emb_load(t0, e1);
         if (n_it > 1) emb_load(tile_at(1), e2);
         emb_store(0, e1);
-        prod_tile(a, g, pw, prod_entries(a, prod_bounds(a, t0), pw), s_mark[pw], s_acc[0]);
-        ProdTile p1{};
-        uint2 b2 = make_uint2(0u, 0u);
-        if (n_it > 1) p1 = prod_entries(a, prod_bounds(a, tile_at(1)), pw);
-        if (n_it > 2) b2 = prod_bounds(a, tile_at(2));
+        {
+            const ProdTile p0 = prod_entries(a, prod_bounds(a, t0), pw);
+            prod_tile(a, g, pw, p0, prod_ahead(a, g, pw, p0, s_mark[pw]), s_mark[pw], s_acc[0]);
+        }
+        // pipeline: tile bounds three tiles ahead, round-0 entries two ahead, the first
+        // steps' users[] loads one ahead, the adds for the tile being filled
+        ProdTile p1{}, p2{};
+        PairsAhead pa1{};
+        uint2 b3 = make_uint2(0u, 0u);
+        if (n_it > 1) {
+            p1 = prod_entries(a, prod_bounds(a, tile_at(1)), pw);
+            pa1 = prod_ahead(a, g, pw, p1, s_mark[pw]);
+        }
+        if (n_it > 2) p2 = prod_entries(a, prod_bounds(a, tile_at(2)), pw);
+        if (n_it > 3) b3 = prod_bounds(a, tile_at(3));
         __syncthreads();
         for (int it = 0; it < n_it; ++it) {
             const int nb = (it & 1) ^ 1;
             if (it + 1 < n_it) {
                 emb_store(nb, e2);  // tile it + 1, loaded one iteration ago
                 if (it + 2 < n_it) emb_load(tile_at(it + 2), e2);
-                uint2 b3 = make_uint2(0u, 0u);
-                if (it + 3 < n_it) b3 = prod_bounds(a, tile_at(it + 3));
-                ProdTile p2{};
-                if (it + 2 < n_it) p2 = prod_entries(a, b2, pw);
-                prod_tile(a, g, pw, p1, s_mark[pw], s_acc[nb]);
+                prod_tile(a, g, pw, p1, pa1, s_mark[pw], s_acc[nb]);
                 p1 = p2;
-                b2 = b3;
+                if (it + 2 < n_it) pa1 = prod_ahead(a, g, pw, p1, s_mark[pw]);
+                if (it + 3 < n_it) p2 = prod_entries(a, b3, pw);
+                if (it + 4 < n_it) b3 = prod_bounds(a, tile_at(it + 4));
             }
             __syncthreads();
         }
