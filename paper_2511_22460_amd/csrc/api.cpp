@@ -559,7 +559,7 @@ static void layout(const Index& ix, bool topk, const BatchSizes& z, Plan* P) {
     const size_t n_users_off = (size_t)nu * nqg + 1, n_users = 2 * (size_t)std::max<int64_t>(1, z.nnz);
     P->bucket_n = z.bucket_n;
     size_t off = 0;
-    auto put = [&](size_t bytes) { size_t o = off; off = align256(off + std::max<size_t>(bytes, 4)); return o; };
+    auto put = [&](size_t bytes) { size_t o = off; off = align256(off + std::max<size_t>(bytes, 16)); return o; };
     P->off_plan = off;
     P->o_ukb = put(4 * (size_t)nu);
     P->o_ukp = put(4 * (size_t)(nu + 1));

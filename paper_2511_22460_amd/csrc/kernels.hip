@@ -679,40 +679,55 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             }
             if (DT == 2 && ptid < kTileAds) s_escale[buf][ptid] = r.scale;
         };
-        Raw e1, e2;
         const uint32_t t0 = tile_at(0);
-        emb_load(t0, e1);
-        if (n_it > 1) emb_load(tile_at(1), e2);
-        emb_store(0, e1);
         {
+            Raw e0;
+            emb_load(t0, e0);
+            emb_store(0, e0);
             const ProdTile p0 = prod_entries(a, prod_bounds(a, t0), pw);
             prod_tile(a, g, pw, p0, prod_ahead(a, g, pw, p0, s_mark[pw]), s_mark[pw], s_acc[0]);
         }
-        // pipeline: tile bounds three tiles ahead, round-0 entries two ahead, the first
-        // steps' users[] loads one ahead, the adds for the tile being filled
-        ProdTile p1{}, p2{};
-        PairsAhead pa1{};
-        uint2 b3 = make_uint2(0u, 0u);
-        if (n_it > 1) {
-            p1 = prod_entries(a, prod_bounds(a, tile_at(1)), pw);
-            pa1 = prod_ahead(a, g, pw, p1, s_mark[pw]);
-        }
-        if (n_it > 2) p2 = prod_entries(a, prod_bounds(a, tile_at(2)), pw);
-        if (n_it > 3) b3 = prod_bounds(a, tile_at(3));
+        // Tiles u = 1 .. n_it - 1 are filled in iteration u - 1. Every load is issued two
+        // iterations before its first use, so the state is kept in two sets, for odd and even
+        // u. Before the step for tile u its set holds: the embedding block of u (loaded), the
+        // first pairs of u (loaded), the entries of u and of u + 2, the bounds of u + 4.
+        struct Set {
+            Raw e;
+            PairsAhead pa;
+            ProdTile pc, pn;
+            uint2 bn;
+        };
+        Set so{}, se{};
+        auto entries_of = [&](int u) { return prod_entries(a, prod_bounds(a, tile_at(u)), pw); };
+        auto fill = [&](Set& st, int u) {  // prologue: the state before the step for tile u
+            if (u >= n_it) return;
+            emb_load(tile_at(u), st.e);
+            st.pc = entries_of(u);
+            st.pa = prod_ahead(a, g, pw, st.pc, s_mark[pw]);
+            if (u + 2 < n_it) st.pn = entries_of(u + 2);
+            if (u + 4 < n_it) st.bn = prod_bounds(a, tile_at(u + 4));
+        };
+        fill(so, 1);
+        fill(se, 2);
         __syncthreads();
-        for (int it = 0; it < n_it; ++it) {
-            const int nb = (it & 1) ^ 1;
-            if (it + 1 < n_it) {
-                emb_store(nb, e2);  // tile it + 1, loaded one iteration ago
-                if (it + 2 < n_it) emb_load(tile_at(it + 2), e2);
-                prod_tile(a, g, pw, p1, pa1, s_mark[pw], s_acc[nb]);
-                p1 = p2;
-                if (it + 2 < n_it) pa1 = prod_ahead(a, g, pw, p1, s_mark[pw]);
-                if (it + 3 < n_it) p2 = prod_entries(a, b3, pw);
-                if (it + 4 < n_it) b3 = prod_bounds(a, tile_at(it + 4));
+        auto step = [&](int u, Set& st) {
+            const int nb = u & 1;  // buffer of tile u (the consumers read it in iteration u)
+            emb_store(nb, st.e);
+            if (u + 2 < n_it) emb_load(tile_at(u + 2), st.e);
+            prod_tile(a, g, pw, st.pc, st.pa, s_mark[pw], s_acc[nb]);
+            if (u + 2 < n_it) {
+                st.pa = prod_ahead(a, g, pw, st.pn, s_mark[pw]);
+                st.pc = st.pn;
             }
+            if (u + 4 < n_it) st.pn = prod_entries(a, st.bn, pw);
+            if (u + 6 < n_it) st.bn = prod_bounds(a, tile_at(u + 6));
             __syncthreads();
+        };
+        for (int u = 1; u < n_it; u += 2) {
+            step(u, so);
+            if (u + 1 < n_it) step(u + 1, se);
         }
+        __syncthreads();  // the consumers' last iteration
         return;
     }
 
@@ -771,8 +786,34 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             __syncthreads();
             continue;
         }
-        // cross term of this lane's 16 cells, read, cleared for the buffer's next use and
-        // converted to FP32 while the other waves of the SIMD run their products
+        // products first: the tile's B operands are read from LDS up to eight quads ahead of
+        // the products that use them, so one LDS latency is exposed per tile
+        const uint32_t tile = tile_at(it);
+        f32x16 c = {};
+        const f32x4* eb = s_emb[cur];
+        if (DT == 0) {
+            constexpr int W = NQ < 8 ? NQ : 8;
+            f32x4 ev[W];
+#pragma unroll
+            for (int i = 0; i < W; ++i) ev[i] = eb[i * 64 + lane];
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                const f32x4 e4 = ev[i % W];
+                if (i + W < NQ) ev[i % W] = eb[(i + W) * 64 + lane];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    c = __builtin_amdgcn_mfma_f32_32x32x2f32(ureg[4 * i + j], e4[j], c, 0, 0, 0);
+            }
+        } else {
+            bf16x8 ev[NUB];
+#pragma unroll
+            for (int s2 = 0; s2 < NUB; ++s2) ev[s2] = __builtin_bit_cast(bf16x8, eb[s2 * 64 + lane]);
+#pragma unroll
+            for (int s2 = 0; s2 < NUB; ++s2)
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ubf[s2], ev[s2], c, 0, 0, 0);
+        }
+        // then the cross term of this lane's 16 cells: read (all reads in flight together),
+        // cleared for the buffer's next use, converted to FP32
         float wd[16];
         {
             ulonglong2 av[8];
@@ -797,29 +838,6 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
                     const unsigned long long u = (k & 1) ? av[2 * g4 + (k >> 1)].y : av[2 * g4 + (k >> 1)].x;
                     wd[4 * g4 + k] = fixed_to_f32((long long)u, exk[k]);
                 }
-            }
-        }
-        const uint32_t tile = tile_at(it);
-        f32x16 c = {};
-        const f32x4* eb = s_emb[cur];
-        if (DT == 0) {
-            // B operands one quad ahead of the products that use them
-            f32x4 e_next = eb[lane];
-#pragma unroll
-            for (int i = 0; i < NQ; ++i) {
-                const f32x4 e4 = e_next;
-                if (i + 1 < NQ) e_next = eb[(i + 1) * 64 + lane];
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    c = __builtin_amdgcn_mfma_f32_32x32x2f32(ureg[4 * i + j], e4[j], c, 0, 0, 0);
-            }
-        } else {
-            bf16x8 e_next = __builtin_bit_cast(bf16x8, eb[lane]);
-#pragma unroll
-            for (int s2 = 0; s2 < NUB; ++s2) {
-                const bf16x8 e8 = e_next;
-                if (s2 + 1 < NUB) e_next = __builtin_bit_cast(bf16x8, eb[(s2 + 1) * 64 + lane]);
-                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ubf[s2], e8, c, 0, 0, 0);
             }
         }
         const float escale = DT == 2 ? s_escale[cur][o] : 1.0f;
