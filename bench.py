@@ -28,6 +28,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the FP32 scoring kernel from the committed counter summary, or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_score_f32_c2_10M_B256_traffic.txt")
+    src = os.path.join(ROOT, "paper_2511_22460_amd", "csrc", "kernels.hip")
+    try:
+        fields = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if fields["kernel_source_sha256"].strip() != sha:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 WORKLOADS = {
     "c2": "plain FP32 at scale: 10M ads x 64-d FP32, 1M keys / ~4e8 postings, "
           "256 queries x 32 keys (Zipf 1.0 by rank), K=1000",
@@ -130,6 +146,8 @@ def main():
              for k in ("host_ms", "decode_ms", "sample_ms", "score_ms", "finalize_ms")}
     rounds = max(t["rounds"] for t in timings)
     flops = 2.0 * B * N * d
+    # postings of the batch's distinct keys: each is read once as an 8-byte tile-bucket entry
+    distinct_postings = int(np.diff(wl.key_offsets)[np.unique(wl.feat_keys)].sum())
     achieved = flops / (score_ms * 1e-3) / 1e12
 
     # reduced-precision scans of the same batch: BF16 and FP8-e4m3 copies streamed, 4 K
@@ -261,7 +279,9 @@ def main():
         "selection_rounds_max": rounds,
         "roofline": {"kernel": "k_score (fused deep+wide+select)", "bound": "mfma",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes": N * d * 4.0 + 8.0 * distinct_postings},
         "cpu_baseline": cpu,
         "precision": precision,
         "batching": batching,
