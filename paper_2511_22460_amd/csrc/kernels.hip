@@ -776,12 +776,16 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         const int cur = it & 1;
         unsigned long long* acc = s_acc[cur];
         if (!wave_live) {
-            // rows no live wave reads: keep the buffer clear for its next use
+            // rows of queries in the batch but inactive in this round still receive cross
+            // terms: keep the buffer clear for its next use. Rows past the batch are never
+            // written (the buffers start cleared), so their waves only keep the barrier count.
+            if (q0 < B) {
 #pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-                ulonglong2* p = reinterpret_cast<ulonglong2*>(acc + acc_idx(rg(g4), o));
-                p[0] = make_ulonglong2(0ull, 0ull);
-                p[1] = make_ulonglong2(0ull, 0ull);
+                for (int g4 = 0; g4 < 4; ++g4) {
+                    ulonglong2* p = reinterpret_cast<ulonglong2*>(acc + acc_idx(rg(g4), o));
+                    p[0] = make_ulonglong2(0ull, 0ull);
+                    p[1] = make_ulonglong2(0ull, 0ull);
+                }
             }
             __syncthreads();
             continue;
