@@ -646,7 +646,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     }
     auto tile_at = [&](int i) -> uint32_t {
         const int w = first + i;
-        return a.tile_list ? a.tile_list[w] : (uint32_t)w;
+        return MODE == 1 ? a.tile_list[w] : (uint32_t)w;  // the sample pass walks a tile list
     };
     __syncthreads();
 
@@ -675,7 +675,8 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const int j = ptid + k * kProdThreads;
-                if (j < UNITS) s_emb[buf][j] = DT == 2 ? fp8x8_to_bf16x8(r.c[k]) : r.u[k];
+                if (UNITS % kProdThreads == 0 || j < UNITS)
+                    s_emb[buf][j] = DT == 2 ? fp8x8_to_bf16x8(r.c[k]) : r.u[k];
             }
             if (DT == 2 && ptid < kTileAds) s_escale[buf][ptid] = r.scale;
         };
