@@ -409,24 +409,36 @@ __device__ __forceinline__ EntryLanes entry_lanes(const ScoreArgs& a, int g, uin
     return t;
 }
 
-// Entry (lane) of each pair of step s (pairs 64 s .. 64 s + 63); carry is the entry of the
-// step's pair 64 s - 1 on entry (-1 before the first step) and of pair 64 s + 63 on return.
-__device__ __forceinline__ int step_entry(const EntryLanes& t, uint32_t s, int* mark, int& carry) {
+// Entries (lanes) of the pairs of K consecutive steps s0 .. s0 + K - 1 (step s: pairs 64 s ..
+// 64 s + 63), with one LDS row of 64 slots per step, so that the rows of all K steps are
+// cleared, marked and read back in one round trip. carry is the entry of pair 64 s0 - 1 on
+// entry (-1 before the first step) and of the last pair of the last step on return.
+constexpr int kMarkRows = 4;
+template <int K>
+__device__ __forceinline__ void steps_entries(const EntryLanes& t, uint32_t s0, int* mark, int& carry,
+                                              int* m) {
+    static_assert(K <= kMarkRows, "one row per step");
     const int lane = lane_id();
-    const uint32_t s0 = 64u * s;
     // LDS operations of one wave complete in the order issued: clear, mark, read back. Lanes
-    // exchange values through the row, so the compiler must neither reorder nor elide these
+    // exchange values through the rows, so the compiler must neither reorder nor elide these
     // accesses (it sees them as one thread's accesses to unrelated addresses): compiler
     // barriers between them.
-    mark[lane] = -1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) mark[k * 64 + lane] = -1;
     __asm__ __volatile__("" ::: "memory");
-    if (t.cnt > 0u && t.pre >= s0 && t.pre < s0 + 64u) mark[t.pre - s0] = lane;
+    if (t.cnt > 0u && t.pre >= 64u * s0 && t.pre < 64u * (s0 + K)) mark[t.pre - 64u * s0] = lane;
     __asm__ __volatile__("" ::: "memory");
-    const int mk = mark[lane];
+    int mk[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) mk[k] = mark[k * 64 + lane];
     __asm__ __volatile__("" ::: "memory");
-    const int m = max(wave_incl_max(mk), carry);
-    carry = __builtin_amdgcn_readlane(m, 63);
-    return m;
+#pragma unroll
+    for (int k = 0; k < K; ++k) mk[k] = wave_incl_max(mk[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        m[k] = max(mk[k], carry);
+        carry = __builtin_amdgcn_readlane(m[k], 63);
+    }
 }
 
 __device__ __forceinline__ void pair_add(unsigned long long* acc, uint2 ue, int o, int w) {
@@ -444,15 +456,15 @@ __device__ __forceinline__ void cross_steps(const ScoreArgs& a, const EntryLanes
         const uint64_t before = __ballot(t.cnt > 0u && t.pre < 64u * s_begin);
         carry = before ? 63 - (int)__builtin_clzll(before) : -1;
     }
-    constexpr int kSteps = 4;
+    constexpr int kSteps = kMarkRows;
     for (uint32_t s = s_begin; 64u * s < t.total; s += kSteps) {
-        int ub[kSteps], uo[kSteps], uw[kSteps];
+        int m[kSteps], ub[kSteps], uo[kSteps], uw[kSteps];
+        steps_entries<kSteps>(t, s, mark, carry, m);
 #pragma unroll
         for (int k = 0; k < kSteps; ++k) {
-            const int m = step_entry(t, s + k, mark, carry);
-            ub[k] = __shfl(t.base, m, 64);
-            uo[k] = __shfl(t.o, m, 64);
-            uw[k] = __shfl(t.w, m, 64);
+            ub[k] = __shfl(t.base, m[k], 64);
+            uo[k] = __shfl(t.o, m[k], 64);
+            uw[k] = __shfl(t.w, m[k], 64);
         }
         uint2 ue[kSteps];
 #pragma unroll
@@ -483,16 +495,23 @@ __device__ __forceinline__ PairsAhead pairs_ahead(const ScoreArgs& a, int g, uin
     PairsAhead pa;
     pa.total = t.total;
     int carry = -1;
+    int m[kAheadSteps] = {};
+    static_assert(kMarkRows == 4 && kAheadSteps > kMarkRows && kAheadSteps <= 2 * kMarkRows,
+                  "two groups of steps");
+    // as many rows as the tile's pairs need (small batches have a few pairs per tile)
+    if (t.total > 128u) steps_entries<4>(t, 0, mark, carry, m);
+    else if (t.total > 64u) steps_entries<2>(t, 0, mark, carry, m);
+    else if (t.total > 0u) steps_entries<1>(t, 0, mark, carry, m);
+    if (t.total > 64u * kMarkRows) steps_entries<kAheadSteps - kMarkRows>(t, kMarkRows, mark, carry, m + kMarkRows);
 #pragma unroll
     for (int k = 0; k < kAheadSteps; ++k) {
         pa.uo[k] = 0;
         pa.uw[k] = 0;
         pa.ue[k] = make_uint2(0u, 0u);
         if (64u * k < t.total) {  // wave-uniform
-            const int m = step_entry(t, (uint32_t)k, mark, carry);
-            const int ub = __shfl(t.base, m, 64);
-            pa.uo[k] = __shfl(t.o, m, 64);
-            pa.uw[k] = __shfl(t.w, m, 64);
+            const int ub = __shfl(t.base, m[k], 64);
+            pa.uo[k] = __shfl(t.o, m[k], 64);
+            pa.uw[k] = __shfl(t.w, m[k], 64);
             const uint32_t p = 64u * k + (uint32_t)lane;
             if (p < t.total) pa.ue[k] = users[(uint32_t)ub + p];
         }
@@ -604,7 +623,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     __shared__ uint32_t s_thr_hi[GQ];
     __shared__ uint32_t s_thr_lo[GQ];
     __shared__ uint32_t s_live[GQ];
-    __shared__ int s_mark[kProducerWaves][64];
+    __shared__ int s_mark[kProducerWaves][kMarkRows * 64];
 
     const int tid = (int)threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const bool producer = wave >= CW;
