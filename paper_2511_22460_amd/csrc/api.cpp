@@ -709,7 +709,8 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j)
             P->users_off[(size_t)slot[j] * nqg + q / P->gq + 1]++;
     for (size_t i = 1; i < P->users_off.size(); ++i) P->users_off[i] += P->users_off[i - 1];
-    // per-query fixed-point scale of the cross term: sum_j |m_j| max|W[k_j,:]| * 2^S < 2^60
+    // per-query fixed-point scale of the cross term: sum_j |m_j| max|W[k_j,:]| * 2^S < 2^30, so
+    // that every (query, ad) sum of rounded terms fits an int32
     std::vector<int> Sq(B, 0);
     P->qinv.assign(B, 1.0);
     P->aq.assign(B, 0.0);
@@ -724,23 +725,13 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         if (A > 0.0 && std::isfinite(A)) {
             int e;
             std::frexp(A, &e);  // A < 2^e
-            S = std::max(-900, std::min(900, 60 - e));
-        }
-        // every multiplier must also fit its int32 field: |m| 2^(S - Sw_k) < 2^31
-        double mx = 0.0;
-        for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
-            const double m = bt->feat_mult ? (double)bt->feat_mult[j] : 1.0;
-            mx = std::max(mx, std::ldexp(std::fabs(m), S - ix.key_wshift[bt->feat_keys[j]]));
-        }
-        if (mx >= 2147483520.0) {
-            int e;
-            std::frexp(mx, &e);  // mx < 2^e
-            S -= e - 30;
+            S = std::max(-100, std::min(100, 30 - e));
         }
         Sq[q] = S;
         P->qinv[q] = std::ldexp(1.0, -S);
     }
-    // users: (query within its group, m_fix = round(m * 2^(S_q - Sw_k))), in query order
+    // users: (query within its group, bits of m' = m * 2^(S_q - Sw_k) in FP32), in query order;
+    // |m'| <= 2^(e(max|W_k|) - e(A_q) + 1) |m| max|W_k| / max|W_k| stays far from overflow
     P->users.assign((size_t)2 * std::max<int64_t>(1, nnz), 0u);
     {
         std::vector<uint32_t> fill(P->users_off.begin(), P->users_off.end() - 1);
@@ -750,9 +741,11 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
                 const uint32_t pos = fill[s]++;
                 const double m = bt->feat_mult ? (double)bt->feat_mult[j] : 1.0;
                 const int sw = ix.key_wshift[bt->feat_keys[j]];
-                const long long mf = std::llrint(std::ldexp(m, Sq[q] - sw));
+                const float mf = (float)std::ldexp(m, Sq[q] - sw);
+                uint32_t bits;
+                std::memcpy(&bits, &mf, 4);
                 P->users[2 * pos] = (uint32_t)(q % P->gq);
-                P->users[2 * pos + 1] = (uint32_t)(int32_t)mf;
+                P->users[2 * pos + 1] = bits;
             }
     }
     // output offsets

@@ -67,7 +67,7 @@ struct Index {
     std::vector<uint32_t> key_chunk_off;  // V + 1
     std::vector<int64_t> key_post_off;    // V + 1
     std::vector<float> key_maxw;          // V, max |w| of each list
-    std::vector<int8_t> key_wshift;       // V, Sw_k: weights of key k enter sums as round(w * 2^Sw_k)
+    std::vector<int8_t> key_wshift;       // V, Sw_k: weights of key k enter sums as w * 2^Sw_k
     ebr_index_info stats{};
     int device = 0;
 };

@@ -31,7 +31,7 @@ struct DecodeArgs {
     const float* weights;
     const uint32_t* uk_chunk_begin;   // per distinct key: its first chunk in the index
     const uint32_t* uk_chunk_prefix;  // n_ukeys + 1 prefix sums of chunk counts
-    const int32_t* uk_wshift;         // per distinct key: Sw_k, weights become round(w * 2^Sw_k)
+    const int32_t* uk_wshift;         // per distinct key: Sw_k, weights enter sums as w * 2^Sw_k
     int32_t n_ukeys;
     uint32_t total_chunks;
     int64_t n_tiles;
@@ -39,10 +39,10 @@ struct DecodeArgs {
     uint32_t* st_cnt;                 // count pass: postings per super-tile
     const uint32_t* st_off;           // n_super + 1 exclusive prefix
     uint32_t* st_fill;                // place pass: running fill per super-tile
-    uint32_t* stage;                  // place pass: pairs ((slot << 10) | ad & 1023, w_fix)
+    uint32_t* stage;                  // place pass: pairs ((slot << 10) | ad & 1023, w' bits)
     const uint32_t* users_off;        // non-null: final entries carry their key's users range
     uint32_t* tile_off;               // refine: n_tiles + 1 offsets into bucket
-    uint32_t* bucket;                 // refine: pairs (users range or slot | ad & 31, w_fix)
+    uint32_t* bucket;                 // refine: pairs (users range or slot | ad & 31, w' bits)
 };
 
 struct ScoreArgs {

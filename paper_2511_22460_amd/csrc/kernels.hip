@@ -16,12 +16,13 @@
 //                          K written out; queries whose candidate count fell outside
 //                          [K, capacity] get a tighter or safer threshold and run again.
 //
-// The cross term of Section 3.3 (equation "hitmatch") is accumulated as 64-bit fixed point.
-// Each posting weight of key k is rounded to w_fix = round(w * 2^Sw_k) (|w_fix| < 2^30) when
-// it is placed into its bucket; each (query, key) multiplier to m_fix = round(m * 2^(S_q -
-// Sw_k)) on the host, so m_fix * w_fix ~ m * w * 2^S_q at one common per-query scale with
-// sum |m_fix * w_fix| < 2^60. Integer sums do not depend on the order in which postings are
-// added, so scores are bit-identical across passes, tile schedules and batch compositions.
+// The cross term of Section 3.3 (equation "hitmatch") is accumulated as 32-bit fixed point.
+// Each posting weight of key k is scaled exactly to w' = w * 2^Sw_k (|w'| < 2^30) when it is
+// placed into its bucket, and each (query, key) multiplier on the host to m' = m * 2^(S_q -
+// Sw_k), so that m' * w' = m * w * 2^S_q at one per-query scale with sum_j |m_j| max|W_kj|
+// 2^S_q < 2^30. A (query, posting) pair adds round(fl(m' * w')) to an int32 accumulator; the
+// integer sum is exact and does not depend on the order of the adds, so scores are
+// bit-identical across passes, tile schedules and batch compositions.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -168,7 +169,7 @@ constexpr int kChunksPerWave = 8;
 // One wavefront decodes kChunksPerWave consecutive chunks of the batch's distinct keys and
 // counts (place == 0) or places (place == 1) their postings into 1024-ad super-tile buckets.
 // Runs of postings in the same super-tile are aggregated into one atomic per run. A placed
-// entry is ((slot << 10) | ad & 1023, w_fix); k_refine orders each super-tile by 32-ad tile.
+// entry is ((slot << 10) | ad & 1023, w' bits); k_refine orders each super-tile by 32-ad tile.
 __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
     const int lane = lane_id();
     const uint32_t gw = blockIdx.x * 4u + (threadIdx.x >> 6);
@@ -208,9 +209,9 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
         if (valid) {
             const uint32_t pos = a.st_off[st] + base + (uint32_t)(lane - my_head);
             const float w = a.weights[post_off + lane];
-            const int wfix = __double2int_rn(ldexp((double)w, a.uk_wshift[u]));
+            const float ws = ldexpf(w, a.uk_wshift[u]);  // exact: a power-of-two scale
             reinterpret_cast<uint2*>(a.stage)[pos] =
-                make_uint2((u << kSuperShift) | (id & (kSuperAds - 1)), (uint32_t)wfix);
+                make_uint2((u << kSuperShift) | (id & (kSuperAds - 1)), __float_as_uint(ws));
         }
     }
 }
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
 // One work-group per super-tile: counting sort of its entries by 32-ad tile (LDS counters),
 // the tile offsets, and the final entry format read by k_score: x = (u0 << 13) |
 // ((cnt - 1) << 5) | ad & 31 when the batch is one query group (users[u0, u0 + cnt) are the
-// key's users), else (slot << 5) | ad & 31; y = w_fix.
+// key's users), else (slot << 5) | ad & 31; y = the bits of w'.
 __global__ __launch_bounds__(256) void k_refine(DecodeArgs a) {
     __shared__ uint32_t s_cnt[kTilesPerSuper], s_off[kTilesPerSuper];
     const uint32_t st = blockIdx.x;
@@ -304,16 +305,6 @@ template <int D> struct ScoreShape {
     static constexpr int NT = 64 * (CW + kProducerWaves);
 };
 
-// The cross term's exact fixed-point sum v (|v| < 2^61) times 2^e, in FP32: the high and low
-// 32-bit halves are converted separately, combined by one fused multiply-add and scaled
-// exactly by ldexp. The result is within 2^-23 |v| 2^e + 2^(e+9) of v 2^e, and a fixed
-// function of (v, e), so every pass and every batch produces the same bits.
-__device__ __forceinline__ float fixed_to_f32(long long v, int e) {
-    const int hi = (int)(v >> 32);
-    const uint32_t lo = (uint32_t)v;
-    return ldexpf(fmaf((float)hi, 0x1p32f, (float)lo), e);
-}
-
 // Accumulator cell of (query row q, ad offset o): rows are grouped by four so that the four
 // consecutive rows one lane of the 32x32 matrix-core tile owns are adjacent (two 16-byte
 // LDS reads); the ad column is XOR-swizzled by the row group so that the users of one posting
@@ -345,7 +336,7 @@ __device__ __attribute__((noinline)) void store_dense(float* deep_out, float* wi
 }
 
 // Bucket entry: x = (u0 << 13) | ((cnt - 1) << 5) | ad offset when the batch is one query
-// group (the key's users are users[u0, u0 + cnt)), else (slot << 5) | ad offset; y = w_fix.
+// group (the key's users are users[u0, u0 + cnt)), else (slot << 5) | ad offset; y = w' bits.
 // Producer wave pw owns entries beg + pw + 8 * (lane + 64 r) of each tile; round r = 0 is
 // prefetched one tile ahead.
 struct ProdTile {
@@ -441,13 +432,16 @@ __device__ __forceinline__ void steps_entries(const EntryLanes& t, uint32_t s0, 
     }
 }
 
-__device__ __forceinline__ void pair_add(unsigned long long* acc, uint2 ue, int o, int w) {
-    atomicAdd(&acc[acc_idx((int)ue.x, o)], (unsigned long long)((long long)(int)ue.y * (long long)w));
+// One (query, posting) pair: round(fl(m' * w')) into the query's cell (users hold m' bits,
+// bucket entries w' bits).
+__device__ __forceinline__ void pair_add(uint32_t* acc, uint2 ue, int o, int w) {
+    const float p = __uint_as_float(ue.y) * __uint_as_float((uint32_t)w);
+    atomicAdd(&acc[acc_idx((int)ue.x, o)], (uint32_t)__float2int_rn(p));
 }
 
 // Pairs of steps [s_begin, end) of a set of entries, four steps mapped before their loads.
 __device__ __forceinline__ void cross_steps(const ScoreArgs& a, const EntryLanes& t, uint32_t s_begin,
-                                            int* mark, unsigned long long* acc) {
+                                            int* mark, uint32_t* acc) {
     const int lane = lane_id();
     const uint2* users = reinterpret_cast<const uint2*>(a.users);
     // entry of pair 64 s_begin - 1: the last lane with a non-empty entry starting before it
@@ -535,7 +529,7 @@ __device__ __forceinline__ ProdTile prod_entries(const ScoreArgs& a, uint2 b, in
 // Cross term of one tile (this wave's share): the prefetched round-0 pairs, the rest of
 // round 0, then later rounds of entries.
 __device__ __forceinline__ void prod_tile(const ScoreArgs& a, int g, int pw, const ProdTile& t,
-                                          const PairsAhead& pa, int* mark, unsigned long long* acc) {
+                                          const PairsAhead& pa, int* mark, uint32_t* acc) {
     const int lane = lane_id();
     const uint2* bucket = reinterpret_cast<const uint2*>(a.bucket);
     constexpr uint32_t kRound = kProducerWaves * 64u;
@@ -615,7 +609,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     constexpr int kProdThreads = 64 * kProducerWaves;
     constexpr int UNITS = EmbStage<D, DT>::UNITS;
     constexpr int PER = EmbStage<D, DT>::PER;
-    __shared__ __attribute__((aligned(16))) unsigned long long s_acc[2][GQ * kTileAds];
+    __shared__ __attribute__((aligned(16))) uint32_t s_acc[2][GQ * kTileAds];
     __shared__ f32x4 s_emb[2][NQ * 64];
     __shared__ float s_escale[2][kTileAds];
     __shared__ __attribute__((aligned(16))) int s_qexp[GQ];
@@ -647,7 +641,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     const int n_it = (int)(((int64_t)a.n_work * (range + 1)) / a.n_ranges) - first;
     if (n_it <= 0) return;
 
-    for (int i = tid; i < 2 * GQ * kTileAds; i += NT) (&s_acc[0][0])[i] = 0ull;
+    for (int i = tid; i < 2 * GQ * kTileAds; i += NT) (&s_acc[0][0])[i] = 0u;
     for (int i = tid; i < GQ; i += NT) {
         const int q = qbase + i;
         const bool in = q < B;
@@ -794,18 +788,15 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     const int o = lane & 31;
     for (int it = 0; it < n_it; ++it) {
         const int cur = it & 1;
-        unsigned long long* acc = s_acc[cur];
+        uint32_t* acc = s_acc[cur];
         if (!wave_live) {
             // rows of queries in the batch but inactive in this round still receive cross
             // terms: keep the buffer clear for its next use. Rows past the batch are never
             // written (the buffers start cleared), so their waves only keep the barrier count.
             if (q0 < B) {
 #pragma unroll
-                for (int g4 = 0; g4 < 4; ++g4) {
-                    ulonglong2* p = reinterpret_cast<ulonglong2*>(acc + acc_idx(rg(g4), o));
-                    p[0] = make_ulonglong2(0ull, 0ull);
-                    p[1] = make_ulonglong2(0ull, 0ull);
-                }
+                for (int g4 = 0; g4 < 4; ++g4)
+                    *reinterpret_cast<uint4*>(acc + acc_idx(rg(g4), o)) = make_uint4(0u, 0u, 0u, 0u);
             }
             __syncthreads();
             continue;
@@ -840,28 +831,19 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         // cleared for the buffer's next use, converted to FP32
         float wd[16];
         {
-            ulonglong2 av[8];
+            uint4 av[4];
 #pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-                const ulonglong2* p = reinterpret_cast<const ulonglong2*>(acc + acc_idx(rg(g4), o));
-                av[2 * g4] = p[0];
-                av[2 * g4 + 1] = p[1];
-            }
+            for (int g4 = 0; g4 < 4; ++g4) av[g4] = *reinterpret_cast<const uint4*>(acc + acc_idx(rg(g4), o));
 #pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-                ulonglong2* p = reinterpret_cast<ulonglong2*>(acc + acc_idx(rg(g4), o));
-                p[0] = make_ulonglong2(0ull, 0ull);
-                p[1] = make_ulonglong2(0ull, 0ull);
-            }
+            for (int g4 = 0; g4 < 4; ++g4)
+                *reinterpret_cast<uint4*>(acc + acc_idx(rg(g4), o)) = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
             for (int g4 = 0; g4 < 4; ++g4) {
                 const int4 ex = *reinterpret_cast<const int4*>(s_qexp + rg(g4));
-                const int exk[4] = {ex.x, ex.y, ex.z, ex.w};
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const unsigned long long u = (k & 1) ? av[2 * g4 + (k >> 1)].y : av[2 * g4 + (k >> 1)].x;
-                    wd[4 * g4 + k] = fixed_to_f32((long long)u, exk[k]);
-                }
+                wd[4 * g4] = ldexpf((float)(int)av[g4].x, ex.x);
+                wd[4 * g4 + 1] = ldexpf((float)(int)av[g4].y, ex.y);
+                wd[4 * g4 + 2] = ldexpf((float)(int)av[g4].z, ex.z);
+                wd[4 * g4 + 3] = ldexpf((float)(int)av[g4].w, ex.w);
             }
         }
         const float escale = DT == 2 ? s_escale[cur][o] : 1.0f;
