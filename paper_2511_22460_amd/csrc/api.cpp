@@ -880,6 +880,7 @@ static ScoreArgs score_args(const Index& ix, const Plan& P, const ebr_batch* bt,
     s.bucket = (const uint32_t*)(ws + P.off_bucket);
     s.users_off = (const uint32_t*)(ws + P.o_uoff);
     s.users = (const uint32_t*)(ws + P.o_users);
+    s.n_users = (uint32_t)P.nnz;
     s.qinv = (const double*)(ws + P.o_qi);
     s.n_work = (int32_t)ix.n_tiles;
     s.tile_list = nullptr;

@@ -57,7 +57,8 @@ struct ScoreArgs {
     const uint32_t* tile_off;         // n_tiles + 1
     const uint32_t* bucket;           // pairs
     const uint32_t* users_off;        // n_ukeys * n_qgroups + 1
-    const uint32_t* users;            // pairs (query within group, m_fix)
+    const uint32_t* users;            // pairs (query within group, bits of m')
+    uint32_t n_users;                 // pairs in users
     const double* qinv;               // 2^-S per query
     int32_t n_work;                   // tiles to visit
     int32_t n_ranges;                 // contiguous tile ranges per query group (set at launch)

@@ -441,7 +441,7 @@ __device__ __forceinline__ void pair_add(uint32_t* acc, uint2 ue, int o, int w) 
 
 // Pairs of steps [s_begin, end) of a set of entries, four steps mapped before their loads.
 __device__ __forceinline__ void cross_steps(const ScoreArgs& a, const EntryLanes& t, uint32_t s_begin,
-                                            int* mark, uint32_t* acc) {
+                                            int* mark, uint32_t* acc, const uint2* lds_users) {
     const int lane = lane_id();
     const uint2* users = reinterpret_cast<const uint2*>(a.users);
     // entry of pair 64 s_begin - 1: the last lane with a non-empty entry starting before it
@@ -464,7 +464,7 @@ __device__ __forceinline__ void cross_steps(const ScoreArgs& a, const EntryLanes
 #pragma unroll
         for (int k = 0; k < kSteps; ++k) {
             const uint32_t p = 64u * (s + k) + (uint32_t)lane;
-            if (p < t.total) ue[k] = users[(uint32_t)ub[k] + p];
+            if (p < t.total) ue[k] = lds_users ? lds_users[(uint32_t)ub[k] + p] : users[(uint32_t)ub[k] + p];
         }
 #pragma unroll
         for (int k = 0; k < kSteps; ++k)
@@ -475,6 +475,8 @@ __device__ __forceinline__ void cross_steps(const ScoreArgs& a, const EntryLanes
 // The first kAheadSteps steps of a tile's round-0 entries, mapped and their users[] loads
 // issued one tile before the adds (the loads' latency then hides behind a whole tile).
 constexpr int kAheadSteps = 6;
+// (query, multiplier) pairs of one query group that are copied to LDS when they fit.
+constexpr int kUsersLds = 8192;
 struct PairsAhead {
     uint2 ue[kAheadSteps];
     int uo[kAheadSteps], uw[kAheadSteps];
@@ -482,7 +484,7 @@ struct PairsAhead {
 };
 
 __device__ __forceinline__ PairsAhead pairs_ahead(const ScoreArgs& a, int g, uint2 e, bool valid,
-                                                  int* mark) {
+                                                  int* mark, const uint2* lds_users) {
     const int lane = lane_id();
     const uint2* users = reinterpret_cast<const uint2*>(a.users);
     const EntryLanes t = entry_lanes(a, g, e, valid);
@@ -507,7 +509,7 @@ __device__ __forceinline__ PairsAhead pairs_ahead(const ScoreArgs& a, int g, uin
             pa.uo[k] = __shfl(t.o, m[k], 64);
             pa.uw[k] = __shfl(t.w, m[k], 64);
             const uint32_t p = 64u * k + (uint32_t)lane;
-            if (p < t.total) pa.ue[k] = users[(uint32_t)ub + p];
+            if (p < t.total) pa.ue[k] = lds_users ? lds_users[(uint32_t)ub + p] : users[(uint32_t)ub + p];
         }
     }
     return pa;
@@ -529,7 +531,8 @@ __device__ __forceinline__ ProdTile prod_entries(const ScoreArgs& a, uint2 b, in
 // Cross term of one tile (this wave's share): the prefetched round-0 pairs, the rest of
 // round 0, then later rounds of entries.
 __device__ __forceinline__ void prod_tile(const ScoreArgs& a, int g, int pw, const ProdTile& t,
-                                          const PairsAhead& pa, int* mark, uint32_t* acc) {
+                                          const PairsAhead& pa, int* mark, uint32_t* acc,
+                                          const uint2* lds_users) {
     const int lane = lane_id();
     const uint2* bucket = reinterpret_cast<const uint2*>(a.bucket);
     constexpr uint32_t kRound = kProducerWaves * 64u;
@@ -540,19 +543,19 @@ __device__ __forceinline__ void prod_tile(const ScoreArgs& a, int g, int pw, con
         if (64u * k + (uint32_t)lane < pa.total) pair_add(acc, pa.ue[k], pa.uo[k], pa.uw[k]);
     if (pa.total > 64u * kAheadSteps)
         cross_steps(a, entry_lanes(a, g, t.e0, first + kProducerWaves * (uint32_t)lane < t.end),
-                    kAheadSteps, mark, acc);
+                    kAheadSteps, mark, acc, lds_users);
     for (uint32_t base = first + kRound; base < t.end; base += kRound) {
         const uint32_t ei = base + kProducerWaves * (uint32_t)lane;
         const bool ok = ei < t.end;
         const uint2 e = ok ? bucket[ei] : make_uint2(0u, 0u);
-        cross_steps(a, entry_lanes(a, g, e, ok), 0, mark, acc);
+        cross_steps(a, entry_lanes(a, g, e, ok), 0, mark, acc, lds_users);
     }
 }
 
 __device__ __forceinline__ PairsAhead prod_ahead(const ScoreArgs& a, int g, int pw, const ProdTile& t,
-                                                 int* mark) {
+                                                 int* mark, const uint2* lds_users) {
     const uint32_t first = t.beg + (uint32_t)pw;
-    return pairs_ahead(a, g, t.e0, first + kProducerWaves * (uint32_t)lane_id() < t.end, mark);
+    return pairs_ahead(a, g, t.e0, first + kProducerWaves * (uint32_t)lane_id() < t.end, mark, lds_users);
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -618,6 +621,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     __shared__ uint32_t s_thr_lo[GQ];
     __shared__ uint32_t s_live[GQ];
     __shared__ int s_mark[kProducerWaves][kMarkRows * 64];
+    __shared__ uint2 s_users[kUsersLds];
 
     const int tid = (int)threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const bool producer = wave >= CW;
@@ -642,6 +646,13 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     if (n_it <= 0) return;
 
     for (int i = tid; i < 2 * GQ * kTileAds; i += NT) (&s_acc[0][0])[i] = 0u;
+    // one query group: its (query, multiplier) users fit in LDS when few enough
+    const uint2* lu = nullptr;
+    if (a.packed && a.n_users <= (uint32_t)kUsersLds) {
+        for (uint32_t i = (uint32_t)tid; i < a.n_users; i += (uint32_t)NT)
+            s_users[i] = reinterpret_cast<const uint2*>(a.users)[i];
+        lu = s_users;
+    }
     for (int i = tid; i < GQ; i += NT) {
         const int q = qbase + i;
         const bool in = q < B;
@@ -699,7 +710,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             emb_load(t0, e0);
             emb_store(0, e0);
             const ProdTile p0 = prod_entries(a, prod_bounds(a, t0), pw);
-            prod_tile(a, g, pw, p0, prod_ahead(a, g, pw, p0, s_mark[pw]), s_mark[pw], s_acc[0]);
+            prod_tile(a, g, pw, p0, prod_ahead(a, g, pw, p0, s_mark[pw], lu), s_mark[pw], s_acc[0], lu);
         }
         // Tiles u = 1 .. n_it - 1 are filled in iteration u - 1. Every load is issued two
         // iterations before its first use, so the state is kept in two sets, for odd and even
@@ -717,7 +728,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             if (u >= n_it) return;
             emb_load(tile_at(u), st.e);
             st.pc = entries_of(u);
-            st.pa = prod_ahead(a, g, pw, st.pc, s_mark[pw]);
+            st.pa = prod_ahead(a, g, pw, st.pc, s_mark[pw], lu);
             if (u + 2 < n_it) st.pn = entries_of(u + 2);
             if (u + 4 < n_it) st.bn = prod_bounds(a, tile_at(u + 4));
         };
@@ -728,9 +739,9 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             const int nb = u & 1;  // buffer of tile u (the consumers read it in iteration u)
             emb_store(nb, st.e);
             if (u + 2 < n_it) emb_load(tile_at(u + 2), st.e);
-            prod_tile(a, g, pw, st.pc, st.pa, s_mark[pw], s_acc[nb]);
+            prod_tile(a, g, pw, st.pc, st.pa, s_mark[pw], s_acc[nb], lu);
             if (u + 2 < n_it) {
-                st.pa = prod_ahead(a, g, pw, st.pn, s_mark[pw]);
+                st.pa = prod_ahead(a, g, pw, st.pn, s_mark[pw], lu);
                 st.pc = st.pn;
             }
             if (u + 4 < n_it) st.pn = prod_entries(a, st.bn, pw);
