@@ -615,7 +615,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     __shared__ __attribute__((aligned(16))) uint32_t s_acc[2][GQ * kTileAds];
     __shared__ f32x4 s_emb[2][NQ * 64];
     __shared__ float s_escale[2][kTileAds];
-    __shared__ __attribute__((aligned(16))) int s_qexp[GQ];
+    __shared__ __attribute__((aligned(16))) float s_qscale[GQ];
     __shared__ __attribute__((aligned(16))) float s_thr[GQ];
     __shared__ uint32_t s_thr_hi[GQ];
     __shared__ uint32_t s_thr_lo[GQ];
@@ -656,7 +656,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     for (int i = tid; i < GQ; i += NT) {
         const int q = qbase + i;
         const bool in = q < B;
-        s_qexp[i] = in ? ilogb(a.qinv[q]) : 0;  // qinv = 2^-S_q exactly
+        s_qscale[i] = in ? (float)a.qinv[q] : 0.0f;  // 2^-S_q, |S_q| <= 100: exact in FP32
         if (MODE == 0) {
             const uint32_t hi = in ? a.thresh[2 * q] : 0xffffffffu;
             s_thr_hi[i] = hi;
@@ -850,11 +850,10 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
                 *reinterpret_cast<uint4*>(acc + acc_idx(rg(g4), o)) = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
             for (int g4 = 0; g4 < 4; ++g4) {
-                const int4 ex = *reinterpret_cast<const int4*>(s_qexp + rg(g4));
-                wd[4 * g4] = ldexpf((float)(int)av[g4].x, ex.x);
-                wd[4 * g4 + 1] = ldexpf((float)(int)av[g4].y, ex.y);
-                wd[4 * g4 + 2] = ldexpf((float)(int)av[g4].z, ex.z);
-                wd[4 * g4 + 3] = ldexpf((float)(int)av[g4].w, ex.w);
+                wd[4 * g4] = (float)(int)av[g4].x;  // the row's scale is applied below
+                wd[4 * g4 + 1] = (float)(int)av[g4].y;
+                wd[4 * g4 + 2] = (float)(int)av[g4].z;
+                wd[4 * g4 + 3] = (float)(int)av[g4].w;
             }
         }
         const float escale = DT == 2 ? s_escale[cur][o] : 1.0f;
@@ -869,9 +868,12 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         for (int g4 = 0; g4 < 4; ++g4) {
             const int r0 = rg(g4);
             const f32x4 th = *reinterpret_cast<const f32x4*>(s_thr + r0);
+            const f32x4 sq = *reinterpret_cast<const f32x4*>(s_qscale + r0);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const float wide = wd[4 * g4 + k];
+                // the cross term's integer sum times 2^-S_q (exact); the score is one fused
+                // multiply-add, the same value as the sum deep + wide
+                const float wide = wd[4 * g4 + k] * sq[k];
                 const float deep = DT == 2 ? c[4 * g4 + k] * escale : c[4 * g4 + k];
                 if (MODE == 2) {
                     const int q = qbase + r0 + k;
@@ -880,9 +882,9 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
                 } else if (MODE == 1) {
                     const int rl = r0 - wave * 32 + k;
                     if (q0 + rl < B)
-                        skeys[(uint32_t)rl * (uint32_t)a.sample_ld + scol] = ad_ok ? score_key(deep + wide) : 0u;
+                        skeys[(uint32_t)rl * (uint32_t)a.sample_ld + scol] = ad_ok ? score_key(fmaf(wd[4 * g4 + k], sq[k], deep)) : 0u;
                 } else {
-                    sc[4 * g4 + k] = deep + wide;
+                    sc[4 * g4 + k] = fmaf(wd[4 * g4 + k], sq[k], deep);
                     pass |= sc[4 * g4 + k] >= th[k];  // NaN threshold: never
                 }
             }
@@ -897,7 +899,8 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
                     if (sc[r] >= s_thr[ql]) {
                         const uint32_t key = score_key(sc[r]);
                         if (key > s_thr_hi[ql] || (key == s_thr_hi[ql] && idk >= s_thr_lo[ql]))
-                            append_candidate(a.cand, a.cand_cnt, a.cand_wide, a.cap, qbase + ql, key, idk, wd[r]);
+                            append_candidate(a.cand, a.cand_cnt, a.cand_wide, a.cap, qbase + ql, key, idk,
+                                             wd[r] * s_qscale[ql]);
                     }
                 }
             }
