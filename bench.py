@@ -69,6 +69,8 @@ def main():
                     help="arrival rates (queries/s) of the serving benchmark")
     ap.add_argument("--serve-ads", type=int, default=50_000_000)
     ap.add_argument("--max-wait-us", type=int, default=300)
+    ap.add_argument("--serve-scratch-gib", type=float, default=8.0,
+                    help="scratch budget of the serving loop (split between two batches in flight)")
     ap.add_argument("--batch-steps", type=int, default=5,
                     help="timed batches of the 4096-query uneven batch (0: skip)")
     args = ap.parse_args()
@@ -307,7 +309,7 @@ def serve_main(args, np, torch, W, E, dev):
     ix = E.Index.from_workload(wl, device=dev, dtypes=1 | (1 << E.BF16))
     st = ix.stats()
     log(f"[serve] index built in {time.time() - t0:.1f}s: {st['arena_bytes'] / 1e9:.2f} GB arena")
-    scratch = 4 << 30
+    scratch = int(args.serve_scratch_gib * (1 << 30)) & ~255
     srv = E.Server(ix, scratch_bytes=scratch, max_batch=256, max_wait_us=args.max_wait_us,
                    pipeline=2, scan_dtype=E.BF16, rescore_factor=4)
     lib = E.load()
@@ -406,7 +408,7 @@ def serve_main(args, np, torch, W, E, dev):
         "data": "synthetic (seeded; paper's WeChat logs unavailable)",
         "config": {"workload": f"serving: {wl.n_ads} ads x 64-d (BF16 scan + FP32 master), "
                                f"{wl.n_postings} postings, F ~ U{{4..128}}, K in {{100, 500, 2000}}, "
-                               "Poisson arrivals, 4 GiB scratch, max batch 256, 2 batches in flight",
+                               f"Poisson arrivals, {args.serve_scratch_gib:g} GiB scratch, max batch 256, 2 batches in flight",
                    "max_wait_us": args.max_wait_us, "scratch_bytes": scratch},
         "p50_ms": best["p50_ms"] if best else None,
         "p99_ms": best["p99_ms"] if best else None,
