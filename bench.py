@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--max-wait-us", type=int, default=300)
     ap.add_argument("--serve-scratch-gib", type=float, default=8.0,
                     help="scratch budget of the serving loop (split between two batches in flight)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (default launch shapes)")
     ap.add_argument("--batch-steps", type=int, default=5,
                     help="timed batches of the 4096-query uneven batch (0: skip)")
     args = ap.parse_args()
@@ -122,6 +124,15 @@ def main():
 
     def step():
         return ix.score_topk(U, wl.feat_offsets, wl.feat_keys, wl.k, wl.feat_mult, out=out)
+
+    # launch shape of this batch from the autotuner (recorded in the index, used by step())
+    tune = None
+    if not args.no_tune:
+        rep, _ = ix.autotune(U, wl.feat_offsets, wl.feat_keys, wl.k, wl.feat_mult, reps=3)
+        tune = {"shape": rep["best"], "default_ms": rep["default_ms"], "best_ms": rep["best_ms"],
+                "tried": len(rep["tried"])}
+        log(f"[bench] autotune: {rep['best']} {rep['best_ms']:.3f} ms (default {rep['default_ms']:.3f} ms, "
+            f"{len(rep['tried'])} shapes)")
 
     E.set_timing(True)
     for i in range(args.warmup):
@@ -211,30 +222,52 @@ def main():
         nb = int(wb.k.sum())
         outb = (torch.empty(nb, dtype=torch.int32, device=dev), torch.empty(nb, dtype=torch.float32, device=dev))
 
-        def bstep():
+        btune = None
+        if not args.no_tune:
+            rep, _ = ix.autotune(Ub, wb.feat_offsets, wb.feat_keys, wb.k, wb.feat_mult,
+                                 scan_dtype=E.BF16, rescore_factor=4, reps=2)
+            btune = {"shape": rep["best"], "default_ms": rep["default_ms"], "best_ms": rep["best_ms"],
+                     "tried": len(rep["tried"])}
+            log(f"[bench] autotune 4096: {rep['best']} {rep['best_ms']:.2f} ms "
+                f"(default {rep['default_ms']:.2f} ms)")
+        graph = E.Graph()
+
+        def bstep(g=None):
             return ix.score_topk(Ub, wb.feat_offsets, wb.feat_keys, wb.k, wb.feat_mult,
-                                 scan_dtype=E.BF16, rescore_factor=4, out=outb)
-        bstep()
-        torch.cuda.synchronize()
-        tt = []
-        t1 = time.perf_counter()
-        for i in range(args.batch_steps):
-            bstep()
-            tt.append(E.last_timings())
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t1
+                                 scan_dtype=E.BF16, rescore_factor=4, out=outb, graph=g)
+
+        def timed(g):
+            bstep(g)
+            torch.cuda.synchronize()
+            tt = []
+            t1 = time.perf_counter()
+            for i in range(args.batch_steps):
+                bstep(g)
+                if g is None:
+                    tt.append(E.last_timings())
+            torch.cuda.synchronize()
+            return time.perf_counter() - t1, tt
+
+        el_e, tt = timed(None)      # eager launches, per-phase HIP-event times
+        el, _ = timed(graph)        # the batch's kernels as one captured graph
         qb = wb.n_queries * args.batch_steps / el
         batching = {
             "workload": "4096 queries in one launch on the same index, F ~ U{4..128}, "
-                        "K ~ U{100..2000}, BF16 scan, 4 K rescored in FP32",
+                        "K ~ U{100..2000}, BF16 scan, 4 K rescored in FP32; autotuned launch "
+                        "shape, kernels captured in a HIP graph",
             "queries_per_s": qb, "ads_scored_per_s": qb * N, "ms_per_batch": 1000 * el / args.batch_steps,
+            "eager_queries_per_s": wb.n_queries * args.batch_steps / el_e,
+            "eager_ms_per_batch": 1000 * el_e / args.batch_steps,
+            "graph": graph.stats(), "autotune": btune,
             "feature_pairs": int(wb.feat_offsets[-1]), "sum_k": nb,
             "uncertified_queries_per_batch": float(np.mean([t["uncertified"] for t in tt])),
             "phases_ms": {k: float(np.mean([t[k] for t in tt]))
                           for k in ("host_ms", "decode_ms", "sample_ms", "score_ms", "finalize_ms", "rescore_ms")},
             "rounds_max": max(t["rounds"] for t in tt),
         }
-        log(f"[bench] batching 4096: {qb:.0f} queries/s ({1000 * el / args.batch_steps:.1f} ms/batch)")
+        graph.close()
+        log(f"[bench] batching 4096: {qb:.0f} queries/s ({1000 * el / args.batch_steps:.1f} ms/batch graph, "
+            f"{1000 * el_e / args.batch_steps:.1f} ms eager)")
 
     cpu = None
     if args.cpu_queries != 0:
@@ -279,6 +312,7 @@ def main():
         "p99_ms": float(np.percentile(lat, 99) * 1000),
         "phases_ms": phase,
         "selection_rounds_max": rounds,
+        "autotune": tune,
         "roofline": {"kernel": "k_score (fused deep+wide+select)", "bound": "mfma",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),

@@ -54,7 +54,7 @@ typedef enum {
 /* Arithmetic type of the ad-embedding scan. */
 typedef enum { EBR_F32 = 0, EBR_BF16 = 1, EBR_FP8E4M3 = 2 } ebr_dtype;
 
-typedef struct ebr_index ebr_index; /* opaque; immutable after build */
+typedef struct ebr_index ebr_index; /* opaque; immutable after build but for its launch shapes */
 
 /* ------------------------------------------------------------------------ index */
 
@@ -186,6 +186,104 @@ ebr_status ebr_score_topk(const ebr_index* index, const ebr_batch* batch, void* 
 ebr_status ebr_score_dense(const ebr_index* index, const ebr_batch* batch, void* ws,
                            size_t ws_bytes, float* deep, float* wide, void* hip_stream);
 
+/* ------------------------------------------------------------------------ launch shapes */
+
+/*
+ * How a batch's work is divided among work-groups. Section 3.4 (with Algorithm 2)
+ * hands every thread an equal share of the posting work; here the shares are
+ *  score_ranges   contiguous ranges of 32-ad tiles per query group in the candidate
+ *                 scan: one work-group per (range, group); 0 = one work-group per
+ *                 compute unit, ranges rounded down to a multiple of 8 (one range's
+ *                 work-groups then share an XCD and its L2)
+ *  sample_ranges  the same for the threshold pre-pass over the sample tiles
+ *  decode_chunks  64-posting chunks one decode wavefront takes, 1..64 (0 = 8)
+ * Any shape gives bit-identical results (the cross term is an exact fixed-point sum
+ * and the outputs are sorted); only the time changes. Ranges are clamped to the
+ * number of tiles; score_ranges * query groups must stay <= 2^24.
+ */
+typedef struct {
+    int32_t score_ranges;
+    int32_t sample_ranges;
+    int32_t decode_chunks;
+} ebr_launch_shape;
+
+#define EBR_TUNE_MAX 16
+
+/*
+ * Autotuner report: the shapes tried, in order, with the median device time of the
+ * whole batch (decode through rescore, HIP events on the call's stream) under each;
+ * tried[0] is the default shape. best is the fastest; best_ms its time.
+ */
+typedef struct {
+    int32_t n_tried;
+    ebr_launch_shape tried[EBR_TUNE_MAX];
+    float tried_ms[EBR_TUNE_MAX];
+    ebr_launch_shape best;
+    float best_ms;
+    float default_ms;
+} ebr_tune_report;
+
+/*
+ * Autotuner. Runs `batch` (as ebr_score_topk, same workspace and outputs) under the
+ * default shape and then under candidate shapes, one field at a time (score ranges
+ * at 1, 2 and 4 work-groups per compute unit; then sample ranges; then 4, 8, 16 and
+ * 32 decode chunks per wavefront), `reps` timed runs each (<= 0: 3) after one
+ * untimed run, keeping each field's fastest value. The winner is recorded in the
+ * index for batches with the same scan dtype and the same number of query groups
+ * (256 queries each at d <= 64, 128 above); ebr_score_topk, ebr_score_topk_graph and
+ * the serving loop then use it. The outputs hold the batch's results on return.
+ * The index's table is guarded by a mutex: tuning may overlap other calls.
+ * Errors as ebr_score_topk; out may be NULL.
+ */
+ebr_status ebr_autotune(ebr_index* index, const ebr_batch* batch, void* ws, size_t ws_bytes,
+                        uint32_t* out_ids, float* out_scores, int32_t reps, void* hip_stream,
+                        ebr_tune_report* out);
+
+/*
+ * Set (shape non-NULL) or clear (NULL) the recorded shape for batches of n_queries
+ * queries on scan_dtype, or read the shape such a batch would use (zero fields: the
+ * default). EBR_EINVAL: n_queries < 1, an unknown dtype, fields out of range.
+ */
+ebr_status ebr_set_launch_shape(ebr_index* index, ebr_dtype scan_dtype, int32_t n_queries,
+                                const ebr_launch_shape* shape);
+ebr_status ebr_get_launch_shape(const ebr_index* index, ebr_dtype scan_dtype, int32_t n_queries,
+                                ebr_launch_shape* out);
+
+/* ------------------------------------------------------------------------ graphs */
+
+/*
+ * A batch's device work as one HIP graph. ebr_score_topk_graph plans the batch on
+ * the host like ebr_score_topk and copies the plan to the device on hip_stream (from
+ * the handle's pinned staging); it records the batch's kernel sequence (decode,
+ * pre-pass, the gated selection rounds, and for reduced-precision scans the exact
+ * rescore) by stream capture on the handle's own stream, loads it into the handle's
+ * executable graph (an in-place update when the sequence has the same nodes as the
+ * last one, else a new instantiation) and launches that on hip_stream. What follows the graph is as in ebr_score_topk and
+ * rare: extra selection rounds, and the FP32 rerun of queries whose recall
+ * certificate failed. Results are bit-identical to ebr_score_topk's.
+ * The handle owns a HIP stream of the device current at create (default priority),
+ * the executable graph and pinned host staging that grows to the largest plan seen
+ * (hipHostMalloc); it allocates no device memory. A handle serves one call at a
+ * time (calls block until their results are complete, so consecutive calls on one
+ * thread are fine); give each thread its own. Per-phase timings are not recorded
+ * for graph calls.
+ */
+typedef struct ebr_graph ebr_graph; /* opaque */
+
+typedef struct {
+    uint64_t calls;           /* ebr_score_topk_graph calls that launched a graph */
+    uint64_t instantiations;  /* new executable graphs */
+    uint64_t updates;         /* in-place updates of the executable graph */
+    uint64_t nodes;           /* nodes of the last recorded sequence */
+} ebr_graph_info;
+
+ebr_status ebr_graph_create(ebr_graph** out);
+ebr_status ebr_score_topk_graph(ebr_graph* graph, const ebr_index* index, const ebr_batch* batch,
+                                void* ws, size_t ws_bytes, uint32_t* out_ids, float* out_scores,
+                                void* hip_stream);
+ebr_status ebr_graph_stats(const ebr_graph* graph, ebr_graph_info* out);
+void ebr_graph_destroy(ebr_graph* graph);
+
 /* ------------------------------------------------------------------------ timing */
 
 /*
@@ -242,6 +340,10 @@ typedef struct ebr_server ebr_server; /* opaque */
  *                queued; < 0: 0)
  *  pipeline      batches in flight, 1..4 (0: 2)
  *  scan_dtype, rescore_factor   as in ebr_batch, for every query
+ *  graph         nonzero: each slot runs its batches through its own ebr_graph
+ *                handle (ebr_score_topk_graph) instead of launching them eagerly
+ * Batches use the launch shape recorded in the index (ebr_autotune) for their
+ * dtype and query-group count.
  */
 typedef struct {
     int32_t max_batch;
@@ -249,6 +351,7 @@ typedef struct {
     int32_t pipeline;
     ebr_dtype scan_dtype;
     int32_t rescore_factor;
+    int32_t graph;
 } ebr_server_opts;
 
 /*

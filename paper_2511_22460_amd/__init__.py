@@ -29,7 +29,9 @@ EXPORTS = ("ebr_index_size", "ebr_build_index", "ebr_index_stats", "ebr_decode_k
            "ebr_codec_size", "ebr_codec_encode", "ebr_codec_decode", "ebr_last_error",
            "ebr_version", "ebr_set_timing", "ebr_get_timings", "ebr_quantize_bf16",
            "ebr_quantize_fp8", "ebr_dequantize_fp8", "ebr_server_create", "ebr_submit",
-           "ebr_poll", "ebr_server_stats", "ebr_server_reset_stats", "ebr_server_destroy")
+           "ebr_poll", "ebr_server_stats", "ebr_server_reset_stats", "ebr_server_destroy",
+           "ebr_autotune", "ebr_set_launch_shape", "ebr_get_launch_shape", "ebr_graph_create",
+           "ebr_score_topk_graph", "ebr_graph_stats", "ebr_graph_destroy")
 
 
 class EbrError(RuntimeError):
@@ -89,10 +91,41 @@ class Batch(ctypes.Structure):
                 ("scan_dtype", ctypes.c_int), ("rescore_factor", ctypes.c_int32)]
 
 
+class LaunchShape(ctypes.Structure):
+    _fields_ = [("score_ranges", ctypes.c_int32), ("sample_ranges", ctypes.c_int32),
+                ("decode_chunks", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+TUNE_MAX = 16
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("n_tried", ctypes.c_int32), ("tried", LaunchShape * TUNE_MAX),
+                ("tried_ms", ctypes.c_float * TUNE_MAX), ("best", LaunchShape),
+                ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float)]
+
+    def as_dict(self):
+        n = self.n_tried
+        return {"tried": [(self.tried[i].as_dict(), float(self.tried_ms[i])) for i in range(n)],
+                "best": self.best.as_dict(), "best_ms": float(self.best_ms),
+                "default_ms": float(self.default_ms)}
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_uint64), ("instantiations", ctypes.c_uint64),
+                ("updates", ctypes.c_uint64), ("nodes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("max_wait_us", ctypes.c_int32),
                 ("pipeline", ctypes.c_int32), ("scan_dtype", ctypes.c_int),
-                ("rescore_factor", ctypes.c_int32)]
+                ("rescore_factor", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class Query(ctypes.Structure):
@@ -157,6 +190,13 @@ def load():
         "ebr_server_stats": ([P, P], st),
         "ebr_server_reset_stats": ([P], st),
         "ebr_server_destroy": ([P], st),
+        "ebr_autotune": ([P, P, P, sz, P, P, i32, P, P], st),
+        "ebr_set_launch_shape": ([P, ctypes.c_int, i32, P], st),
+        "ebr_get_launch_shape": ([P, ctypes.c_int, i32, P], st),
+        "ebr_graph_create": ([ctypes.POINTER(P)], st),
+        "ebr_score_topk_graph": ([P, P, P, P, sz, P, P, P], st),
+        "ebr_graph_stats": ([P, P], st),
+        "ebr_graph_destroy": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(h, name)
@@ -347,9 +387,11 @@ class Index:
         return n.value
 
     def score_topk(self, user_emb, feat_offsets, feat_keys, k, feat_mult=None,
-                   scan_dtype: int = F32, rescore_factor: int = 4, out=None, stream=None):
+                   scan_dtype: int = F32, rescore_factor: int = 4, out=None, stream=None,
+                   graph: Optional["Graph"] = None):
         """Top-K per query. Returns (ids int32 tensor [sum K], scores float32 tensor [sum K],
-        offsets np.int64 [B + 1]); ids are uint32 values stored in int32 (N < 2^31 here)."""
+        offsets np.int64 [B + 1]); ids are uint32 values stored in int32 (N < 2^31 here).
+        With a Graph handle the batch's device work runs as one captured HIP graph."""
         import torch
         b, keep = self._batch(user_emb, feat_offsets, feat_keys, feat_mult, k, scan_dtype,
                               rescore_factor)
@@ -363,20 +405,65 @@ class Index:
         else:
             ids, scores = out
         lib = load()
+        if graph is None:
+            def call(wp, wn):
+                return lib.ebr_score_topk(self._h, ctypes.byref(b), wp, wn, ids.data_ptr(),
+                                          scores.data_ptr(), _stream(stream))
+        else:
+            def call(wp, wn):
+                return lib.ebr_score_topk_graph(graph._h, self._h, ctypes.byref(b), wp, wn,
+                                                ids.data_ptr(), scores.data_ptr(), _stream(stream))
         # the kept workspace is tried first; it grows (one sizing call) only when too small
         ws = self._ws
-        rc = lib.ebr_score_topk(self._h, ctypes.byref(b), ws.data_ptr() if ws is not None else None,
-                                ws.numel() if ws is not None else 0, ids.data_ptr(),
-                                scores.data_ptr(), _stream(stream))
+        rc = call(ws.data_ptr() if ws is not None else None, ws.numel() if ws is not None else 0)
         if rc == EBR_ENOMEM and lib.ebr_last_error().startswith(b"workspace too small"):
             n = ctypes.c_size_t()
             _check(lib.ebr_workspace_size(self._h, ctypes.byref(b), ctypes.byref(n)),
                    "ebr_workspace_size")
             ws = self.workspace(n.value)
-            rc = lib.ebr_score_topk(self._h, ctypes.byref(b), ws.data_ptr(), ws.numel(),
-                                    ids.data_ptr(), scores.data_ptr(), _stream(stream))
-        _check(rc, "ebr_score_topk")
+            rc = call(ws.data_ptr(), ws.numel())
+        _check(rc, "ebr_score_topk" if graph is None else "ebr_score_topk_graph")
         return ids[:total], scores[:total], offs
+
+    def autotune(self, user_emb, feat_offsets, feat_keys, k, feat_mult=None,
+                 scan_dtype: int = F32, rescore_factor: int = 4, reps: int = 3, stream=None):
+        """Autotune the launch shape on this batch (ebr_autotune) and record it in the index
+        for batches of the same dtype and query-group count. Returns the report as a dict and
+        the batch's results (ids, scores, offsets)."""
+        import torch
+        b, keep = self._batch(user_emb, feat_offsets, feat_keys, feat_mult, k, scan_dtype,
+                              rescore_factor)
+        kq = keep[4]
+        offs = np.zeros(len(kq) + 1, dtype=np.int64)
+        np.cumsum(kq, out=offs[1:])
+        total = int(offs[-1])
+        ids = torch.empty(max(1, total), dtype=torch.int32, device=self.device)
+        scores = torch.empty(max(1, total), dtype=torch.float32, device=self.device)
+        n = ctypes.c_size_t()
+        _check(load().ebr_workspace_size(self._h, ctypes.byref(b), ctypes.byref(n)),
+               "ebr_workspace_size")
+        ws = self.workspace(n.value)
+        rep = TuneReport()
+        _check(load().ebr_autotune(self._h, ctypes.byref(b), ws.data_ptr(), ws.numel(),
+                                   ids.data_ptr(), scores.data_ptr(), int(reps), _stream(stream),
+                                   ctypes.byref(rep)), "ebr_autotune")
+        return rep.as_dict(), (ids[:total], scores[:total], offs)
+
+    def set_launch_shape(self, scan_dtype: int, n_queries: int, shape: Optional[dict]):
+        """Record (dict with score_ranges / sample_ranges / decode_chunks) or clear (None)
+        the launch shape of batches of n_queries queries on scan_dtype."""
+        sh = None if shape is None else LaunchShape(int(shape.get("score_ranges", 0)),
+                                                    int(shape.get("sample_ranges", 0)),
+                                                    int(shape.get("decode_chunks", 0)))
+        _check(load().ebr_set_launch_shape(self._h, scan_dtype, int(n_queries),
+                                           None if sh is None else ctypes.byref(sh)),
+               "ebr_set_launch_shape")
+
+    def launch_shape(self, scan_dtype: int, n_queries: int) -> dict:
+        sh = LaunchShape()
+        _check(load().ebr_get_launch_shape(self._h, scan_dtype, int(n_queries), ctypes.byref(sh)),
+               "ebr_get_launch_shape")
+        return sh.as_dict()
 
     def score_dense(self, user_emb, feat_offsets, feat_keys, feat_mult=None, scan_dtype: int = F32,
                     stream=None):
@@ -407,17 +494,44 @@ class Index:
         return self.score_topk(U, w.feat_offsets, w.feat_keys, w.k, w.feat_mult, **kw)
 
 
+class Graph:
+    """A captured-batch handle (ebr_graph_*): pass it to Index.score_topk(graph=...) to run a
+    batch's device work as one HIP graph. One call at a time per handle."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(load().ebr_graph_create(ctypes.byref(h)), "ebr_graph_create")
+        self._h = h
+
+    def stats(self) -> dict:
+        info = GraphInfo()
+        _check(load().ebr_graph_stats(self._h, ctypes.byref(info)), "ebr_graph_stats")
+        return info.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ebr_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Server:
     """Serving loop over a resident Index (ebr_server_*): submit single queries from host
     memory, poll for their results. The scratch arena is a torch-owned device buffer."""
 
     def __init__(self, index: "Index", scratch_bytes: int, max_batch: int = 256,
                  max_wait_us: int = 200, pipeline: int = 2, scan_dtype: int = F32,
-                 rescore_factor: int = 4):
+                 rescore_factor: int = 4, graph: bool = False):
         import torch
         self.index = index
         self.scratch = torch.empty(max(256, int(scratch_bytes)), dtype=torch.uint8, device=index.device)
-        opts = ServerOpts(max_batch, max_wait_us, pipeline, scan_dtype, rescore_factor)
+        opts = ServerOpts(max_batch, max_wait_us, pipeline, scan_dtype, rescore_factor,
+                          1 if graph else 0)
         h = ctypes.c_void_p()
         _check(load().ebr_server_create(index._h, self.scratch.data_ptr(), self.scratch.numel(),
                                         ctypes.byref(opts), ctypes.byref(h)), "ebr_server_create")

@@ -54,7 +54,7 @@ struct PhaseClock {
     bool on = false;
     hipStream_t st = nullptr;
     std::vector<hipEvent_t> ev;
-    explicit PhaseClock(hipStream_t s) : on(g_timing.load() != 0), st(s) {}
+    PhaseClock(hipStream_t s, bool enable) : on(enable), st(s) {}
     ~PhaseClock() { for (hipEvent_t e : ev) (void)hipEventDestroy(e); }
     int mark() {  // returns the event index, or -1 when timing is off
         if (!on) return -1;
@@ -808,6 +808,9 @@ static std::vector<char> pack_plan(const Plan& P) {
     return blob;
 }
 
+// Chunks one decode wavefront takes unless a launch shape says otherwise.
+static constexpr int kDefaultDecodeChunks = 8;
+
 static int score_ctas() {
     static std::atomic<int> ctas{0};
     int c = ctas.load(std::memory_order_relaxed);
@@ -831,10 +834,10 @@ static int score_ctas() {
     } while (0)
 
 // Upload the plan, decode the batch's lists into tile buckets. Shared by top-K and dense.
+// The plan bytes (pack_plan) are uploaded from src first unless src is null (already there).
 static ebr_status run_decode(const Index& ix, const Plan& P, char* ws, hipStream_t st,
-                             std::vector<char>& blob) {
-    blob = pack_plan(P);
-    HIP_TRY(hipMemcpyAsync(ws + P.off_plan, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
+                             const char* src, size_t n_src, int chunks_per_wave) {
+    if (src) HIP_TRY(hipMemcpyAsync(ws + P.off_plan, src, n_src, hipMemcpyHostToDevice, st));
     uint32_t* stcnt = (uint32_t*)(ws + P.off_stcnt);
     uint32_t* stoff = (uint32_t*)(ws + P.off_stoff);
     uint32_t* stfill = (uint32_t*)(ws + P.off_stfill);
@@ -849,6 +852,7 @@ static ebr_status run_decode(const Index& ix, const Plan& P, char* ws, hipStream
     d.uk_wshift = (const int32_t*)(ws + P.o_ukw);
     d.n_ukeys = P.nu;
     d.total_chunks = P.total_chunks;
+    d.chunks_per_wave = (uint32_t)chunks_per_wave;
     d.n_tiles = ix.n_tiles;
     d.n_super = P.n_super;
     d.st_cnt = stcnt;
@@ -900,8 +904,86 @@ static ebr_status check_users(const ebr_batch* bt, int B, int dim, hipStream_t s
     return EBR_OK;
 }
 
+// Launch shape of a batch: the override, else the one recorded for (dtype, query groups),
+// else zeros (the defaults).
+static ebr_launch_shape shape_for(const Index& ix, int dtype, int nqg, const ebr_launch_shape* over) {
+    if (over) return *over;
+    std::lock_guard<std::mutex> lk(ix.shape_mu);
+    auto it = ix.shapes.find({dtype, nqg});
+    return it == ix.shapes.end() ? ebr_launch_shape{} : it->second;
+}
+
+// The shape's fields with the defaults filled in, for a batch of nqg query groups.
+static ebr_launch_shape effective_shape(const Index& ix, const ebr_launch_shape& sh, int64_t n_sample,
+                                        int nqg) {
+    ebr_launch_shape e = sh;
+    if (e.score_ranges <= 0) e.score_ranges = score_ranges((int)ix.n_tiles, nqg, score_ctas());
+    if (e.sample_ranges <= 0) e.sample_ranges = score_ranges((int)std::max<int64_t>(1, n_sample), nqg, score_ctas());
+    if (e.decode_chunks <= 0) e.decode_chunks = kDefaultDecodeChunks;
+    return e;
+}
+
+}  // namespace ebr
+
+// A captured batch sequence: the capture stream, the executable graph, pinned plan staging.
+struct ebr_graph {
+    int device = 0;
+    hipStream_t cs = nullptr;
+    hipGraphExec_t exec = nullptr;
+    char* pinned = nullptr;
+    size_t pinned_cap = 0;
+    ebr_graph_info info{};
+    std::mutex mu;
+};
+
+namespace ebr {
+
+// Load a captured sequence into the handle's executable graph (in place when only
+// parameters changed) and launch it on s. Consumes `graph`.
+static ebr_status graph_launch(ebr_graph* g, hipGraph_t graph, hipStream_t s) {
+    size_t n = 0;
+    if (hipGraphGetNodes(graph, nullptr, &n) != hipSuccess) n = 0;
+    bool loaded = false;
+    if (g->exec && n == g->info.nodes) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult r = hipGraphExecUpdateError;
+        if (hipGraphExecUpdate(g->exec, graph, &bad, &r) == hipSuccess && r == hipGraphExecUpdateSuccess) {
+            loaded = true;
+            g->info.updates++;
+        } else {
+            (void)hipGetLastError();  // the update's refusal is not an error of the call
+        }
+    }
+    if (!loaded) {
+        if (g->exec) {
+            (void)hipGraphExecDestroy(g->exec);
+            g->exec = nullptr;
+        }
+        hipError_t e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            g->exec = nullptr;
+            (void)hipGraphDestroy(graph);
+            set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e));
+            return EBR_EDEVICE;
+        }
+        g->info.instantiations++;
+    }
+    g->info.nodes = n;
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(hipGraphLaunch(g->exec, s));
+    g->info.calls++;
+    return EBR_OK;
+}
+
+struct TopkOpts {
+    ebr_graph* graph = nullptr;             // capture the device sequence into this handle
+    const ebr_launch_shape* shape = nullptr; // replaces the recorded shape
+    bool force_timing = false;              // record phase times whatever ebr_set_timing says
+};
+
 static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, size_t ws_bytes,
-                            uint32_t* out_ids, float* out_scores, hipStream_t s, ebr_timings* tm) {
+                            uint32_t* out_ids, float* out_scores, hipStream_t s, ebr_timings* tm,
+                            const TopkOpts& opt = TopkOpts{}) {
     const auto t_host = std::chrono::steady_clock::now();
     Plan P;
     ebr_status st = plan_batch(ix, batch, true, &P);
@@ -912,13 +994,34 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
     if (n_out > 0 && (!out_ids || !out_scores)) { set_error("NULL output"); return EBR_EINVAL; }
     if (P.B == 0 || P.kmax == 0) return EBR_OK;
     const bool approx = P.dtype != EBR_F32;
+    const int64_t ns = (int64_t)P.sample_tiles.size();
+    const ebr_launch_shape sh =
+        effective_shape(ix, shape_for(ix, P.dtype, P.n_qg, opt.shape), ns, P.n_qg);
+    if (sh.score_ranges < 1 || sh.sample_ranges < 1 || sh.decode_chunks < 1 || sh.decode_chunks > 64) {
+        set_error("launch shape out of range");
+        return EBR_EINVAL;
+    }
+    std::vector<char> blob = pack_plan(P);
+    const char* src = blob.data();
+    ebr_graph* g = opt.graph;
+    hipStream_t ls = s;  // the stream the device sequence is enqueued (or captured) on
+    if (g) {
+        if (g->pinned_cap < blob.size()) {
+            if (g->pinned) (void)hipHostFree(g->pinned);
+            g->pinned = nullptr;
+            g->pinned_cap = 0;
+            const size_t cap = std::max<size_t>(blob.size() + blob.size() / 4, 1 << 20);
+            HIP_TRY(hipHostMalloc((void**)&g->pinned, cap, hipHostMallocDefault));
+            g->pinned_cap = cap;
+        }
+        std::memcpy(g->pinned, blob.data(), blob.size());
+        // the plan goes up on the caller's stream ahead of the graph, which holds kernels only
+        HIP_TRY(hipMemcpyAsync(ws + P.off_plan, g->pinned, blob.size(), hipMemcpyHostToDevice, s));
+        src = nullptr;
+        ls = g->cs;
+    }
     const double host_ms = ms_since(t_host);
-    PhaseClock clk(s);
-    const int e_dec0 = clk.mark();
-    std::vector<char> blob;
-    st = run_decode(ix, P, ws, s, blob);
-    if (st) return st;
-    const int e_dec1 = clk.mark();
+    PhaseClock clk(ls, !g && (opt.force_timing || g_timing.load() != 0));
 
     const int B = P.B;
     uint32_t* thr = (uint32_t*)(ws + P.off_thr);
@@ -926,36 +1029,16 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
     uint32_t* active = (uint32_t*)(ws + P.off_active);
     uint32_t* ccnt = (uint32_t*)(ws + P.off_ccnt);
     uint32_t* unres = (uint32_t*)(ws + P.off_unres);
+    uint32_t* unc = (uint32_t*)(ws + P.off_unc);
     Control* ctl = (Control*)(ws + P.off_ctl);
     unsigned long long* cand = (unsigned long long*)(ws + P.off_cand);
-    const int64_t ns = (int64_t)P.sample_tiles.size();
 
-    // per-query set-up on the device: user rows finite, status / activity, certificate eps
-    LAUNCH(launch_fill_u32((uint32_t*)ctl, 0u, (int64_t)(sizeof(Control) / 4), s));
-    PrepArgs pa{};
-    pa.user = batch->user_emb;
-    pa.n_queries = B;
-    pa.dim = ix.dim;
-    pa.kq = (const int32_t*)(ws + P.o_kq);
-    pa.aq = (const double*)(ws + P.o_aq);
-    pa.status = status;
-    pa.active = active;
-    pa.eps = approx ? (float*)(ws + P.off_eps) : nullptr;
-    const int cq = P.dtype == EBR_BF16 ? 0 : 1;
-    pa.q_err2 = ix.q_err2[cq];
-    pa.q_norm2 = ix.q_norm2[cq];
-    pa.e_norm2 = ix.e_norm2;
-    pa.ctl = ctl;
-    LAUNCH(launch_prep(pa, s));
-
-    // sample pass and per-query threshold (for K' candidates on approximate scans)
     ScoreArgs sa = score_args(ix, P, batch, ws);
     sa.ctl = ctl;
     sa.n_work = (int32_t)ns;
     sa.tile_list = (const uint32_t*)(ws + P.o_st);
     sa.sample_keys = (uint32_t*)(ws + P.off_skeys);
     sa.sample_ld = ns * kTileAds;
-    LAUNCH(launch_score(sa, ix.dim, 1, score_ctas(), s));
     SelectArgs se{};
     se.keys = sa.sample_keys;
     se.ld = sa.sample_ld;
@@ -968,9 +1051,6 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
     se.only_status = -1;
     se.thresh = thr;
     se.ctl = ctl;
-    LAUNCH(launch_select(se, B, s));
-    const int e_smp1 = clk.mark();
-
     ScoreArgs ca = score_args(ix, P, batch, ws);
     ca.ctl = ctl;
     ca.thresh = thr;
@@ -1000,38 +1080,116 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
         fa.r_stilde = (float*)(ws + P.off_rst);
         fa.r_ld = std::max(1, P.kcmax);
     }
+    RescoreArgs ra{};
+    ra.ctl = ctl;
+    ra.emb = ix.emb_f32;
+    ra.user = batch->user_emb;
+    ra.n_ads = ix.n_ads;
+    ra.kq = fa.kq;
+    ra.kcnt = fa.kcnt;
+    ra.status = status;
+    ra.uncertified = unc;
+    ra.r_id = fa.r_id;
+    ra.r_wide = fa.r_wide;
+    ra.r_stilde = fa.r_stilde;
+    ra.eps = (const float*)(ws + P.off_eps);
+    ra.r_ld = fa.r_ld;
+    ra.out_off = fa.out_off;
+    ra.out_ids = out_ids;
+    ra.out_scores = out_scores;
 
-    // Selection rounds, enqueued without host synchronisation: round r > 0 runs only if round
-    // r - 1 left a query unresolved. Queries short of K' candidates first take the sample's
-    // K'-th key (which at least K' sample ads reach), then no threshold at all; overflowing
-    // queries take the K'-th largest stored key.
+    int e_dec0 = -1, e_dec1 = -1, e_smp1 = -1, e_rs0 = -1, e_rs1 = -1;
     std::vector<std::array<int, 3>> round_marks;
-    for (int r = 0; r < kMaxRounds; ++r) {
-        const uint32_t* gate = r == 0 ? nullptr : &ctl->unres[r - 1];
-        if (r > 0) {
-            se.gate = gate;
-            se.round = r;
-            se.only_status = kStatusNeedLower;
-            LAUNCH(launch_select(se, B, s));
+    // The device sequence of the batch, enqueued on ls without host synchronisation.
+    auto enqueue = [&]() -> ebr_status {
+        e_dec0 = clk.mark();
+        ebr_status r = run_decode(ix, P, ws, ls, src, blob.size(), sh.decode_chunks);
+        if (r) return r;
+        e_dec1 = clk.mark();
+        // per-query set-up on the device: user rows finite, status / activity, certificate eps
+        LAUNCH(launch_fill_u32((uint32_t*)ctl, 0u, (int64_t)(sizeof(Control) / 4), ls));
+        PrepArgs pa{};
+        pa.user = batch->user_emb;
+        pa.n_queries = B;
+        pa.dim = ix.dim;
+        pa.kq = (const int32_t*)(ws + P.o_kq);
+        pa.aq = (const double*)(ws + P.o_aq);
+        pa.status = status;
+        pa.active = active;
+        pa.eps = approx ? (float*)(ws + P.off_eps) : nullptr;
+        const int cq = P.dtype == EBR_BF16 ? 0 : 1;
+        pa.q_err2 = ix.q_err2[cq];
+        pa.q_norm2 = ix.q_norm2[cq];
+        pa.e_norm2 = ix.e_norm2;
+        pa.ctl = ctl;
+        LAUNCH(launch_prep(pa, ls));
+        // sample pass and per-query threshold (for K' candidates on approximate scans)
+        LAUNCH(launch_score(sa, ix.dim, 1, sh.sample_ranges, ls));
+        LAUNCH(launch_select(se, B, ls));
+        e_smp1 = clk.mark();
+        // Selection rounds: round r > 0 runs only if round r - 1 left a query unresolved.
+        // Queries short of K' candidates first take the sample's K'-th key (which at least
+        // K' sample ads reach), then no threshold at all; overflowing queries take the
+        // K'-th largest stored key.
+        for (int rr = 0; rr < kMaxRounds; ++rr) {
+            const uint32_t* gate = rr == 0 ? nullptr : &ctl->unres[rr - 1];
+            if (rr > 0) {
+                se.gate = gate;
+                se.round = rr;
+                se.only_status = kStatusNeedLower;
+                LAUNCH(launch_select(se, B, ls));
+            }
+            LAUNCH(launch_round_reset(ccnt, B, gate, ls));
+            ca.gate = gate;
+            fa.gate = gate;
+            fa.unresolved = &ctl->unres[rr];
+            const int e0 = clk.mark();
+            LAUNCH(launch_score(ca, ix.dim, 0, sh.score_ranges, ls));
+            const int e1 = clk.mark();
+            LAUNCH(launch_finalize(fa, B, ls));
+            const int e2 = clk.mark();
+            round_marks.push_back({e0, e1, e2});
         }
-        LAUNCH(launch_round_reset(ccnt, B, gate, s));
-        ca.gate = gate;
-        fa.gate = gate;
-        fa.unresolved = &ctl->unres[r];
-        const int e0 = clk.mark();
-        LAUNCH(launch_score(ca, ix.dim, 0, score_ctas(), s));
-        const int e1 = clk.mark();
-        LAUNCH(launch_finalize(fa, B, s));
-        const int e2 = clk.mark();
-        round_marks.push_back({e0, e1, e2});
+        if (approx) {
+            // exact FP32 rescore of the K' candidates, top K, recall certificate; skipped
+            // while a query is still unresolved (then it runs after the extra rounds)
+            LAUNCH(launch_fill_u32(unc, 0u, 1, ls));
+            ra.skip = &ctl->unres[kMaxRounds - 1];
+            e_rs0 = clk.mark();
+            LAUNCH(launch_rescore(ra, ix.dim, B, ls));
+            e_rs1 = clk.mark();
+        }
+        return EBR_OK;
+    };
+
+    if (g) {
+        std::lock_guard<std::mutex> lk(g->mu);
+        HIP_TRY(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
+        const ebr_status r = enqueue();
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ls, &graph);
+        if (r || ec != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            if (!r) set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+            return r ? r : EBR_EDEVICE;
+        }
+        st = graph_launch(g, graph, s);
+        if (st) return st;
+    } else {
+        st = enqueue();
+        if (st) return st;
     }
+
     Control hc{};
+    uint32_t nunc = 0;
     HIP_TRY(hipMemcpyAsync(&hc, ctl, sizeof(Control), hipMemcpyDeviceToHost, s));
+    if (approx) HIP_TRY(hipMemcpyAsync(&nunc, unc, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (hc.error & 1u) { set_error("non-finite user embedding in the batch"); return EBR_EINVAL; }
     int rounds_run = 1;
     for (int r = 0; r + 1 < kMaxRounds; ++r) rounds_run += hc.unres[r] > 0 ? 1 : 0;
     // rare: still unresolved after the enqueued rounds; continue round by round
+    const bool extra = hc.unres[kMaxRounds - 1] > 0;
     for (int r = kMaxRounds; hc.unres[kMaxRounds - 1] > 0; ++r) {
         if (r >= 64) { set_error("top-K selection did not converge"); return EBR_EDEVICE; }
         se.gate = nullptr;
@@ -1043,7 +1201,7 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
         fa.gate = nullptr;
         LAUNCH(launch_fill_u32(unres, 0u, 1, s));
         fa.unresolved = unres;
-        LAUNCH(launch_score(ca, ix.dim, 0, score_ctas(), s));
+        LAUNCH(launch_score(ca, ix.dim, 0, sh.score_ranges, s));
         LAUNCH(launch_finalize(fa, B, s));
         uint32_t left = 0;
         HIP_TRY(hipMemcpyAsync(&left, unres, 4, hipMemcpyDeviceToHost, s));
@@ -1051,38 +1209,14 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
         ++rounds_run;
         hc.unres[kMaxRounds - 1] = left;
     }
-
-    int e_rs0 = -1, e_rs1 = -1;
-    int n_unc = 0;
-    if (approx) {
-        // exact FP32 rescore of the K' candidates, top K, recall certificate
-        uint32_t* unc = (uint32_t*)(ws + P.off_unc);
+    if (approx && extra) {
+        ra.skip = nullptr;
         LAUNCH(launch_fill_u32(unc, 0u, 1, s));
-        RescoreArgs ra{};
-        ra.ctl = ctl;
-        ra.emb = ix.emb_f32;
-        ra.user = batch->user_emb;
-        ra.n_ads = ix.n_ads;
-        ra.kq = fa.kq;
-        ra.kcnt = fa.kcnt;
-        ra.status = status;
-        ra.uncertified = unc;
-        ra.r_id = fa.r_id;
-        ra.r_wide = fa.r_wide;
-        ra.r_stilde = fa.r_stilde;
-        ra.eps = (const float*)(ws + P.off_eps);
-        ra.r_ld = fa.r_ld;
-        ra.out_off = fa.out_off;
-        ra.out_ids = out_ids;
-        ra.out_scores = out_scores;
-        e_rs0 = clk.mark();
         LAUNCH(launch_rescore(ra, ix.dim, B, s));
-        e_rs1 = clk.mark();
-        uint32_t nunc = 0;
         HIP_TRY(hipMemcpyAsync(&nunc, unc, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        n_unc = (int)nunc;
     }
+    const int n_unc = (int)nunc;
     if (tm) {
         tm->host_ms = host_ms;
         tm->decode_ms = clk.ms(e_dec0, e_dec1);
@@ -1091,7 +1225,7 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
             tm->score_ms += clk.ms(r[0], r[1]);
             tm->finalize_ms += clk.ms(r[1], r[2]);
         }
-        tm->score_first_ms = clk.ms(round_marks[0][0], round_marks[0][1]);
+        tm->score_first_ms = round_marks.empty() ? 0.0 : clk.ms(round_marks[0][0], round_marks[0][1]);
         tm->rescore_ms = clk.ms(e_rs0, e_rs1);
         tm->rounds = rounds_run;
         tm->uncertified = n_unc;
@@ -1147,8 +1281,12 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
 }
 
 ebr_status run_topk(const Index& ix, const ebr_batch* batch, char* ws, size_t ws_bytes,
-                    uint32_t* out_ids, float* out_scores, void* stream, ebr_timings* tm) {
-    return topk_impl(ix, batch, ws, ws_bytes, out_ids, out_scores, (hipStream_t)stream, tm);
+                    uint32_t* out_ids, float* out_scores, void* stream, ebr_timings* tm,
+                    ebr_graph* graph, const ebr_launch_shape* shape) {
+    TopkOpts o;
+    o.graph = graph;
+    o.shape = shape;
+    return topk_impl(ix, batch, ws, ws_bytes, out_ids, out_scores, (hipStream_t)stream, tm, o);
 }
 
 size_t topk_workspace_bytes(const Index& ix, int dtype, BatchSizes z) {
@@ -1191,6 +1329,199 @@ ebr_status ebr_score_topk(const ebr_index* index, const ebr_batch* batch, void* 
     }
 }
 
+static bool shape_ok(const ebr_launch_shape& sh) {
+    return sh.score_ranges >= 0 && sh.score_ranges <= (1 << 24) && sh.sample_ranges >= 0 &&
+           sh.sample_ranges <= (1 << 24) && sh.decode_chunks >= 0 && sh.decode_chunks <= 64;
+}
+
+static int query_groups(const ebr_index* index, int32_t n_queries) {
+    const int gq = score_group_queries(index->dim);
+    return (int)(((int64_t)n_queries + gq - 1) / gq);
+}
+
+ebr_status ebr_set_launch_shape(ebr_index* index, ebr_dtype scan_dtype, int32_t n_queries,
+                                const ebr_launch_shape* shape) {
+    if (!index) { set_error("index is NULL"); return EBR_EINVAL; }
+    if (n_queries < 1 || scan_dtype < EBR_F32 || scan_dtype > EBR_FP8E4M3) { set_error("bad dtype or query count"); return EBR_EINVAL; }
+    if (shape && !shape_ok(*shape)) { set_error("launch shape out of range"); return EBR_EINVAL; }
+    try {
+        std::lock_guard<std::mutex> lk(index->shape_mu);
+        const std::pair<int, int> key{(int)scan_dtype, query_groups(index, n_queries)};
+        if (shape) index->shapes[key] = *shape;
+        else index->shapes.erase(key);
+    } catch (const std::bad_alloc&) {
+        set_error("host out of memory");
+        return EBR_ENOMEM;
+    }
+    return EBR_OK;
+}
+
+ebr_status ebr_get_launch_shape(const ebr_index* index, ebr_dtype scan_dtype, int32_t n_queries,
+                                ebr_launch_shape* out) {
+    if (!index || !out) { set_error("NULL argument"); return EBR_EINVAL; }
+    if (n_queries < 1 || scan_dtype < EBR_F32 || scan_dtype > EBR_FP8E4M3) { set_error("bad dtype or query count"); return EBR_EINVAL; }
+    *out = shape_for(*index, (int)scan_dtype, query_groups(index, n_queries), nullptr);
+    return EBR_OK;
+}
+
+ebr_status ebr_autotune(ebr_index* index, const ebr_batch* batch, void* ws_v, size_t ws_bytes,
+                        uint32_t* out_ids, float* out_scores, int32_t reps, void* hip_stream,
+                        ebr_tune_report* out) {
+    try {
+        if (!index) { set_error("index is NULL"); return EBR_EINVAL; }
+        const Index& ix = *index;
+        ebr_tune_report rep{};
+        if (out) *out = rep;
+        Plan P;
+        ebr_status st = plan_batch(ix, batch, true, &P);
+        if (st) return st;
+        hipStream_t s = (hipStream_t)hip_stream;
+        char* ws = (char*)ws_v;
+        TopkOpts o;
+        o.force_timing = true;
+        if (P.B == 0 || P.kmax == 0)  // nothing runs on the device: nothing to tune
+            return topk_impl(ix, batch, ws, ws_bytes, out_ids, out_scores, s, nullptr, o);
+        reps = reps <= 0 ? 3 : std::min(reps, 64);
+        const int nqg = P.n_qg;
+        const int64_t ns = (int64_t)P.sample_tiles.size();
+        // device time of the batch under a shape: the median over reps of the summed phases
+        auto run = [&](const ebr_launch_shape& sh, float* ms) -> ebr_status {
+            std::vector<double> t;
+            o.shape = &sh;
+            for (int r = 0; r < reps; ++r) {
+                ebr_timings tm{};
+                ebr_status e = topk_impl(ix, batch, ws, ws_bytes, out_ids, out_scores, s, &tm, o);
+                if (e) return e;
+                t.push_back(tm.decode_ms + tm.sample_ms + tm.score_ms + tm.finalize_ms + tm.rescore_ms);
+            }
+            std::sort(t.begin(), t.end());
+            *ms = (float)t[t.size() / 2];
+            return EBR_OK;
+        };
+        ebr_launch_shape best = effective_shape(ix, ebr_launch_shape{}, ns, nqg);
+        {
+            ebr_timings tm{};
+            o.shape = &best;
+            st = topk_impl(ix, batch, ws, ws_bytes, out_ids, out_scores, s, &tm, o);  // untimed
+            if (st) return st;
+        }
+        float best_ms = 0.0f;
+        st = run(best, &best_ms);
+        if (st) return st;
+        rep.tried[0] = best;
+        rep.tried_ms[0] = best_ms;
+        rep.default_ms = best_ms;
+        rep.n_tried = 1;
+        auto consider = [&](ebr_launch_shape c) -> ebr_status {
+            c = effective_shape(ix, c, ns, nqg);
+            if (c.score_ranges == best.score_ranges && c.sample_ranges == best.sample_ranges &&
+                c.decode_chunks == best.decode_chunks)
+                return EBR_OK;
+            if (rep.n_tried >= EBR_TUNE_MAX) return EBR_OK;
+            float ms = 0.0f;
+            const ebr_status e = run(c, &ms);
+            if (e) return e;
+            rep.tried[rep.n_tried] = c;
+            rep.tried_ms[rep.n_tried] = ms;
+            rep.n_tried++;
+            if (ms < 0.99f * best_ms) {  // 1% margin: ties keep the earlier shape
+                best = c;
+                best_ms = ms;
+            }
+            return EBR_OK;
+        };
+        const int cus = score_ctas();
+        auto ranges_at = [&](int per_cu, int64_t n_work) {
+            int R = (int)std::max<int64_t>(1, (int64_t)per_cu * cus / nqg);
+            if (R >= 8) R -= R % 8;
+            return (int)std::min<int64_t>(R, std::max<int64_t>(1, n_work));
+        };
+        for (int m : {1, 2, 4}) {
+            ebr_launch_shape c = best;
+            c.score_ranges = ranges_at(m, ix.n_tiles);
+            st = consider(c);
+            if (st) return st;
+        }
+        for (int m : {1, 2, 4}) {
+            ebr_launch_shape c = best;
+            c.sample_ranges = ranges_at(m, ns);
+            st = consider(c);
+            if (st) return st;
+        }
+        for (int dc : {4, 8, 16, 32}) {
+            ebr_launch_shape c = best;
+            c.decode_chunks = dc;
+            st = consider(c);
+            if (st) return st;
+        }
+        rep.best = best;
+        rep.best_ms = best_ms;
+        {
+            std::lock_guard<std::mutex> lk(index->shape_mu);
+            index->shapes[{P.dtype, nqg}] = best;
+        }
+        // leave the winner's results in the outputs
+        o.shape = &best;
+        st = topk_impl(ix, batch, ws, ws_bytes, out_ids, out_scores, s, nullptr, o);
+        if (st) return st;
+        if (out) *out = rep;
+        return EBR_OK;
+    } catch (const std::bad_alloc&) {
+        set_error("host out of memory");
+        return EBR_ENOMEM;
+    }
+}
+
+ebr_status ebr_graph_create(ebr_graph** out) {
+    if (!out) { set_error("NULL argument"); return EBR_EINVAL; }
+    *out = nullptr;
+    ebr_graph* g = new (std::nothrow) ebr_graph();
+    if (!g) { set_error("host out of memory"); return EBR_ENOMEM; }
+    hipError_t e = hipGetDevice(&g->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete g;
+        set_error("graph stream: %s", hipGetErrorString(e));
+        return EBR_EDEVICE;
+    }
+    *out = g;
+    return EBR_OK;
+}
+
+ebr_status ebr_score_topk_graph(ebr_graph* graph, const ebr_index* index, const ebr_batch* batch,
+                                void* ws_v, size_t ws_bytes, uint32_t* out_ids, float* out_scores,
+                                void* hip_stream) {
+    try {
+        if (!graph || !index) { set_error("NULL handle"); return EBR_EINVAL; }
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || dev != graph->device) {
+            set_error("graph handle belongs to device %d", graph->device);
+            return EBR_EINVAL;
+        }
+        TopkOpts o;
+        o.graph = graph;
+        return topk_impl(*index, batch, (char*)ws_v, ws_bytes, out_ids, out_scores,
+                         (hipStream_t)hip_stream, nullptr, o);
+    } catch (const std::bad_alloc&) {
+        set_error("host out of memory");
+        return EBR_ENOMEM;
+    }
+}
+
+ebr_status ebr_graph_stats(const ebr_graph* graph, ebr_graph_info* out) {
+    if (!graph || !out) { set_error("NULL argument"); return EBR_EINVAL; }
+    *out = graph->info;
+    return EBR_OK;
+}
+
+void ebr_graph_destroy(ebr_graph* graph) {
+    if (!graph) return;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->cs) (void)hipStreamDestroy(graph->cs);
+    if (graph->pinned) (void)hipHostFree(graph->pinned);
+    delete graph;
+}
+
 ebr_status ebr_score_dense(const ebr_index* index, const ebr_batch* batch, void* ws_v,
                            size_t ws_bytes, float* deep, float* wide, void* hip_stream) {
     try {
@@ -1207,13 +1538,13 @@ ebr_status ebr_score_dense(const ebr_index* index, const ebr_batch* batch, void*
         st = check_users(batch, P.B, ix.dim, s);
         if (st) return st;
         char* ws = (char*)ws_v;
-        std::vector<char> blob;
-        st = run_decode(ix, P, ws, s, blob);
+        const std::vector<char> blob = pack_plan(P);
+        st = run_decode(ix, P, ws, s, blob.data(), blob.size(), kDefaultDecodeChunks);
         if (st) return st;
         ScoreArgs a = score_args(ix, P, batch, ws);
         a.deep_out = deep;
         a.wide_out = wide;
-        LAUNCH(launch_score(a, ix.dim, 2, score_ctas(), s));
+        LAUNCH(launch_score(a, ix.dim, 2, score_ranges((int)ix.n_tiles, P.n_qg, score_ctas()), s));
         HIP_TRY(hipStreamSynchronize(s));
         return EBR_OK;
     } catch (const std::bad_alloc&) {

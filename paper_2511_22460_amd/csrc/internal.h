@@ -3,7 +3,10 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ebr.h"
@@ -70,6 +73,9 @@ struct Index {
     std::vector<int8_t> key_wshift;       // V, Sw_k: weights of key k enter sums as w * 2^Sw_k
     ebr_index_info stats{};
     int device = 0;
+    // launch shapes recorded by the autotuner, per (scan dtype, query groups)
+    mutable std::mutex shape_mu;
+    std::map<std::pair<int, int>, ebr_launch_shape> shapes;
 };
 
 // Arena plan: byte offsets of each section (256-byte aligned).
@@ -131,9 +137,12 @@ struct BatchSizes {
 // Exact workspace bytes of a top-K batch of these sizes on scan dtype `dtype`.
 size_t topk_workspace_bytes(const Index& ix, int dtype, BatchSizes z);
 
-// ebr_score_topk without the entry point's bookkeeping; stream is a hipStream_t.
+// ebr_score_topk without the entry point's bookkeeping; stream is a hipStream_t. With a
+// graph handle the device sequence is captured and launched as one graph
+// (ebr_score_topk_graph); shape, when non-null, replaces the recorded launch shape.
 ebr_status run_topk(const Index& ix, const ebr_batch* batch, char* ws, size_t ws_bytes,
-                    uint32_t* out_ids, float* out_scores, void* stream, ebr_timings* tm);
+                    uint32_t* out_ids, float* out_scores, void* stream, ebr_timings* tm,
+                    ebr_graph* graph = nullptr, const ebr_launch_shape* shape = nullptr);
 
 }  // namespace ebr
 

@@ -34,6 +34,7 @@ struct DecodeArgs {
     const int32_t* uk_wshift;         // per distinct key: Sw_k, weights enter sums as w * 2^Sw_k
     int32_t n_ukeys;
     uint32_t total_chunks;
+    uint32_t chunks_per_wave;         // consecutive chunks one decode wavefront takes (1..64)
     int64_t n_tiles;
     int64_t n_super;                  // 1024-ad super-tiles
     uint32_t* st_cnt;                 // count pass: postings per super-tile
@@ -135,6 +136,7 @@ struct RescoreArgs {
     const float* r_stilde;
     const float* eps;                 // per query: bound on |approximate - exact| score
     const Control* ctl;
+    const uint32_t* skip;             // non-null and nonzero: selection unfinished, do nothing
     int32_t r_ld;
     const int64_t* out_off;
     uint32_t* out_ids;
@@ -170,7 +172,7 @@ bool score_dim_supported(int dim);
 // Queries per query group of the scoring kernel for this embedding width.
 int score_group_queries(int dim);
 int score_ranges(int n_work, int n_qgroups, int ctas);
-int launch_score(const ScoreArgs& a, int dim, int mode, int ctas, void* stream);
+int launch_score(const ScoreArgs& a, int dim, int mode, int ranges, void* stream);
 int launch_select(const SelectArgs& a, int n_queries, void* stream);
 int launch_finalize(const FinalArgs& a, int n_queries, void* stream);
 int launch_rescore(const RescoreArgs& a, int dim, int n_queries, void* stream);

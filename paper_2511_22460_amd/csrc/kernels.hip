@@ -164,18 +164,16 @@ __device__ __forceinline__ uint32_t decode_chunk_lane(const ChunkHdr* chunks, co
     return id;
 }
 
-constexpr int kChunksPerWave = 8;
-
-// One wavefront decodes kChunksPerWave consecutive chunks of the batch's distinct keys and
+// One wavefront decodes a.chunks_per_wave consecutive chunks of the batch's distinct keys and
 // counts (place == 0) or places (place == 1) their postings into 1024-ad super-tile buckets.
 // Runs of postings in the same super-tile are aggregated into one atomic per run. A placed
 // entry is ((slot << 10) | ad & 1023, w' bits); k_refine orders each super-tile by 32-ad tile.
 __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
     const int lane = lane_id();
     const uint32_t gw = blockIdx.x * 4u + (threadIdx.x >> 6);
-    const uint32_t c_begin = gw * (uint32_t)kChunksPerWave;
+    const uint32_t c_begin = gw * a.chunks_per_wave;
     if (c_begin >= a.total_chunks) return;
-    const uint32_t c_end = min(a.total_chunks, c_begin + (uint32_t)kChunksPerWave);
+    const uint32_t c_end = min(a.total_chunks, c_begin + a.chunks_per_wave);
     // distinct-key slot owning the first chunk: the last u with prefix[u] <= c_begin
     int lo = 0, hi = a.n_ukeys;
     while (hi - lo > 1) {
@@ -1063,6 +1061,7 @@ __global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
     const int tid = (int)threadIdx.x;
     const int K = a.kq[q];
     if (a.ctl && a.ctl->error) return;
+    if (a.skip && *a.skip != 0u) return;
     if (K <= 0 || a.status[q] != kStatusDone) return;
     const int Kc = a.kcnt[q];
     for (int i = tid; i < D; i += 1024) s_u[i] = a.user[(int64_t)q * D + i];
@@ -1227,7 +1226,8 @@ int launch_refine(const DecodeArgs& a, void* stream) {
 
 int launch_decode(const DecodeArgs& a, int place, void* stream) {
     if (a.total_chunks == 0) return 0;
-    const uint32_t waves = (a.total_chunks + kChunksPerWave - 1) / kChunksPerWave;
+    if (a.chunks_per_wave < 1 || a.chunks_per_wave > 64) return (int)hipErrorInvalidValue;
+    const uint32_t waves = (a.total_chunks + a.chunks_per_wave - 1) / a.chunks_per_wave;
     const unsigned blocks = (waves + 3u) / 4u;
     hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(256), 0, (hipStream_t)stream, a, place);
     return last(hipSuccess);
@@ -1273,10 +1273,11 @@ int score_ranges(int n_work, int n_qgroups, int ctas) {
     return R;
 }
 
-int launch_score(const ScoreArgs& a_in, int dim, int mode, int ctas, void* stream) {
+int launch_score(const ScoreArgs& a_in, int dim, int mode, int ranges, void* stream) {
     if (a_in.n_work <= 0 || a_in.n_qgroups <= 0) return 0;
+    if (ranges < 1 || (int64_t)ranges * a_in.n_qgroups > (1 << 24)) return (int)hipErrorInvalidValue;
     ScoreArgs a = a_in;
-    a.n_ranges = score_ranges(a.n_work, a.n_qgroups, ctas);
+    a.n_ranges = ranges < a.n_work ? ranges : a.n_work;
     dim3 grid((unsigned)(a.n_ranges * a.n_qgroups));
     hipStream_t st = (hipStream_t)stream;
     const int dt = a.dtype;

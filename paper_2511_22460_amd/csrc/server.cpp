@@ -56,6 +56,7 @@ struct Slot {
     float* h_user = nullptr;    // pinned, max_batch x d
     uint32_t* h_ids = nullptr;  // pinned, out_cap
     float* h_scores = nullptr;  // pinned, out_cap
+    ebr_graph* graph = nullptr; // the slot's captured-batch handle (graph option)
 };
 
 inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -224,7 +225,7 @@ void ebr_server::run_batch(Slot& sl, std::vector<Ticket*>& take) {
             bt.scan_dtype = opt.scan_dtype;
             bt.rescore_factor = factor;
             ebr_timings tm{};
-            st = run_topk(*ix, &bt, p, ws_bytes, d_ids, d_scores, sl.stream, &tm);
+            st = run_topk(*ix, &bt, p, ws_bytes, d_ids, d_scores, sl.stream, &tm, sl.graph);
         }
         if (!st && n_out > 0) {
             he = hipMemcpyAsync(sl.h_ids, d_ids, 4 * (size_t)n_out, hipMemcpyDeviceToHost, sl.stream);
@@ -314,6 +315,7 @@ ebr_status ebr_server_create(const ebr_index* index, void* scratch, size_t scrat
         auto fail = [&](const char* what, hipError_t e) {
             set_error("%s failed: %s", what, hipGetErrorString(e));
             for (Slot& sl : S->slots) {
+                if (sl.graph) ebr_graph_destroy(sl.graph);
                 if (sl.stream) (void)hipStreamDestroy(sl.stream);
                 if (sl.h_user) (void)hipHostFree(sl.h_user);
                 if (sl.h_ids) (void)hipHostFree(sl.h_ids);
@@ -334,6 +336,7 @@ ebr_status ebr_server_create(const ebr_index* index, void* scratch, size_t scrat
             if (e != hipSuccess) return fail("hipHostMalloc", e);
             e = hipHostMalloc((void**)&sl.h_scores, 4 * (size_t)S->out_cap, hipHostMallocDefault);
             if (e != hipSuccess) return fail("hipHostMalloc", e);
+            if (o.graph && ebr_graph_create(&sl.graph) != EBR_OK) return fail("ebr_graph_create", hipErrorUnknown);
         }
         S->t_stats = Clock::now();
         for (int i = 0; i < o.pipeline; ++i) S->workers.emplace_back([S, i] { S->worker(i); });
@@ -347,6 +350,7 @@ ebr_status ebr_server_create(const ebr_index* index, void* scratch, size_t scrat
             S->cv_work.notify_all();
             for (auto& w : S->workers) w.join();
             for (Slot& sl : S->slots) {
+                if (sl.graph) ebr_graph_destroy(sl.graph);
                 if (sl.stream) (void)hipStreamDestroy(sl.stream);
                 if (sl.h_user) (void)hipHostFree(sl.h_user);
                 if (sl.h_ids) (void)hipHostFree(sl.h_ids);
@@ -486,6 +490,7 @@ ebr_status ebr_server_destroy(ebr_server* S) {
     for (auto& w : S->workers) w.join();
     ebr_status st = EBR_OK;
     for (Slot& sl : S->slots) {
+        if (sl.graph) ebr_graph_destroy(sl.graph);
         if (sl.stream && hipStreamDestroy(sl.stream) != hipSuccess) st = EBR_EDEVICE;
         if (sl.h_user) (void)hipHostFree(sl.h_user);
         if (sl.h_ids) (void)hipHostFree(sl.h_ids);

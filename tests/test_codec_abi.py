@@ -156,3 +156,44 @@ def test_server_entry_points_reject_null_handles():
     assert lib.ebr_server_reset_stats(None) == E.EBR_EINVAL
     assert lib.ebr_server_destroy(None) == E.EBR_EINVAL
     assert "NULL" in lib.ebr_last_error().decode()
+
+
+def test_tuning_and_graph_entry_points_reject_null_handles():
+    lib = E.load()
+    import ctypes
+    sh = E.LaunchShape(0, 0, 0)
+    assert lib.ebr_set_launch_shape(None, E.F32, 1, ctypes.byref(sh)) == E.EBR_EINVAL
+    assert lib.ebr_get_launch_shape(None, E.F32, 1, ctypes.byref(sh)) == E.EBR_EINVAL
+    rep = E.TuneReport()
+    assert lib.ebr_autotune(None, None, None, 0, None, None, 0, None, ctypes.byref(rep)) == E.EBR_EINVAL
+    assert lib.ebr_score_topk_graph(None, None, None, None, 0, None, None, None) == E.EBR_EINVAL
+    assert lib.ebr_graph_stats(None, None) == E.EBR_EINVAL
+    assert lib.ebr_graph_create(None) == E.EBR_EINVAL
+    lib.ebr_graph_destroy(None)  # a no-op
+
+
+def test_abi_struct_sizes_match_the_header(tmp_path):
+    """The binding's ctypes structures have the sizes the C compiler gives include/ebr.h's."""
+    import ctypes
+    import os
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "sizes.c"
+    names = ["ebr_launch_shape", "ebr_tune_report", "ebr_graph_info", "ebr_server_opts",
+             "ebr_batch", "ebr_query", "ebr_server_info", "ebr_timings", "ebr_build_desc",
+             "ebr_index_info"]
+    src.write_text('#include <stdio.h>\n#include "ebr.h"\nint main(void) {\n' +
+                   "".join(f'  printf("%zu\\n", sizeof({n}));\n' for n in names) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "sizes"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    mine = [E.LaunchShape, E.TuneReport, E.GraphInfo, E.ServerOpts, E.Batch, E.Query,
+            E.ServerStats, E.Timings, E.BuildDesc, E.IndexInfo]
+    assert got == [ctypes.sizeof(t) for t in mine]

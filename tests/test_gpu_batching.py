@@ -62,12 +62,24 @@ def test_uneven_batch_equals_queries_run_alone(uneven):
 
 
 def test_c4_full_size_sampled_queries():
-    """4096 queries in one launch over the 10M-ad inventory (BF16 scan, 4 K rescored)."""
+    """4096 queries in one launch over the 10M-ad inventory (BF16 scan, 4 K rescored), in the
+    benchmark's launch configuration: autotuned shape, kernels captured in a graph; the eager
+    path gives the same bits."""
     dev()
     base = W.make("c2")
     wl = W.queries_for(base, "c4")
     ix = E.Index.from_workload(wl, dtypes=1 | (1 << 1))
-    ids, sc, offs = ix.topk_workload(wl, scan_dtype=E.BF16, rescore_factor=4)
+    U = torch.from_numpy(np.ascontiguousarray(wl.user_emb)).to(dev())
+    rep, _ = ix.autotune(U, wl.feat_offsets, wl.feat_keys, wl.k, wl.feat_mult, scan_dtype=E.BF16,
+                         rescore_factor=4, reps=1)
+    assert ix.launch_shape(E.BF16, wl.n_queries) == rep["best"]
+    g = E.Graph()
+    ids, sc, offs = ix.topk_workload(wl, scan_dtype=E.BF16, rescore_factor=4, graph=g)
     torch.cuda.synchronize()
     assert offs[-1] == int(wl.k.sum())
-    check(wl, ids.cpu().numpy().view(np.uint32), sc.cpu().numpy(), offs, [0, 2048, 4095])
+    ids, sc = ids.cpu().numpy().view(np.uint32), sc.cpu().numpy()
+    check(wl, ids, sc, offs, [0, 2048, 4095])
+    e_ids, e_sc, _ = ix.topk_workload(wl, scan_dtype=E.BF16, rescore_factor=4)
+    assert np.array_equal(e_ids.cpu().numpy().view(np.uint32), ids)
+    assert np.array_equal(e_sc.cpu().numpy().view(np.uint32), sc.view(np.uint32))
+    g.close()

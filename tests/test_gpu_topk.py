@@ -228,6 +228,11 @@ def test_c2_full_size_sampled_queries(c2):
     ids, sc, offs = run(ix, wl)
     assert offs[-1] == 256 * 1000
     check_all(wl, ids, sc, offs, qs=[0, 77, 154, 255], label="c2")
+    # the benchmark autotunes the launch shape first: the tuned launch gives the same bits
+    U = torch.from_numpy(np.ascontiguousarray(wl.user_emb)).to(dev())
+    rep, _ = ix.autotune(U, wl.feat_offsets, wl.feat_keys, wl.k, wl.feat_mult, reps=1)
+    t_ids, t_sc, _ = run(ix, wl)
+    assert np.array_equal(t_ids, ids) and np.array_equal(t_sc.view(np.uint32), sc.view(np.uint32)), rep
 
 
 def test_c2_decode_sampled_keys_bit_exact(c2):
