@@ -25,6 +25,8 @@
 // bit-identical across passes, tile schedules and batch compositions.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "kernels.h"
 
@@ -39,7 +41,7 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = lane_id();
-#pragma unroll
+    #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         uint32_t t = __shfl_up(v, off, 64);
         if (lane >= off) v += t;
@@ -412,18 +414,18 @@ __device__ __forceinline__ void steps_entries(const EntryLanes& t, uint32_t s0, 
     // exchange values through the rows, so the compiler must neither reorder nor elide these
     // accesses (it sees them as one thread's accesses to unrelated addresses): compiler
     // barriers between them.
-#pragma unroll
+    #pragma unroll
     for (int k = 0; k < K; ++k) mark[k * 64 + lane] = -1;
     __asm__ __volatile__("" ::: "memory");
     if (t.cnt > 0u && t.pre >= 64u * s0 && t.pre < 64u * (s0 + K)) mark[t.pre - 64u * s0] = lane;
     __asm__ __volatile__("" ::: "memory");
     int mk[K];
-#pragma unroll
+    #pragma unroll
     for (int k = 0; k < K; ++k) mk[k] = mark[k * 64 + lane];
     __asm__ __volatile__("" ::: "memory");
-#pragma unroll
+    #pragma unroll
     for (int k = 0; k < K; ++k) mk[k] = wave_incl_max(mk[k]);
-#pragma unroll
+    #pragma unroll
     for (int k = 0; k < K; ++k) {
         m[k] = max(mk[k], carry);
         carry = __builtin_amdgcn_readlane(m[k], 63);
@@ -437,11 +439,26 @@ __device__ __forceinline__ void pair_add(uint32_t* acc, uint2 ue, int o, int w) 
     atomicAdd(&acc[acc_idx((int)ue.x, o)], (uint32_t)__float2int_rn(p));
 }
 
+// The (query, multiplier) pairs of a one-group batch copied to LDS: an LDS-typed pointer, so
+// that its loads are LDS reads (a generic pointer would make them flat loads).
+typedef __attribute__((address_space(3))) const unsigned long long lds_uint2;
+
+// users[i] from the LDS copy (LU) or from global memory
+template <bool LU>
+__device__ __forceinline__ uint2 user_at(const ScoreArgs& a, lds_uint2* lds_users, uint32_t i) {
+    if constexpr (LU) {
+        const unsigned long long v = lds_users[i];
+        return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+    } else {
+        return reinterpret_cast<const uint2*>(a.users)[i];
+    }
+}
+
 // Pairs of steps [s_begin, end) of a set of entries, four steps mapped before their loads.
+template <bool LU>
 __device__ __forceinline__ void cross_steps(const ScoreArgs& a, const EntryLanes& t, uint32_t s_begin,
-                                            int* mark, uint32_t* acc, const uint2* lds_users) {
+                                            int* mark, uint32_t* acc, lds_uint2* lds_users) {
     const int lane = lane_id();
-    const uint2* users = reinterpret_cast<const uint2*>(a.users);
     // entry of pair 64 s_begin - 1: the last lane with a non-empty entry starting before it
     int carry = -1;
     if (s_begin > 0) {
@@ -452,19 +469,19 @@ __device__ __forceinline__ void cross_steps(const ScoreArgs& a, const EntryLanes
     for (uint32_t s = s_begin; 64u * s < t.total; s += kSteps) {
         int m[kSteps], ub[kSteps], uo[kSteps], uw[kSteps];
         steps_entries<kSteps>(t, s, mark, carry, m);
-#pragma unroll
+        #pragma unroll
         for (int k = 0; k < kSteps; ++k) {
             ub[k] = __shfl(t.base, m[k], 64);
             uo[k] = __shfl(t.o, m[k], 64);
             uw[k] = __shfl(t.w, m[k], 64);
         }
         uint2 ue[kSteps];
-#pragma unroll
+        #pragma unroll
         for (int k = 0; k < kSteps; ++k) {
             const uint32_t p = 64u * (s + k) + (uint32_t)lane;
-            if (p < t.total) ue[k] = lds_users ? lds_users[(uint32_t)ub[k] + p] : users[(uint32_t)ub[k] + p];
+            if (p < t.total) ue[k] = user_at<LU>(a, lds_users, (uint32_t)ub[k] + p);
         }
-#pragma unroll
+        #pragma unroll
         for (int k = 0; k < kSteps; ++k)
             if (64u * (s + k) + (uint32_t)lane < t.total) pair_add(acc, ue[k], uo[k], uw[k]);
     }
@@ -481,10 +498,10 @@ struct PairsAhead {
     uint32_t total;
 };
 
+template <bool LU>
 __device__ __forceinline__ PairsAhead pairs_ahead(const ScoreArgs& a, int g, uint2 e, bool valid,
-                                                  int* mark, const uint2* lds_users) {
+                                                  int* mark, lds_uint2* lds_users) {
     const int lane = lane_id();
-    const uint2* users = reinterpret_cast<const uint2*>(a.users);
     const EntryLanes t = entry_lanes(a, g, e, valid);
     PairsAhead pa;
     pa.total = t.total;
@@ -497,7 +514,7 @@ __device__ __forceinline__ PairsAhead pairs_ahead(const ScoreArgs& a, int g, uin
     else if (t.total > 64u) steps_entries<2>(t, 0, mark, carry, m);
     else if (t.total > 0u) steps_entries<1>(t, 0, mark, carry, m);
     if (t.total > 64u * kMarkRows) steps_entries<kAheadSteps - kMarkRows>(t, kMarkRows, mark, carry, m + kMarkRows);
-#pragma unroll
+    #pragma unroll
     for (int k = 0; k < kAheadSteps; ++k) {
         pa.uo[k] = 0;
         pa.uw[k] = 0;
@@ -507,7 +524,7 @@ __device__ __forceinline__ PairsAhead pairs_ahead(const ScoreArgs& a, int g, uin
             pa.uo[k] = __shfl(t.o, m[k], 64);
             pa.uw[k] = __shfl(t.w, m[k], 64);
             const uint32_t p = 64u * k + (uint32_t)lane;
-            if (p < t.total) pa.ue[k] = lds_users ? lds_users[(uint32_t)ub + p] : users[(uint32_t)ub + p];
+            if (p < t.total) pa.ue[k] = user_at<LU>(a, lds_users, (uint32_t)ub + p);
         }
     }
     return pa;
@@ -528,32 +545,34 @@ __device__ __forceinline__ ProdTile prod_entries(const ScoreArgs& a, uint2 b, in
 
 // Cross term of one tile (this wave's share): the prefetched round-0 pairs, the rest of
 // round 0, then later rounds of entries.
+template <bool LU>
 __device__ __forceinline__ void prod_tile(const ScoreArgs& a, int g, int pw, const ProdTile& t,
                                           const PairsAhead& pa, int* mark, uint32_t* acc,
-                                          const uint2* lds_users) {
+                                          lds_uint2* lds_users) {
     const int lane = lane_id();
     const uint2* bucket = reinterpret_cast<const uint2*>(a.bucket);
     constexpr uint32_t kRound = kProducerWaves * 64u;
     const uint32_t first = t.beg + (uint32_t)pw;
     if (first >= t.end) return;
-#pragma unroll
+    #pragma unroll
     for (int k = 0; k < kAheadSteps; ++k)
         if (64u * k + (uint32_t)lane < pa.total) pair_add(acc, pa.ue[k], pa.uo[k], pa.uw[k]);
     if (pa.total > 64u * kAheadSteps)
-        cross_steps(a, entry_lanes(a, g, t.e0, first + kProducerWaves * (uint32_t)lane < t.end),
-                    kAheadSteps, mark, acc, lds_users);
+        cross_steps<LU>(a, entry_lanes(a, g, t.e0, first + kProducerWaves * (uint32_t)lane < t.end),
+                        kAheadSteps, mark, acc, lds_users);
     for (uint32_t base = first + kRound; base < t.end; base += kRound) {
         const uint32_t ei = base + kProducerWaves * (uint32_t)lane;
         const bool ok = ei < t.end;
         const uint2 e = ok ? bucket[ei] : make_uint2(0u, 0u);
-        cross_steps(a, entry_lanes(a, g, e, ok), 0, mark, acc, lds_users);
+        cross_steps<LU>(a, entry_lanes(a, g, e, ok), 0, mark, acc, lds_users);
     }
 }
 
+template <bool LU>
 __device__ __forceinline__ PairsAhead prod_ahead(const ScoreArgs& a, int g, int pw, const ProdTile& t,
-                                                 int* mark, const uint2* lds_users) {
+                                                 int* mark, lds_uint2* lds_users) {
     const uint32_t first = t.beg + (uint32_t)pw;
-    return pairs_ahead(a, g, t.e0, first + kProducerWaves * (uint32_t)lane_id() < t.end, mark, lds_users);
+    return pairs_ahead<LU>(a, g, t.e0, first + kProducerWaves * (uint32_t)lane_id() < t.end, mark, lds_users);
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -576,7 +595,7 @@ __device__ __forceinline__ uint32_t fp8_to_bf16_bits(uint32_t c) {
 // Eight e4m3fn codes (little-endian in v) -> eight BF16 values packed as one 16-byte operand.
 __device__ __forceinline__ f32x4 fp8x8_to_bf16x8(uint2 v) {
     uint32_t w[4];
-#pragma unroll
+    #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const uint32_t src = i < 2 ? v.x : v.y;
         const int sh = (i & 1) * 16;
@@ -645,11 +664,11 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
 
     for (int i = tid; i < 2 * GQ * kTileAds; i += NT) (&s_acc[0][0])[i] = 0u;
     // one query group: its (query, multiplier) users fit in LDS when few enough
-    const uint2* lu = nullptr;
-    if (a.packed && a.n_users <= (uint32_t)kUsersLds) {
+    const bool users_in_lds = a.packed && a.n_users <= (uint32_t)kUsersLds;
+    lds_uint2* lu = (lds_uint2*)s_users;
+    if (users_in_lds) {
         for (uint32_t i = (uint32_t)tid; i < a.n_users; i += (uint32_t)NT)
             s_users[i] = reinterpret_cast<const uint2*>(a.users)[i];
-        lu = s_users;
     }
     for (int i = tid; i < GQ; i += NT) {
         const int q = qbase + i;
@@ -673,84 +692,90 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     __syncthreads();
 
     if (producer) {
-        const int pw = wave - CW;
-        const int ptid = tid - 64 * CW;
-        // pipeline: bucket bounds two tiles ahead, round-0 entries one tile ahead, the
-        // embedding block in registers two tiles ahead (written to LDS one tile ahead)
-        struct Raw {
-            f32x4 u[PER];    // FP32 / BF16 units
-            uint2 c[PER];    // FP8 codes
-            float scale;     // FP8: the scale of ad (ptid) of the tile
-        };
-        auto emb_load = [&](uint32_t t, Raw& r) {
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int j = ptid + k * kProdThreads;
-                if (j < UNITS) {
-                    if (DT == 2) r.c[k] = reinterpret_cast<const uint2*>(a.emb)[(int64_t)t * UNITS + j];
-                    else r.u[k] = reinterpret_cast<const f32x4*>(a.emb)[(int64_t)t * UNITS + j];
+        // the producer is instantiated for users in LDS and in global memory (uniform choice)
+        auto produce = [&](auto lds_tag) {
+            constexpr bool LU = decltype(lds_tag)::value;
+            const int pw = wave - CW;
+            const int ptid = tid - 64 * CW;
+            // pipeline: bucket bounds two tiles ahead, round-0 entries one tile ahead, the
+            // embedding block in registers two tiles ahead (written to LDS one tile ahead)
+            struct Raw {
+                f32x4 u[PER];    // FP32 / BF16 units
+                uint2 c[PER];    // FP8 codes
+                float scale;     // FP8: the scale of ad (ptid) of the tile
+            };
+            auto emb_load = [&](uint32_t t, Raw& r) {
+                #pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int j = ptid + k * kProdThreads;
+                    if (j < UNITS) {
+                        if (DT == 2) r.c[k] = reinterpret_cast<const uint2*>(a.emb)[(int64_t)t * UNITS + j];
+                        else r.u[k] = reinterpret_cast<const f32x4*>(a.emb)[(int64_t)t * UNITS + j];
+                    }
                 }
+                if (DT == 2 && ptid < kTileAds) r.scale = a.fp8_scale[(int64_t)t * kTileAds + ptid];
+            };
+            auto emb_store = [&](int buf, const Raw& r) {
+                #pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int j = ptid + k * kProdThreads;
+                    if (UNITS % kProdThreads == 0 || j < UNITS)
+                        s_emb[buf][j] = DT == 2 ? fp8x8_to_bf16x8(r.c[k]) : r.u[k];
+                }
+                if (DT == 2 && ptid < kTileAds) s_escale[buf][ptid] = r.scale;
+            };
+            const uint32_t t0 = tile_at(0);
+            {
+                Raw e0;
+                emb_load(t0, e0);
+                emb_store(0, e0);
+                const ProdTile p0 = prod_entries(a, prod_bounds(a, t0), pw);
+                prod_tile<LU>(a, g, pw, p0, prod_ahead<LU>(a, g, pw, p0, s_mark[pw], lu), s_mark[pw], s_acc[0], lu);
             }
-            if (DT == 2 && ptid < kTileAds) r.scale = a.fp8_scale[(int64_t)t * kTileAds + ptid];
-        };
-        auto emb_store = [&](int buf, const Raw& r) {
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int j = ptid + k * kProdThreads;
-                if (UNITS % kProdThreads == 0 || j < UNITS)
-                    s_emb[buf][j] = DT == 2 ? fp8x8_to_bf16x8(r.c[k]) : r.u[k];
-            }
-            if (DT == 2 && ptid < kTileAds) s_escale[buf][ptid] = r.scale;
-        };
-        const uint32_t t0 = tile_at(0);
-        {
-            Raw e0;
-            emb_load(t0, e0);
-            emb_store(0, e0);
-            const ProdTile p0 = prod_entries(a, prod_bounds(a, t0), pw);
-            prod_tile(a, g, pw, p0, prod_ahead(a, g, pw, p0, s_mark[pw], lu), s_mark[pw], s_acc[0], lu);
-        }
-        // Tiles u = 1 .. n_it - 1 are filled in iteration u - 1. Every load is issued two
-        // iterations before its first use, so the state is kept in two sets, for odd and even
-        // u. Before the step for tile u its set holds: the embedding block of u (loaded), the
-        // first pairs of u (loaded), the entries of u and of u + 2, the bounds of u + 4.
-        struct Set {
-            Raw e;
-            PairsAhead pa;
-            ProdTile pc, pn;
-            uint2 bn;
-        };
-        Set so{}, se{};
-        auto entries_of = [&](int u) { return prod_entries(a, prod_bounds(a, tile_at(u)), pw); };
-        auto fill = [&](Set& st, int u) {  // prologue: the state before the step for tile u
-            if (u >= n_it) return;
-            emb_load(tile_at(u), st.e);
-            st.pc = entries_of(u);
-            st.pa = prod_ahead(a, g, pw, st.pc, s_mark[pw], lu);
-            if (u + 2 < n_it) st.pn = entries_of(u + 2);
-            if (u + 4 < n_it) st.bn = prod_bounds(a, tile_at(u + 4));
-        };
-        fill(so, 1);
-        fill(se, 2);
-        __syncthreads();
-        auto step = [&](int u, Set& st) {
-            const int nb = u & 1;  // buffer of tile u (the consumers read it in iteration u)
-            emb_store(nb, st.e);
-            if (u + 2 < n_it) emb_load(tile_at(u + 2), st.e);
-            prod_tile(a, g, pw, st.pc, st.pa, s_mark[pw], s_acc[nb], lu);
-            if (u + 2 < n_it) {
-                st.pa = prod_ahead(a, g, pw, st.pn, s_mark[pw], lu);
-                st.pc = st.pn;
-            }
-            if (u + 4 < n_it) st.pn = prod_entries(a, st.bn, pw);
-            if (u + 6 < n_it) st.bn = prod_bounds(a, tile_at(u + 6));
+            // Tiles u = 1 .. n_it - 1 are filled in iteration u - 1. Every load is issued two
+            // iterations before its first use, so the state is kept in two sets, for odd and even
+            // u. Before the step for tile u its set holds: the embedding block of u (loaded), the
+            // first pairs of u (loaded), the entries of u and of u + 2, the bounds of u + 4.
+            struct Set {
+                Raw e;
+                PairsAhead pa;
+                ProdTile pc, pn;
+                uint2 bn;
+            };
+            Set so{}, se{};
+            auto entries_of = [&](int u) { return prod_entries(a, prod_bounds(a, tile_at(u)), pw); };
+            auto fill = [&](Set& st, int u) {  // prologue: the state before the step for tile u
+                if (u >= n_it) return;
+                emb_load(tile_at(u), st.e);
+                st.pc = entries_of(u);
+                st.pa = prod_ahead<LU>(a, g, pw, st.pc, s_mark[pw], lu);
+                if (u + 2 < n_it) st.pn = entries_of(u + 2);
+                if (u + 4 < n_it) st.bn = prod_bounds(a, tile_at(u + 4));
+            };
+            fill(so, 1);
+            fill(se, 2);
             __syncthreads();
+            auto step = [&](int u, Set& st) {
+                const int nb = u & 1;  // buffer of tile u (the consumers read it in iteration u)
+                emb_store(nb, st.e);
+                if (u + 2 < n_it) emb_load(tile_at(u + 2), st.e);
+                prod_tile<LU>(a, g, pw, st.pc, st.pa, s_mark[pw], s_acc[nb], lu);
+                if (u + 2 < n_it) {
+                    st.pa = prod_ahead<LU>(a, g, pw, st.pn, s_mark[pw], lu);
+                    st.pc = st.pn;
+                }
+                if (u + 4 < n_it) st.pn = prod_entries(a, st.bn, pw);
+                if (u + 6 < n_it) st.bn = prod_bounds(a, tile_at(u + 6));
+                __syncthreads();
+            };
+            for (int u = 1; u < n_it; u += 2) {
+                step(u, so);
+                if (u + 1 < n_it) step(u + 1, se);
+            }
+            __syncthreads();  // the consumers' last iteration
         };
-        for (int u = 1; u < n_it; u += 2) {
-            step(u, so);
-            if (u + 1 < n_it) step(u + 1, se);
-        }
-        __syncthreads();  // the consumers' last iteration
+        if (users_in_lds) produce(std::true_type{});
+        else produce(std::false_type{});
         return;
     }
 
@@ -765,15 +790,15 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         const int q = q0 + (lane & 31);
         if (DT == 0) {
             const int kofs = lane >> 5;
-#pragma unroll
+            #pragma unroll
             for (int s = 0; s < NUR; ++s)
                 ureg[s] = (q < B) ? a.user[(int64_t)q * D + 2 * s + kofs] : 0.0f;
         } else {
             const int kofs = 8 * (lane >> 5);
-#pragma unroll
+            #pragma unroll
             for (int s = 0; s < NUB; ++s) {
                 uint32_t w[4];
-#pragma unroll
+                #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const float x0 = (q < B) ? a.user[(int64_t)q * D + 16 * s + kofs + 2 * i] : 0.0f;
                     const float x1 = (q < B) ? a.user[(int64_t)q * D + 16 * s + kofs + 2 * i + 1] : 0.0f;
@@ -803,7 +828,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             // terms: keep the buffer clear for its next use. Rows past the batch are never
             // written (the buffers start cleared), so their waves only keep the barrier count.
             if (q0 < B) {
-#pragma unroll
+                #pragma unroll
                 for (int g4 = 0; g4 < 4; ++g4)
                     *reinterpret_cast<uint4*>(acc + acc_idx(rg(g4), o)) = make_uint4(0u, 0u, 0u, 0u);
             }
@@ -818,21 +843,21 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         if (DT == 0) {
             constexpr int W = NQ < 8 ? NQ : 8;
             f32x4 ev[W];
-#pragma unroll
+            #pragma unroll
             for (int i = 0; i < W; ++i) ev[i] = eb[i * 64 + lane];
-#pragma unroll
+            #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 const f32x4 e4 = ev[i % W];
                 if (i + W < NQ) ev[i % W] = eb[(i + W) * 64 + lane];
-#pragma unroll
+                #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     c = __builtin_amdgcn_mfma_f32_32x32x2f32(ureg[4 * i + j], e4[j], c, 0, 0, 0);
             }
         } else {
             bf16x8 ev[NUB];
-#pragma unroll
+            #pragma unroll
             for (int s2 = 0; s2 < NUB; ++s2) ev[s2] = __builtin_bit_cast(bf16x8, eb[s2 * 64 + lane]);
-#pragma unroll
+            #pragma unroll
             for (int s2 = 0; s2 < NUB; ++s2)
                 c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ubf[s2], ev[s2], c, 0, 0, 0);
         }
@@ -841,12 +866,12 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         float wd[16];
         {
             uint4 av[4];
-#pragma unroll
+            #pragma unroll
             for (int g4 = 0; g4 < 4; ++g4) av[g4] = *reinterpret_cast<const uint4*>(acc + acc_idx(rg(g4), o));
-#pragma unroll
+            #pragma unroll
             for (int g4 = 0; g4 < 4; ++g4)
                 *reinterpret_cast<uint4*>(acc + acc_idx(rg(g4), o)) = make_uint4(0u, 0u, 0u, 0u);
-#pragma unroll
+            #pragma unroll
             for (int g4 = 0; g4 < 4; ++g4) {
                 wd[4 * g4] = (float)(int)av[g4].x;  // the row's scale is applied below
                 wd[4 * g4 + 1] = (float)(int)av[g4].y;
@@ -862,12 +887,12 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         // sample pass: row base of this wave's block plus a 32-bit offset per row
         uint32_t* skeys = MODE == 1 ? a.sample_keys + (int64_t)q0 * a.sample_ld : nullptr;
         const uint32_t scol = (uint32_t)(first + it) * kTileAds + (uint32_t)o;
-#pragma unroll
+        #pragma unroll
         for (int g4 = 0; g4 < 4; ++g4) {
             const int r0 = rg(g4);
             const f32x4 th = *reinterpret_cast<const f32x4*>(s_thr + r0);
             const f32x4 sq = *reinterpret_cast<const f32x4*>(s_qscale + r0);
-#pragma unroll
+            #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 // the cross term's integer sum times 2^-S_q (exact); the score is one fused
                 // multiply-add, the same value as the sum deep + wide
@@ -891,7 +916,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             // rare: exact (key, id) comparison against the threshold, then append
             if (pass && ad_ok) {
                 const uint32_t idk = 0xffffffffu - (uint32_t)ad;
-#pragma unroll
+                #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int ql = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                     if (sc[r] >= s_thr[ql]) {
@@ -1079,11 +1104,11 @@ __global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
             if (piece < PC) {
                 const int64_t b = id >> kTileShift;
                 const f32x4 e4 = emb[(b * NQ + i4) * 64 + (int)(id & (kTileAds - 1)) + 32 * h];
-#pragma unroll
+                #pragma unroll
                 for (int j = 0; j < 4; ++j) part = fmaf(s_u[8 * i4 + 2 * j + h], e4[j], part);
             }
         }
-#pragma unroll
+        #pragma unroll
         for (int m = TPC / 2; m > 0; m >>= 1) part += __shfl_xor(part, m, TPC);
         if (ok && piece == 0) {
             const float sc = part + a.r_wide[(int64_t)q * a.r_ld + r];
