@@ -170,7 +170,9 @@ ebr_status ebr_workspace_size(const ebr_index* index, const ebr_batch* batch, si
  * ebr_workspace_size (256-byte aligned). out_ids (uint32) and out_scores (FP32
  * s(u, a)) are device arrays of sum K_q entries, each query's slice ordered by
  * (score descending, id ascending); -0.0 scores are returned as +0.0.
- * The call blocks until the results are complete on hip_stream.
+ * The call blocks until the results are complete on hip_stream. The kernels run
+ * in the launch shape recorded for the batch's dtype and query-group count
+ * (ebr_autotune, ebr_set_launch_shape), else the default; results do not depend on it.
  * EBR_EINVAL: keys out of range or repeated in a query, K_q out of range,
  * non-finite multipliers or user vectors.
  */

@@ -1163,7 +1163,6 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
     };
 
     if (g) {
-        std::lock_guard<std::mutex> lk(g->mu);
         HIP_TRY(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
         const ebr_status r = enqueue();
         hipGraph_t graph = nullptr;
@@ -1286,6 +1285,8 @@ ebr_status run_topk(const Index& ix, const ebr_batch* batch, char* ws, size_t ws
     TopkOpts o;
     o.graph = graph;
     o.shape = shape;
+    if (!graph) return topk_impl(ix, batch, ws, ws_bytes, out_ids, out_scores, (hipStream_t)stream, tm, o);
+    std::lock_guard<std::mutex> lk(graph->mu);
     return topk_impl(ix, batch, ws, ws_bytes, out_ids, out_scores, (hipStream_t)stream, tm, o);
 }
 
@@ -1500,6 +1501,8 @@ ebr_status ebr_score_topk_graph(ebr_graph* graph, const ebr_index* index, const 
         }
         TopkOpts o;
         o.graph = graph;
+        // the handle's staging, stream and executable graph serve one call at a time
+        std::lock_guard<std::mutex> lk(graph->mu);
         return topk_impl(*index, batch, (char*)ws_v, ws_bytes, out_ids, out_scores,
                          (hipStream_t)hip_stream, nullptr, o);
     } catch (const std::bad_alloc&) {
