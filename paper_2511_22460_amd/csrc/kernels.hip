@@ -779,6 +779,65 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         return;
     }
 
+    // consumer, groups of at most 2 CW queries (FP32, d <= 64): lane (wave w, half h) owns the
+    // cell of row 2 w + h and ad column lane mod 32 and computes its dot product as a chain of
+    // FMAs in the order and rounding of the 32x32x2 matrix product (per step the even
+    // dimension, then the odd one, each rounded), so its scores are bit-identical to the
+    // matrix-core path's, while the work is spread over all consumer waves instead of a
+    // 32-row product on one SIMD for a handful of rows.
+    if (DT == 0 && MODE != 2 && D <= 64 && B - qbase <= 2 * CW) {
+        const int o = lane & 31;
+        const int row = 2 * wave + (lane >> 5);
+        const int q = qbase + row;
+        const bool qok = q < B;
+        const bool wave_on = qbase + 2 * wave < B;  // wave-uniform
+        float us[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) us[d] = qok ? a.user[(int64_t)q * D + d] : 0.0f;
+        __syncthreads();
+        for (int it = 0; it < n_it; ++it) {
+            if (wave_on) {
+                const int cur = it & 1;
+                uint32_t* acc = s_acc[cur];
+                const f32x4* eb = s_emb[cur];
+                float deep = 0.0f;
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) {
+                    const f32x4 e0 = eb[i * 64 + o];       // dimensions 8 i + 2 j
+                    const f32x4 e1 = eb[i * 64 + 32 + o];  // dimensions 8 i + 2 j + 1
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        deep = fmaf(us[8 * i + 2 * j], e0[j], deep);
+                        deep = fmaf(us[8 * i + 2 * j + 1], e1[j], deep);
+                    }
+                }
+                const int cell = acc_idx(row, o);
+                const uint32_t wv = acc[cell];
+                acc[cell] = 0u;
+                const float sq = s_qscale[row];
+                const float sc = fmaf((float)(int)wv, sq, deep);
+                const int64_t ad = (int64_t)tile_at(it) * kTileAds + o;
+                const bool ad_ok = ad < a.n_ads;
+                if (MODE == 1) {
+                    if (qok)
+                        a.sample_keys[(int64_t)q * a.sample_ld + (uint32_t)(first + it) * kTileAds + (uint32_t)o] =
+                            ad_ok ? score_key(sc) : 0u;
+                } else {
+                    const bool pass = qok && ad_ok && sc >= s_thr[row];  // NaN threshold: never
+                    if (__ballot(pass) != 0ull && pass) {
+                        const uint32_t idk = 0xffffffffu - (uint32_t)ad;
+                        const uint32_t key = score_key(sc);
+                        if (key > s_thr_hi[row] || (key == s_thr_hi[row] && idk >= s_thr_lo[row]))
+                            append_candidate(a.cand, a.cand_cnt, a.cand_wide, a.cap, q, key, idk,
+                                             (float)(int)wv * sq);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
+
     // consumer: A operand (user rows) of this wave's 32-query block, kept in registers:
     // FP32 pairs for the 32x32x2 FP32 product, or BF16 octets (round to nearest even)
     const int q0 = qbase + wave * 32;

@@ -128,6 +128,32 @@ def test_topk_is_deterministic_and_same_alone_as_in_a_mix(small):
         assert np.array_equal(a_sc.view(np.uint32), sc1[a:b].view(np.uint32)), q
 
 
+def test_small_groups_match_the_matrix_core_path_bit_for_bit(small):
+    """Groups of at most 16 queries take the per-lane FMA-chain dot product; its scores must
+    be the matrix-core path's bit for bit: the same queries inside a group of 40, and the
+    dense hook's deep + wide (matrix-core products) for every returned ad."""
+    wl, ix = small
+    qs = list(range(16))
+    few = run(ix, wl, qs=qs)            # one group of 16: the FMA-chain path
+    many = run(ix, wl, qs=list(range(40)))  # one group of 40: the matrix-core path
+    for i in qs:
+        a, b = few[2][i], few[2][i + 1]
+        c, d = many[2][i], many[2][i + 1]
+        assert np.array_equal(few[0][a:b], many[0][c:d]), i
+        assert np.array_equal(few[1][a:b].view(np.uint32), many[1][c:d].view(np.uint32)), i
+    for qs1 in ([5], [0, 7, 11]):
+        w = wl.subset(qs1)
+        U = torch.from_numpy(np.ascontiguousarray(w.user_emb)).to(dev())
+        deep, wide = ix.score_dense(U, w.feat_offsets, w.feat_keys, w.feat_mult)
+        deep, wide = deep.cpu().numpy(), wide.cpu().numpy()
+        ids, sc, offs = run(ix, wl, qs=qs1)
+        for i in range(len(qs1)):
+            sel = ids[offs[i]:offs[i + 1]].astype(np.int64)
+            want = (deep[i, sel] + wide[i, sel]).astype(np.float32)
+            want[want == 0] = 0.0  # -0.0 is returned as +0.0
+            assert np.array_equal(sc[offs[i]:offs[i + 1]].view(np.uint32), want.view(np.uint32)), qs1
+
+
 def test_topk_c1_config():
     dev()
     wl = W.make("c1")
