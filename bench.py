@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--max-wait-us", type=int, default=300)
     ap.add_argument("--serve-scratch-gib", type=float, default=8.0,
                     help="scratch budget of the serving loop (split between two batches in flight)")
+    ap.add_argument("--sweep-steps", type=int, default=5,
+                    help="timed batches per size of the 1 / 16 / 64-query FP32 sweep (0: skip)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (default launch shapes)")
     ap.add_argument("--batch-steps", type=int, default=5,
@@ -162,6 +164,32 @@ def main():
     # postings of the batch's distinct keys: each is read once as an 8-byte tile-bucket entry
     distinct_postings = int(np.diff(wl.key_offsets)[np.unique(wl.feat_keys)].sum())
     achieved = flops / (score_ms * 1e-3) / 1e12
+
+    # smaller batches of the same queries (FP32): the scan's time and its HBM fraction, the
+    # roofline that bounds it when the matrix work is small
+    sweep = []
+    if args.sweep_steps > 0:
+        for bq in (1, 16, 64):
+            ws = wl.subset(range(bq))
+            Us = torch.from_numpy(np.ascontiguousarray(ws.user_emb)).to(dev)
+            for i in range(2):
+                ix.score_topk(Us, ws.feat_offsets, ws.feat_keys, ws.k, ws.feat_mult)
+            torch.cuda.synchronize()
+            tt = []
+            t1 = time.perf_counter()
+            for i in range(args.sweep_steps):
+                ix.score_topk(Us, ws.feat_offsets, ws.feat_keys, ws.k, ws.feat_mult)
+                tt.append(E.last_timings())
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t1
+            sms = float(np.mean([t["score_ms"] for t in tt]))
+            dp = int(np.diff(wl.key_offsets)[np.unique(ws.feat_keys)].sum())
+            gbs = (N * d * 4.0 + 8.0 * dp) / (sms * 1e-3) / 1e9
+            sweep.append({"queries": bq, "queries_per_s": bq * args.sweep_steps / el,
+                          "ms_per_batch": 1000 * el / args.sweep_steps, "score_ms": sms,
+                          "score_hbm_gbs": gbs, "score_hbm_frac": gbs / PEAK_HBM_GBS})
+            log(f"[bench] B={bq}: {bq * args.sweep_steps / el:.0f} queries/s, k_score {sms:.3f} ms "
+                f"({gbs:.0f} GB/s of embeddings and bucket)")
 
     # reduced-precision scans of the same batch: BF16 and FP8-e4m3 copies streamed, 4 K
     # candidates rescored exactly in FP32 (results equal the FP32 path's up to ties)
@@ -313,6 +341,7 @@ def main():
         "phases_ms": phase,
         "selection_rounds_max": rounds,
         "autotune": tune,
+        "batch_sweep": sweep,
         "roofline": {"kernel": "k_score (fused deep+wide+select)", "bound": "mfma",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
