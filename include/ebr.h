@@ -344,6 +344,11 @@ typedef struct ebr_server ebr_server; /* opaque */
  *  scan_dtype, rescore_factor   as in ebr_batch, for every query
  *  graph         nonzero: each slot runs its batches through its own ebr_graph
  *                handle (ebr_score_topk_graph) instead of launching them eagerly
+ *  f32_below     batches of at most this many queries run the FP32 scan whatever
+ *                scan_dtype says (0: never). The FP32 scan has a faster path for
+ *                groups of at most 16 queries, and the exact rescore of the reduced-
+ *                precision scans returns the FP32 scan's ids and score bits, so a
+ *                query's results do not depend on which scan its batch took.
  * Batches use the launch shape recorded in the index (ebr_autotune) for their
  * dtype and query-group count.
  */
@@ -354,6 +359,7 @@ typedef struct {
     ebr_dtype scan_dtype;
     int32_t rescore_factor;
     int32_t graph;
+    int32_t f32_below;
 } ebr_server_opts;
 
 /*

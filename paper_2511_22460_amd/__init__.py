@@ -125,7 +125,8 @@ class GraphInfo(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("max_wait_us", ctypes.c_int32),
                 ("pipeline", ctypes.c_int32), ("scan_dtype", ctypes.c_int),
-                ("rescore_factor", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("rescore_factor", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("f32_below", ctypes.c_int32)]
 
 
 class Query(ctypes.Structure):
@@ -526,12 +527,12 @@ class Server:
 
     def __init__(self, index: "Index", scratch_bytes: int, max_batch: int = 256,
                  max_wait_us: int = 200, pipeline: int = 2, scan_dtype: int = F32,
-                 rescore_factor: int = 4, graph: bool = False):
+                 rescore_factor: int = 4, graph: bool = False, f32_below: int = 0):
         import torch
         self.index = index
         self.scratch = torch.empty(max(256, int(scratch_bytes)), dtype=torch.uint8, device=index.device)
         opts = ServerOpts(max_batch, max_wait_us, pipeline, scan_dtype, rescore_factor,
-                          1 if graph else 0)
+                          1 if graph else 0, int(f32_below))
         h = ctypes.c_void_p()
         _check(load().ebr_server_create(index._h, self.scratch.data_ptr(), self.scratch.numel(),
                                         ctypes.byref(opts), ctypes.byref(h)), "ebr_server_create")

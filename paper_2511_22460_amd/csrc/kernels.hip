@@ -1127,18 +1127,16 @@ __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
 }
 
 // Exact FP32 rescore of the Kc approximate-best candidates of query q (one work-group): each
-// candidate's FP32 row is gathered from the 32x32x2 layout as D/4 16-byte pieces, one thread
-// per piece, and the dot product is reduced over the pieces in a fixed order; the score adds
-// the carried cross term. The Kc exact keys are sorted and the first K written. Certificate:
+// candidate's FP32 row is gathered from the 32x32x2 layout by one thread, whose dot product is
+// the FP32 scan's own FMA chain, so the rescored score is bit-identical to the FP32 scan's;
+// the score adds the carried cross term. The Kc exact keys are sorted and the first K
+// written. Certificate:
 // every ad outside the candidates has an approximate score <= the Kc-th approximate score s~
 // and differs from its exact score by at most eps_q, so s~ + eps_q < (K-th exact score)
 // proves the result is the exact top-K; otherwise the query is marked uncertified.
 template <int D>
 __global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
     constexpr int NQ = D / 8;
-    constexpr int PC = D / 4;                        // 16-byte pieces per row
-    constexpr int TPC = PC <= 16 ? 16 : 32;          // threads per candidate (power of two)
-    constexpr int CPP = 1024 / TPC;                  // candidates per pass
     __shared__ unsigned long long s[kMaxK];
     __shared__ float s_u[D];
     const int q = (int)blockIdx.x;
@@ -1150,29 +1148,32 @@ __global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
     const int Kc = a.kcnt[q];
     for (int i = tid; i < D; i += 1024) s_u[i] = a.user[(int64_t)q * D + i];
     __syncthreads();
+    // one thread per candidate: the dot product is one FMA chain over the dimensions in
+    // order, which is what the FP32 scan's 32x32x2 products compute (the k = 0 dimension of
+    // each step, then the k = 1 one, each rounded), so a rescored score has the FP32 scan's
+    // bits; the cross term is the scan's exact value.
     const f32x4* emb = reinterpret_cast<const f32x4*>(a.emb);
-    const int piece = tid % TPC;
-    const int i4 = piece >> 1, h = piece & 1;
-    for (int r0 = 0; r0 < Kc; r0 += CPP) {
-        const int r = r0 + tid / TPC;
-        const bool ok = r < Kc;
-        float part = 0.0f;
-        uint32_t id = 0;
-        if (ok) {
-            id = a.r_id[(int64_t)q * a.r_ld + r];
-            if (piece < PC) {
-                const int64_t b = id >> kTileShift;
-                const f32x4 e4 = emb[(b * NQ + i4) * 64 + (int)(id & (kTileAds - 1)) + 32 * h];
-                #pragma unroll
-                for (int j = 0; j < 4; ++j) part = fmaf(s_u[8 * i4 + 2 * j + h], e4[j], part);
+    for (int r = tid; r < Kc; r += 1024) {
+        const uint32_t id = a.r_id[(int64_t)q * a.r_ld + r];
+        const int64_t b = id >> kTileShift;
+        const int o = (int)(id & (kTileAds - 1));
+        f32x4 e0[NQ], e1[NQ];
+        #pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            e0[i] = emb[(b * NQ + i) * 64 + o];       // dimensions 8 i + 2 j
+            e1[i] = emb[(b * NQ + i) * 64 + 32 + o];  // dimensions 8 i + 2 j + 1
+        }
+        float deep = 0.0f;
+        #pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            #pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                deep = fmaf(s_u[8 * i + 2 * j], e0[i][j], deep);
+                deep = fmaf(s_u[8 * i + 2 * j + 1], e1[i][j], deep);
             }
         }
-        #pragma unroll
-        for (int m = TPC / 2; m > 0; m >>= 1) part += __shfl_xor(part, m, TPC);
-        if (ok && piece == 0) {
-            const float sc = part + a.r_wide[(int64_t)q * a.r_ld + r];
-            s[r] = ((unsigned long long)score_key(sc) << 32) | (unsigned long long)(0xffffffffu - id);
-        }
+        const float sc = deep + a.r_wide[(int64_t)q * a.r_ld + r];
+        s[r] = ((unsigned long long)score_key(sc) << 32) | (unsigned long long)(0xffffffffu - id);
     }
     int P = 64;
     while (P < Kc) P <<= 1;

@@ -222,8 +222,11 @@ void ebr_server::run_batch(Slot& sl, std::vector<Ticket*>& take) {
             bt.feat_keys = keys.empty() ? nullptr : keys.data();
             bt.feat_mult = any_mult ? mult.data() : nullptr;
             bt.k = kk.data();
-            bt.scan_dtype = opt.scan_dtype;
-            bt.rescore_factor = factor;
+            // small batches may take the FP32 scan: its per-lane path for small query groups
+            // is faster there, and a rescored query has the FP32 scan's result bits anyway
+            const bool f32 = B <= opt.f32_below;
+            bt.scan_dtype = f32 ? EBR_F32 : opt.scan_dtype;
+            bt.rescore_factor = f32 ? 0 : factor;
             ebr_timings tm{};
             st = run_topk(*ix, &bt, p, ws_bytes, d_ids, d_scores, sl.stream, &tm, sl.graph);
         }
@@ -284,6 +287,7 @@ ebr_status ebr_server_create(const ebr_index* index, void* scratch, size_t scrat
     if (o.max_batch == 0) o.max_batch = 256;
     if (o.pipeline == 0) o.pipeline = 2;
     if (o.max_wait_us < 0) o.max_wait_us = 0;
+    if (o.f32_below < 0) o.f32_below = 0;
     if (o.max_batch < 1 || o.max_batch > kServerMaxBatch) { set_error("max_batch must be in [1, %d]", kServerMaxBatch); return EBR_EINVAL; }
     if (o.pipeline < 1 || o.pipeline > kServerMaxPipeline) { set_error("pipeline must be in [1, %d]", kServerMaxPipeline); return EBR_EINVAL; }
     if (o.scan_dtype != EBR_F32 && o.scan_dtype != EBR_BF16 && o.scan_dtype != EBR_FP8E4M3) { set_error("unknown scan dtype"); return EBR_EINVAL; }

@@ -74,6 +74,19 @@ def test_failed_certificates_fall_back_to_fp32(small, dt):
     check_all(wl, ids, sc, offs, label=f"fallback dtype {dt}")
 
 
+@pytest.mark.parametrize("dt", [E.BF16, E.FP8E4M3])
+def test_rescored_results_equal_the_fp32_scan_bit_for_bit(small, dt):
+    # the rescore computes each candidate's dot product with the FP32 scan's own FMA chain
+    # and adds the scan's exact cross term, so a certified query returns exactly the FP32
+    # scan's ids and score bits (an uncertified one is rerun on the FP32 scan)
+    wl, ix = small
+    f_ids, f_sc, f_offs = run(ix, wl)
+    r_ids, r_sc, r_offs = run(ix, wl, scan_dtype=dt, rescore_factor=4)
+    assert np.array_equal(f_offs, r_offs)
+    assert np.array_equal(r_ids, f_ids)
+    assert np.array_equal(r_sc.view(np.uint32), f_sc.view(np.uint32))
+
+
 def test_precision_scan_deterministic_and_alone_equals_mix(small):
     wl, ix = small
     a1 = run(ix, wl, scan_dtype=E.FP8E4M3)

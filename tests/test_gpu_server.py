@@ -117,6 +117,26 @@ def test_bf16_server_with_rescore(served):
     check_served(wl, ix, res, kw=kw)
 
 
+def test_small_batches_on_the_fp32_scan_give_the_same_bits(served):
+    # a BF16 server whose batches of at most 8 queries take the FP32 scan: queries served one
+    # at a time (FP32) and in a burst (BF16 + rescore) both equal the query run alone on
+    # either scan, bit for bit
+    wl, ix = served
+    kw = dict(scan_dtype=E.BF16, rescore_factor=4)
+    with E.Server(ix, scratch_bytes=512 << 20, max_batch=64, max_wait_us=0, f32_below=8, **kw) as srv:
+        res = {}
+        for q in range(0, 12):  # one at a time
+            res[q] = srv.poll(srv.submit(wl.user_emb[q], wl.query_keys(q), int(wl.k[q])))
+        t = submit_all(srv, wl, range(12, wl.n_queries))
+        res.update({q: srv.poll(tk) for q, tk in t.items()})
+        st = srv.stats()
+    assert st["completed"] == wl.n_queries and st["failed"] == 0
+    check_served(wl, ix, res, kw=kw, oracle_qs={0, 5, 50})
+    for q in (0, 7, 40, 90):
+        f_ids, f_sc = alone(ix, wl, q)
+        assert np.array_equal(res[q][0], f_ids) and np.array_equal(res[q][1].view(np.uint32), f_sc.view(np.uint32)), q
+
+
 def test_submission_errors(served):
     wl, ix = served
     u = wl.user_emb[0]
