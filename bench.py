@@ -69,6 +69,9 @@ def main():
                     help="arrival rates (queries/s) of the serving benchmark")
     ap.add_argument("--serve-ads", type=int, default=50_000_000)
     ap.add_argument("--max-wait-us", type=int, default=300)
+    ap.add_argument("--f32-below", type=int, default=16,
+                    help="serving: batches of at most this many queries take the FP32 scan "
+                         "(same result bits as BF16 + rescore)")
     ap.add_argument("--serve-scratch-gib", type=float, default=8.0,
                     help="scratch budget of the serving loop (split between two batches in flight)")
     ap.add_argument("--sweep-steps", type=int, default=5,
@@ -374,7 +377,7 @@ def serve_main(args, np, torch, W, E, dev):
     log(f"[serve] index built in {time.time() - t0:.1f}s: {st['arena_bytes'] / 1e9:.2f} GB arena")
     scratch = int(args.serve_scratch_gib * (1 << 30)) & ~255
     srv = E.Server(ix, scratch_bytes=scratch, max_batch=256, max_wait_us=args.max_wait_us,
-                   pipeline=2, scan_dtype=E.BF16, rescore_factor=4)
+                   pipeline=2, scan_dtype=E.BF16, rescore_factor=4, f32_below=args.f32_below)
     lib = E.load()
     B = wl.n_queries
     qs, keep = [], []
@@ -467,11 +470,11 @@ def serve_main(args, np, torch, W, E, dev):
         "n_gpus": 1,
         "higher_is_better": True,
         "vs_baseline": None,
-        "dtype": "bf16 scan, f32 rescore",
+        "dtype": f"bf16 scan + f32 rescore; f32 scan for batches of <= {args.f32_below} queries",
         "data": "synthetic (seeded; paper's WeChat logs unavailable)",
         "config": {"workload": f"serving: {wl.n_ads} ads x 64-d (BF16 scan + FP32 master), "
                                f"{wl.n_postings} postings, F ~ U{{4..128}}, K in {{100, 500, 2000}}, "
-                               f"Poisson arrivals, {args.serve_scratch_gib:g} GiB scratch, max batch 256, 2 batches in flight",
+                               f"Poisson arrivals, {args.serve_scratch_gib:g} GiB scratch, max batch 256, 2 batches in flight, batches of <= {args.f32_below} queries on the FP32 scan",
                    "max_wait_us": args.max_wait_us, "scratch_bytes": scratch},
         "p50_ms": best["p50_ms"] if best else None,
         "p99_ms": best["p99_ms"] if best else None,
