@@ -146,7 +146,8 @@ void ebr_free_index(ebr_index* index);
  *                exactly in FP32 and returns the top K_q; a per-query recall certificate
  *                (the K-th exact score exceeds every outsider's best possible exact score)
  *                is checked on the GPU, and a query that fails it is rerun with the FP32
- *                scan, so results always equal the FP32 path's up to tolerance ties.
+ *                scan. The rescore computes each candidate's score with the FP32 scan's
+ *                own arithmetic, so the results are the FP32 scan's ids and score bits.
  *  rescore_factor  candidates per result for reduced-precision scans (<= 0: 4);
  *                rescore_factor * K_q <= 8192. Ignored for F32.
  * Results of query q occupy positions [sum_{p<q} K_p, sum_{p<=q} K_p).
