@@ -83,7 +83,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards by ad range across GPUs by design, but this build runs on one).",
+              "(sharding the inventory by ad range across GPUs is designed, not implemented).",
               file=sys.stderr)
         sys.exit(2)
 

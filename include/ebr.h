@@ -48,7 +48,7 @@ typedef enum {
     EBR_EAGAIN = -4,       /* not ready yet / queue full */
     EBR_ENOTFOUND = -5,    /* unknown ticket */
     EBR_ESHUTDOWN = -6,    /* server is shutting down */
-    EBR_EUNSUPPORTED = -7  /* valid but outside what this build implements */
+    EBR_EUNSUPPORTED = -7  /* valid but not supported (e.g. a scan copy the index lacks) */
 } ebr_status;
 
 /* Arithmetic type of the ad-embedding scan. */
