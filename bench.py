@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000",
                     help="arrival rates (queries/s) of the serving benchmark")
     ap.add_argument("--serve-ads", type=int, default=50_000_000)
+    ap.add_argument("--serve-max-batch", type=int, default=256,
+                    help="serving: most queries per batch")
     ap.add_argument("--max-wait-us", type=int, default=300)
     ap.add_argument("--f32-below", type=int, default=16,
                     help="serving: batches of at most this many queries take the FP32 scan "
@@ -376,7 +378,7 @@ def serve_main(args, np, torch, W, E, dev):
     st = ix.stats()
     log(f"[serve] index built in {time.time() - t0:.1f}s: {st['arena_bytes'] / 1e9:.2f} GB arena")
     scratch = int(args.serve_scratch_gib * (1 << 30)) & ~255
-    srv = E.Server(ix, scratch_bytes=scratch, max_batch=256, max_wait_us=args.max_wait_us,
+    srv = E.Server(ix, scratch_bytes=scratch, max_batch=args.serve_max_batch, max_wait_us=args.max_wait_us,
                    pipeline=2, scan_dtype=E.BF16, rescore_factor=4, f32_below=args.f32_below)
     lib = E.load()
     B = wl.n_queries
@@ -474,7 +476,7 @@ def serve_main(args, np, torch, W, E, dev):
         "data": "synthetic (seeded; paper's WeChat logs unavailable)",
         "config": {"workload": f"serving: {wl.n_ads} ads x 64-d (BF16 scan + FP32 master), "
                                f"{wl.n_postings} postings, F ~ U{{4..128}}, K in {{100, 500, 2000}}, "
-                               f"Poisson arrivals, {args.serve_scratch_gib:g} GiB scratch, max batch 256, 2 batches in flight, batches of <= {args.f32_below} queries on the FP32 scan",
+                               f"Poisson arrivals, {args.serve_scratch_gib:g} GiB scratch, max batch {args.serve_max_batch}, 2 batches in flight, batches of <= {args.f32_below} queries on the FP32 scan",
                    "max_wait_us": args.max_wait_us, "scratch_bytes": scratch},
         "p50_ms": best["p50_ms"] if best else None,
         "p99_ms": best["p99_ms"] if best else None,
