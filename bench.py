@@ -33,7 +33,7 @@ def measured_traffic():
     None when the kernel source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_score_f32_c2_10M_B256_traffic.txt")
-    src = os.path.join(ROOT, "paper_2511_22460_amd", "csrc", "kernels.hip")
+    src = os.path.join(ROOT, "paper_2511_22460_amd", "csrc", "score.h")
     try:
         fields = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()

@@ -206,7 +206,7 @@ static ebr_status measure(const ebr_build_desc* d, Measured* m) {
     return EBR_OK;
 }
 
-// FP32 copy in the matrix-core layout (see k_score in kernels.hip).
+// FP32 copy in the matrix-core layout (see k_score in score.h).
 static void swizzle_f32(const float* E, int64_t n_ads, int32_t d, float* out) {
     const int64_t n_blk = (n_ads + kTileAds - 1) / kTileAds;
     const int NQ = d / 8;

@@ -5,7 +5,7 @@
 // FP8: OCP e4m3fn (1 sign, 4 exponent bits with bias 7, 3 mantissa bits; no infinities;
 // largest finite 448; subnormals m * 2^-9) with one FP32 scale per ad row,
 // scale = max_i |e_i| / 448; codes are round-to-nearest-even of e_i / scale, saturating.
-// Both copies are laid out for v_mfma_f32_32x32x16_bf16 (see kernels.hip).
+// Both copies are laid out for v_mfma_f32_32x32x16_bf16 (see k_score in score.h).
 #include <cmath>
 #include <cstring>
 

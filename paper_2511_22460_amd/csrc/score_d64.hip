@@ -1,0 +1,7 @@
+// k_score and k_rescore at embedding width 64.
+#include "score.h"
+
+namespace ebr {
+template void launch_score_d<64>(const ScoreArgs&, int, int, dim3, hipStream_t);
+template void launch_rescore_d<64>(const RescoreArgs&, int, hipStream_t);
+}  // namespace ebr
