@@ -119,6 +119,32 @@ def topk(ix: Index, u, keys, k, mult=None):
     return out
 
 
+def topk_batch(ix: Index, user_emb, feat_offsets, feat_keys, kq, feat_mult=None):
+    """Top-K of every query of a batch (OpenMP over queries): dict of ids (uint32), score and
+    cond (FP64), each of sum K entries, plus the offsets (query q: [off[q], off[q+1]))."""
+    U = _c(user_emb, np.float32).reshape(-1, ix.dim)
+    fo = _c(feat_offsets, np.int64)
+    fk = _c(feat_keys, np.int32)
+    fm = _c(feat_mult, np.float32)
+    kq = _c(kq, np.int32)
+    B = U.shape[0]
+    if len(fo) != B + 1 or len(kq) != B:
+        raise ValueError("oracle_topk_batch: batch arrays disagree")
+    off = np.zeros(B + 1, np.int64)
+    off[1:] = np.cumsum(kq)
+    n = int(off[-1])
+    out = {"ids": np.empty(n, np.uint32), "score": np.empty(n), "cond": np.empty(n), "offsets": off}
+    if fk is None:
+        fk = np.zeros(0, np.int32)
+    rc = _lib().oracle_topk_batch(ix.n_ads, ix.dim, _ptr(ix.ad_emb), ix.n_keys, _ptr(ix.key_offsets),
+                                  _ptr(ix.post_ids), _ptr(ix.post_w), B, _ptr(U), _ptr(fo), _ptr(fk),
+                                  _ptr(fm), _ptr(kq), _ptr(off), _ptr(out["ids"]), _ptr(out["score"]),
+                                  _ptr(out["cond"]))
+    if rc:
+        raise ValueError("oracle_topk_batch: bad input")
+    return out
+
+
 def topk_query(wl, q: int, k=None):
     """Top-k of query q of a workload-like object (see workloads.Workload)."""
     ix = getattr(wl, "_oracle_index", None)

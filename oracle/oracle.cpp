@@ -105,8 +105,11 @@ int oracle_topk(int64_t n_ads, int32_t dim, const float* ad_emb,
     return 0;
 }
 
-// The same for a batch, one query after another; query q's results start at
-// out_offsets[q] (= sum of the earlier K values). feat_offsets has B + 1 entries.
+// The same for a batch: query q's results start at out_offsets[q] (= sum of the earlier K
+// values); feat_offsets has B + 1 entries. Queries are independent, so they are spread over
+// the OpenMP threads (each query's own loops then run on its one thread); a batch smaller
+// than the thread count runs its queries one after another, each over all threads. Returns
+// 0, or the first error code of any query.
 int oracle_topk_batch(int64_t n_ads, int32_t dim, const float* ad_emb,
                       int64_t n_keys, const int64_t* key_offsets, const uint32_t* post_ids,
                       const float* post_w,
@@ -114,6 +117,9 @@ int oracle_topk_batch(int64_t n_ads, int32_t dim, const float* ad_emb,
                       const int32_t* feat_keys, const float* feat_mult, const int32_t* kq,
                       const int64_t* out_offsets, uint32_t* out_ids, double* out_scores,
                       double* out_cond) {
+    int rc_all = 0;
+    const bool across = n_queries >= omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) if (across)
     for (int32_t q = 0; q < n_queries; ++q) {
         int64_t f0 = feat_offsets[q], f1 = feat_offsets[q + 1];
         int64_t o = out_offsets[q];
@@ -122,9 +128,12 @@ int oracle_topk_batch(int64_t n_ads, int32_t dim, const float* ad_emb,
                              feat_mult ? feat_mult + f0 : nullptr, kq[q], out_ids + o,
                              out_scores ? out_scores + o : nullptr,
                              out_cond ? out_cond + o : nullptr, nullptr, nullptr);
-        if (rc) return rc;
+        if (rc) {
+#pragma omp critical
+            if (!rc_all) rc_all = rc;
+        }
     }
-    return 0;
+    return rc_all;
 }
 
 int oracle_num_threads(void) {
