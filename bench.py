@@ -28,6 +28,77 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_info():
+    """nproc, CPU model and SMT state of the machine running the CPU-baseline leg."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["nproc"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        info["smt"] = open("/sys/devices/system/cpu/smt/control").read().strip()
+        info["smt_active"] = open("/sys/devices/system/cpu/smt/active").read().strip() == "1"
+    except OSError:
+        info["smt"] = "unknown"
+    return info
+
+
+def oracle_leg(wl, budget_s, max_queries=None):
+    """The FP64 oracle (its batch entry, OpenMP over queries) on the first queries of the
+    workload, in chunks of one query per thread until about budget_s of wall time: the CPU
+    baseline, and the reference results the timed GPU outputs are checked against."""
+    import numpy as np
+    import oracle
+    oix = oracle.Index.of(wl)
+    nt = oracle.num_threads()
+    B = wl.n_queries if max_queries is None else min(wl.n_queries, max_queries)
+    done, el, res = 0, 0.0, []
+    while done < B and el < budget_s:
+        qs = list(range(done, min(B, done + nt)))
+        sub = wl.subset(qs)
+        t0 = time.perf_counter()
+        o = oracle.topk_batch(oix, sub.user_emb, sub.feat_offsets, sub.feat_keys, sub.k, sub.feat_mult)
+        el += time.perf_counter() - t0
+        off = o["offsets"]
+        for i, q in enumerate(qs):
+            res.append((q, o["ids"][off[i]:off[i + 1]], o["score"][off[i]:off[i + 1]]))
+        done += len(qs)
+    return {"queries": done, "seconds": el, "threads": nt, "results": res, "index": oix}
+
+
+def check_outputs(wl, leg, ids, sc, offs, label):
+    """The GPU's top-K of the oracle leg's queries against the oracle (tests/parity.py rules:
+    scores within 1e-5 relative, the id set exact up to ties inside the band, order by
+    (score desc, id asc)). Returns (queries checked, failures, min recall)."""
+    import numpy as np
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import ParityError, check_topk_vs_oracle
+    fails, rec = [], []
+    for q, o_ids, o_sc in leg["results"]:
+        a, b = int(offs[q]), int(offs[q + 1])
+
+        def full(q=q):
+            d, w, _ = oracle.scores(leg["index"], wl.user_emb[q], wl.query_keys(q))
+            return d + w
+        try:
+            rec.append(check_topk_vs_oracle(ids[a:b], sc[a:b], int(wl.k[q]), o_ids, o_sc, full,
+                                            label=f"{label} query {q}"))
+        except ParityError as e:
+            fails.append(str(e))
+    for f in fails[:5]:
+        log(f"[bench] PARITY FAILURE: {f}")
+    return {"queries": len(leg["results"]), "failures": len(fails),
+            "recall_min": min(rec) if rec else None}
+
+
 def measured_traffic():
     """HBM bytes per launch of the FP32 scoring kernel from the committed counter summary, or
     None when the kernel source has changed since the counters were taken."""
@@ -57,8 +128,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-queries", type=int, default=-1,
-                    help="queries timed on the CPU oracle (-1: about 15 s worth, 0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="wall time of the CPU oracle leg (0: skip the leg and the output check)")
+    ap.add_argument("--serve-leg-seconds", type=float, default=3.0,
+                    help="seconds per arrival rate of the serving leg on the 50M-ad inventory "
+                         "(0: skip)")
+    ap.add_argument("--serve-leg-rates", default="2000,8000",
+                    help="arrival rates (queries/s) of the serving leg")
     ap.add_argument("--precision-steps", type=int, default=10,
                     help="timed batches of the BF16 and FP8 (+ exact FP32 rescore) scans (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -158,6 +234,10 @@ def main():
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     log(f"[bench] {args.steps} timed steps in {t_total:.3f}s")
+    out_offs = np.zeros(B + 1, np.int64)
+    out_offs[1:] = np.cumsum(wl.k)
+    # the last timed step's results, checked against the oracle below
+    outputs = {"f32": (out[0].cpu().numpy().view(np.uint32).copy(), out[1].cpu().numpy().copy())}
 
     ms_per_step = 1000.0 * t_total / args.steps
     qps = B * args.steps / t_total
@@ -215,6 +295,7 @@ def main():
                 tt.append(E.last_timings())
             torch.cuda.synchronize()
             el = time.perf_counter() - t1
+            outputs[name] = (out[0].cpu().numpy().view(np.uint32).copy(), out[1].cpu().numpy().copy())
             q2 = B * args.precision_steps / el
             precision[name] = {
                 "queries_per_s": q2, "ads_scored_per_s": q2 * N, "ms_per_step": 1000 * el / args.precision_steps,
@@ -302,26 +383,26 @@ def main():
         log(f"[bench] batching 4096: {qb:.0f} queries/s ({1000 * el / args.batch_steps:.1f} ms/batch graph, "
             f"{1000 * el_e / args.batch_steps:.1f} ms eager)")
 
-    cpu = None
-    if args.cpu_queries != 0:
-        import oracle
-        oix = oracle.Index.of(wl)
-        n_cpu = args.cpu_queries
-        t0 = time.perf_counter()
-        done = 0
-        budget = 15.0
-        while True:
-            oracle.topk_query(wl, done % B)
-            done += 1
-            el = time.perf_counter() - t0
-            if (n_cpu > 0 and done >= n_cpu) or (n_cpu < 0 and (el > budget or done >= B)):
-                break
-        cpu = {"value": done / el, "unit": "queries/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"first {done} queries of the batch, FP64 oracle (OpenMP over ads), "
-                         f"{el:.1f}s wall; ads scored/s = {done / el * N:.3e}"}
-        del oix
-        log(f"[bench] cpu oracle: {done} queries in {el:.1f}s")
+    serving = None
+    if args.serve_leg_seconds > 0:
+        serving = serve_leg(args, np, torch, W, E, dev)
+
+    # CPU baseline: the FP64 oracle on the host cores over the first queries of the batch
+    # (about cpu_seconds of wall time); its results check the timed GPU outputs of every scan
+    cpu, parity = None, None
+    if args.cpu_seconds > 0:
+        leg = oracle_leg(wl, args.cpu_seconds)
+        el = leg["seconds"]
+        cpu = {"value": leg["queries"] / el, "unit": "queries/s", "cores": leg["threads"],
+               "kind": "oracle", "host": host_info(),
+               "sample": f"first {leg['queries']} queries of the timed batch, FP64 oracle "
+                         f"(OpenMP over queries, {leg['threads']} threads), {el:.1f}s wall; "
+                         f"ads scored/s = {leg['queries'] / el * N:.3e}"}
+        log(f"[bench] cpu oracle: {leg['queries']} queries in {el:.1f}s on {leg['threads']} threads")
+        parity = {name: check_outputs(wl, leg, o[0], o[1], out_offs, name) for name, o in outputs.items()}
+        parity["ok"] = all(v["failures"] == 0 for v in parity.values() if isinstance(v, dict))
+        log(f"[bench] parity of the timed outputs vs the oracle: {parity}")
+        del leg
 
     res = {
         "metric": "queries/s (ads scored/s = queries/s x N) at oracle-exact top-K",
@@ -353,30 +434,40 @@ def main():
                      "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes": N * d * 4.0 + 8.0 * distinct_postings},
         "cpu_baseline": cpu,
+        "parity": parity,
         "precision": precision,
         "batching": batching,
+        "serving": serving,
     }
     print(json.dumps(res), flush=True)
+    if parity is not None and not parity["ok"]:
+        log("[bench] the timed outputs do not match the oracle")
+        sys.exit(3)
 
 
-def serve_main(args, np, torch, W, E, dev):
-    """Serving: the 50M-ad inventory resident (FP32 master + BF16 scan copy + postings),
-    queries arriving one at a time as a Poisson process at each rate, submitted through the
-    serving loop (continuous batching under a 4 GiB scratch budget, two batches in flight),
-    per-query latency from submission to results in host memory."""
-    import ctypes
-    import oracle
-
+def serve_inventory(args, W, E, dev, n_queries=4096):
+    """The serving inventory (50M ads unless --serve-ads says otherwise), resident: FP32 master
+    + BF16 scan copy + compressed postings."""
     t0 = time.time()
     wl = W.make("c5", n_ads=args.serve_ads,
                 lengths=("rank_power", 3.75e6 * args.serve_ads / 5e7, 0.64, 100,
-                         int(3.75e6 * args.serve_ads / 5e7)), n_queries=4096)
+                         int(3.75e6 * args.serve_ads / 5e7)), n_queries=n_queries)
     log(f"[serve] generated: N={wl.n_ads} V={wl.n_keys} postings={wl.n_postings} pool={wl.n_queries} "
         f"in {time.time() - t0:.1f}s")
     t0 = time.time()
     ix = E.Index.from_workload(wl, device=dev, dtypes=1 | (1 << E.BF16))
     st = ix.stats()
     log(f"[serve] index built in {time.time() - t0:.1f}s: {st['arena_bytes'] / 1e9:.2f} GB arena")
+    return wl, ix
+
+
+def serve_run(args, np, wl, ix, E, rates, seconds, max_n, n_check):
+    """Queries of the pool submitted one at a time as a Poisson process at each rate through
+    the serving loop (continuous batching under the scratch budget, two batches in flight);
+    per-query latency from submission to results in host memory. The first n_check served
+    results are checked against the FP64 oracle first."""
+    import ctypes
+    import oracle
     scratch = int(args.serve_scratch_gib * (1 << 30)) & ~255
     srv = E.Server(ix, scratch_bytes=scratch, max_batch=args.serve_max_batch, max_wait_us=args.max_wait_us,
                    pipeline=2, scan_dtype=E.BF16, rescore_factor=4, f32_below=args.f32_below)
@@ -395,20 +486,26 @@ def serve_main(args, np, torch, W, E, dev):
     tk = ctypes.c_uint64()
     from collections import deque
     tickets = deque()
-
-    def submit(i):
-        q = i % B
-        r = i % ring
-        rc = lib.ebr_submit(srv._h, ctypes.byref(qs[q]), out_ids[r].ctypes.data, out_sc[r].ctypes.data,
-                            ctypes.byref(tk))
-        if rc != 0:
-            raise E.EbrError(rc, "ebr_submit", lib.ebr_last_error().decode())
-        tickets.append(tk.value)
+    counts = {"eagain": 0}
 
     def retire_oldest():
         rc = lib.ebr_poll(srv._h, tickets.popleft(), -1)
         if rc != 0:
             raise E.EbrError(rc, "ebr_poll", lib.ebr_last_error().decode())
+
+    def submit(i):
+        q = i % B
+        r = i % ring
+        while True:
+            rc = lib.ebr_submit(srv._h, ctypes.byref(qs[q]), out_ids[r].ctypes.data, out_sc[r].ctypes.data,
+                                ctypes.byref(tk))
+            if rc != E.EBR_EAGAIN or not tickets:
+                break
+            counts["eagain"] += 1       # queue full: wait for the oldest query, then resubmit
+            retire_oldest()
+        if rc != 0:
+            raise E.EbrError(rc, "ebr_submit", lib.ebr_last_error().decode())
+        tickets.append(tk.value)
 
     def drain():
         while tickets:
@@ -418,29 +515,42 @@ def serve_main(args, np, torch, W, E, dev):
     for i in range(512):
         submit(i)
     drain()
-    # parity: served results of a few queries against the FP64 oracle
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from parity import check_topk
-    oix = oracle.Index.of(wl)
-    n_check = 4
-    for q in range(n_check):
-        submit(q)
-    drain()
-    t_cpu = time.perf_counter()
-    for q in range(n_check):
-        d, w_, _ = oracle.scores(oix, wl.user_emb[q], wl.query_keys(q))
-        k = int(wl.k[q])
-        check_topk(out_ids[q, :k], out_sc[q, :k], k, d + w_, label=f"served query {q}")
-    cpu_el = time.perf_counter() - t_cpu
-    log(f"[serve] {n_check} served queries match the oracle ({cpu_el:.1f}s of oracle time)")
+    # parity: served results of the first queries against the FP64 oracle
+    check = None
+    if n_check > 0:
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity import check_topk_vs_oracle
+        for q in range(n_check):
+            submit(q)
+        drain()
+        sub = wl.subset(range(n_check))
+        oix = oracle.Index.of(wl)
+        t_cpu = time.perf_counter()
+        o = oracle.topk_batch(oix, sub.user_emb, sub.feat_offsets, sub.feat_keys, sub.k, sub.feat_mult)
+        cpu_el = time.perf_counter() - t_cpu
+        off = o["offsets"]
+        rec = []
+        for q in range(n_check):
+            k = int(wl.k[q])
+
+            def full(q=q):
+                d, w_, _ = oracle.scores(oix, wl.user_emb[q], wl.query_keys(q))
+                return d + w_
+            rec.append(check_topk_vs_oracle(out_ids[q, :k], out_sc[q, :k], k, o["ids"][off[q]:off[q + 1]],
+                                            o["score"][off[q]:off[q + 1]], full, label=f"served query {q}"))
+        check = {"queries": n_check, "recall_min": min(rec), "oracle_s": cpu_el,
+                 "oracle_queries_per_s": n_check / cpu_el, "oracle_threads": oracle.num_threads()}
+        log(f"[serve] {n_check} served queries match the oracle ({cpu_el:.1f}s of oracle time)")
+        del oix
 
     points = []
     rng = np.random.default_rng(251122460 + 50)
     nxt = 0
-    for lam in [float(x) for x in args.rates.split(",") if x]:
-        n = int(min(20000, max(2000, 10 * lam)))
+    for lam in rates:
+        n = int(min(max_n, max(500, seconds * lam)))
         arr = np.cumsum(rng.exponential(1.0 / lam, n))
         srv.reset_stats()
+        counts["eagain"] = 0
         start = time.perf_counter()
         lag = 0.0
         for i in range(n):
@@ -458,11 +568,35 @@ def serve_main(args, np, torch, W, E, dev):
         sst = srv.stats()
         pt = {"offered_qps": lam, "queries": n, "achieved_qps": sst["qps"], "p50_ms": sst["p50_ms"],
               "p99_ms": sst["p99_ms"], "max_ms": sst["max_ms"], "mean_batch": sst["mean_batch"],
-              "batches": sst["batches"], "max_submit_lag_ms": 1000 * lag}
+              "batches": sst["batches"], "queue_full_retries": counts["eagain"],
+              "max_submit_lag_ms": 1000 * lag}
         points.append(pt)
         log(f"[serve] rate {lam:.0f}/s: achieved {sst['qps']:.0f}/s p50 {sst['p50_ms']:.2f} ms "
             f"p99 {sst['p99_ms']:.2f} ms batch {sst['mean_batch']:.1f}")
     srv.close()
+    return points, check, scratch
+
+
+def serve_leg(args, np, torch, W, E, dev):
+    """A bounded serving measurement for the default benchmark line."""
+    wl, ix = serve_inventory(args, W, E, dev)
+    rates = [float(x) for x in args.serve_leg_rates.split(",") if x]
+    points, check, scratch = serve_run(args, np, wl, ix, E, rates, args.serve_leg_seconds, 40000, 4)
+    res = {"workload": f"serving: {wl.n_ads} ads x 64-d (BF16 scan + FP32 master), {wl.n_postings} "
+                       f"postings, F ~ U{{4..128}}, K in {{100, 500, 2000}}, Poisson arrivals, "
+                       f"{args.serve_scratch_gib:g} GiB scratch, max batch {args.serve_max_batch}, "
+                       f"2 batches in flight, batches of <= {args.f32_below} queries on the FP32 scan",
+           "points": points, "oracle_check": check, "max_wait_us": args.max_wait_us}
+    del ix
+    torch.cuda.synchronize()
+    return res
+
+
+def serve_main(args, np, torch, W, E, dev):
+    """Serving benchmark: the full arrival-rate sweep on the 50M-ad inventory."""
+    wl, ix = serve_inventory(args, W, E, dev)
+    rates = [float(x) for x in args.rates.split(",") if x]
+    points, check, scratch = serve_run(args, np, wl, ix, E, rates, 10.0, 20000, 4)
     sustained = [p for p in points if p["achieved_qps"] >= 0.95 * p["offered_qps"]]
     best = max(sustained, key=lambda p: p["achieved_qps"]) if sustained else None
     res = {
@@ -481,8 +615,7 @@ def serve_main(args, np, torch, W, E, dev):
         "p50_ms": best["p50_ms"] if best else None,
         "p99_ms": best["p99_ms"] if best else None,
         "points": points,
-        "cpu_baseline": {"value": n_check / cpu_el, "unit": "queries/s", "cores": oracle.num_threads(),
-                         "kind": "oracle", "sample": f"{n_check} queries scored over all ads by the FP64 oracle"},
+        "oracle_check": check,
     }
     print(json.dumps(res), flush=True)
 

@@ -127,6 +127,15 @@ ebr_status ebr_index_stats(const ebr_index* index, ebr_index_info* out);
 ebr_status ebr_decode_key(const ebr_index* index, int64_t key, uint32_t* ids, float* w,
                           int64_t cap, int64_t* len, void* hip_stream);
 
+/*
+ * Test hook: the same for the keys [key_begin, key_end), their lists concatenated in key
+ * order (the layout of post_ids / post_w in ebr_build_desc, from key_offsets[key_begin]).
+ * An index built without weights decodes them as 1. Blocking. EBR_EINVAL for a range
+ * outside [0, V]; EBR_ENOMEM if cap is smaller than the postings (nothing written).
+ */
+ebr_status ebr_decode_keys(const ebr_index* index, int64_t key_begin, int64_t key_end, uint32_t* ids,
+                           float* w, int64_t cap, int64_t* len, void* hip_stream);
+
 void ebr_free_index(ebr_index* index);
 
 /* ------------------------------------------------------------------------ query */
@@ -167,7 +176,12 @@ typedef struct {
 ebr_status ebr_workspace_size(const ebr_index* index, const ebr_batch* batch, size_t* bytes);
 
 /*
- * Top-K of every query of the batch. ws: device workspace of ws_bytes >=
+ * Top-K of every query of the batch: for each query (its non-zero feature values
+ * {(k, w_hat)}, the input of Algorithm 2 in Section 3.4, plus its user vector) the
+ * score s(u, a) of every ad (the summed logits of Section 3.1; the cross term of
+ * Section 3.3, equation "hitmatch") and the K ads with the largest scores (retrieval
+ * keeps a high-scoring subset, Section 3.1; top-k retrieval, Section 2; ties go to the
+ * smaller ad id, which the paper leaves open). ws: device workspace of ws_bytes >=
  * ebr_workspace_size (256-byte aligned). out_ids (uint32) and out_scores (FP32
  * s(u, a)) are device arrays of sum K_q entries, each query's slice ordered by
  * (score descending, id ascending); -0.0 scores are returned as +0.0.
@@ -183,7 +197,9 @@ ebr_status ebr_score_topk(const ebr_index* index, const ebr_batch* batch, void* 
 
 /*
  * Test hook for small inventories: the full B x N FP32 deep and wide terms as
- * the top-K path computes them (row-major, device). The path's score of ad a
+ * the top-K path computes them (row-major, device): the dual-tower inner product
+ * (Section 3.1, equation "dual-tower") and the HitMatch cross term (Section 3.3,
+ * equation "hitmatch"; the dense result of Algorithm 2 in Section 3.4). The path's score of ad a
  * for query q is exactly the FP32 sum deep[q*N+a] + wide[q*N+a]. Blocking.
  */
 ebr_status ebr_score_dense(const ebr_index* index, const ebr_batch* batch, void* ws,
@@ -350,8 +366,15 @@ typedef struct ebr_server ebr_server; /* opaque */
  *                groups of at most 16 queries, and the exact rescore of the reduced-
  *                precision scans returns the FP32 scan's ids and score bits, so a
  *                query's results do not depend on which scan its batch took.
+ *  max_queue     most queries waiting for a batch (not yet on the GPU); ebr_submit
+ *                returns EBR_EAGAIN while the queue is that full (0: 16 x max_batch)
  * Batches use the launch shape recorded in the index (ebr_autotune) for their
  * dtype and query-group count.
+ *
+ * Fault injection (tests of the error path): if the environment variable
+ * EBR_FAULT_BATCH holds a number n >= 0 when the server is created, the server's
+ * batch number n (counted from 0) reports EBR_EDEVICE to every ticket it holds
+ * instead of writing results; the batches before and after it run normally.
  */
 typedef struct {
     int32_t max_batch;
@@ -361,6 +384,7 @@ typedef struct {
     int32_t rescore_factor;
     int32_t graph;
     int32_t f32_below;
+    int32_t max_queue;
 } ebr_server_opts;
 
 /*
@@ -383,14 +407,15 @@ typedef struct {
  * Latency is per query, from ebr_submit to the moment its results are written
  * to the caller's buffers (host steady clock); percentiles over every query
  * completed since create or the last ebr_server_reset_stats.
- *  submitted, completed, failed   query counts; queued: waiting for a batch now
+ *  submitted, completed, failed   query counts; queued: waiting for a batch now;
+ *  rejected       submissions refused with EBR_EAGAIN because the queue was full
  *  batches        batches launched; mean_batch: queries per batch
  *  p50_ms, p99_ms, max_ms, mean_ms   latency
  *  elapsed_ms     wall time since create or reset; qps = completed / elapsed
  *  busy_ms        summed wall time of batches in flight (over slots)
  */
 typedef struct {
-    uint64_t submitted, completed, failed, queued, batches;
+    uint64_t submitted, completed, failed, queued, batches, rejected;
     double mean_batch, p50_ms, p99_ms, max_ms, mean_ms, elapsed_ms, qps, busy_ms;
 } ebr_server_info;
 
@@ -408,7 +433,8 @@ ebr_status ebr_server_create(const ebr_index* index, void* scratch, size_t scrat
  * they are written in (score descending, id ascending) order. *ticket
  * identifies the query for ebr_poll. Thread-safe.
  * EBR_EINVAL for an invalid query; EBR_ENOMEM if the query alone does not fit
- * a slot; EBR_ESHUTDOWN once destroy has begun.
+ * a slot; EBR_EAGAIN if max_queue queries are already waiting (nothing is
+ * queued: poll some tickets, then submit again); EBR_ESHUTDOWN once destroy has begun.
  */
 ebr_status ebr_submit(ebr_server* server, const ebr_query* q, uint32_t* ids_out,
                       float* scores_out, uint64_t* ticket);

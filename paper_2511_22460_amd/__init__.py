@@ -24,7 +24,7 @@ _STATUS = {0: "EBR_OK", -1: "EBR_EINVAL", -2: "EBR_ENOMEM", -3: "EBR_EDEVICE", -
            -5: "EBR_ENOTFOUND", -6: "EBR_ESHUTDOWN", -7: "EBR_EUNSUPPORTED"}
 
 #: every symbol include/ebr.h declares
-EXPORTS = ("ebr_index_size", "ebr_build_index", "ebr_index_stats", "ebr_decode_key",
+EXPORTS = ("ebr_index_size", "ebr_build_index", "ebr_index_stats", "ebr_decode_key", "ebr_decode_keys",
            "ebr_free_index", "ebr_workspace_size", "ebr_score_topk", "ebr_score_dense",
            "ebr_codec_size", "ebr_codec_encode", "ebr_codec_decode", "ebr_last_error",
            "ebr_version", "ebr_set_timing", "ebr_get_timings", "ebr_quantize_bf16",
@@ -126,7 +126,7 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("max_wait_us", ctypes.c_int32),
                 ("pipeline", ctypes.c_int32), ("scan_dtype", ctypes.c_int),
                 ("rescore_factor", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("f32_below", ctypes.c_int32)]
+                ("f32_below", ctypes.c_int32), ("max_queue", ctypes.c_int32)]
 
 
 class Query(ctypes.Structure):
@@ -138,7 +138,8 @@ class Query(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("failed", ctypes.c_uint64), ("queued", ctypes.c_uint64),
-                ("batches", ctypes.c_uint64), ("mean_batch", ctypes.c_double),
+                ("batches", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("mean_batch", ctypes.c_double),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("elapsed_ms", ctypes.c_double), ("qps", ctypes.c_double),
@@ -171,6 +172,7 @@ def load():
         "ebr_build_index": ([P, P, sz, P, ctypes.POINTER(P)], st),
         "ebr_index_stats": ([P, P], st),
         "ebr_decode_key": ([P, i64, P, P, i64, ctypes.POINTER(i64), P], st),
+        "ebr_decode_keys": ([P, i64, i64, P, P, i64, ctypes.POINTER(i64), P], st),
         "ebr_free_index": ([P], None),
         "ebr_workspace_size": ([P, P, ctypes.POINTER(sz)], st),
         "ebr_score_topk": ([P, P, P, sz, P, P, P], st),
@@ -345,6 +347,21 @@ class Index:
         w = torch.empty(cap, dtype=torch.float32, device=self.device)
         _check(load().ebr_decode_key(self._h, key, ids.data_ptr(), w.data_ptr(), cap,
                                      ctypes.byref(n), _stream(stream)), "ebr_decode_key")
+        return ids[:n.value], w[:n.value]
+
+    def decode_keys(self, key_begin: int, key_end: int, stream=None):
+        """GPU decode of the lists of keys [key_begin, key_end), concatenated in key order."""
+        import torch
+        n = ctypes.c_int64()
+        rc = load().ebr_decode_keys(self._h, key_begin, key_end, None, None, 0, ctypes.byref(n),
+                                    _stream(stream))
+        if rc not in (EBR_OK, EBR_ENOMEM):
+            _check(rc, "ebr_decode_keys")
+        cap = max(1, n.value)
+        ids = torch.empty(cap, dtype=torch.int32, device=self.device)
+        w = torch.empty(cap, dtype=torch.float32, device=self.device)
+        _check(load().ebr_decode_keys(self._h, key_begin, key_end, ids.data_ptr(), w.data_ptr(), cap,
+                                      ctypes.byref(n), _stream(stream)), "ebr_decode_keys")
         return ids[:n.value], w[:n.value]
 
     # -------------------------------------------------------------------------- batches
@@ -527,12 +544,13 @@ class Server:
 
     def __init__(self, index: "Index", scratch_bytes: int, max_batch: int = 256,
                  max_wait_us: int = 200, pipeline: int = 2, scan_dtype: int = F32,
-                 rescore_factor: int = 4, graph: bool = False, f32_below: int = 0):
+                 rescore_factor: int = 4, graph: bool = False, f32_below: int = 0,
+                 max_queue: int = 0):
         import torch
         self.index = index
         self.scratch = torch.empty(max(256, int(scratch_bytes)), dtype=torch.uint8, device=index.device)
         opts = ServerOpts(max_batch, max_wait_us, pipeline, scan_dtype, rescore_factor,
-                          1 if graph else 0, int(f32_below))
+                          1 if graph else 0, int(f32_below), int(max_queue))
         h = ctypes.c_void_p()
         _check(load().ebr_server_create(index._h, self.scratch.data_ptr(), self.scratch.numel(),
                                         ctypes.byref(opts), ctypes.byref(h)), "ebr_server_create")

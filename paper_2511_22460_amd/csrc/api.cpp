@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <new>
@@ -463,20 +464,31 @@ ebr_status ebr_index_stats(const ebr_index* index, ebr_index_info* out) {
 
 void ebr_free_index(ebr_index* index) { delete index; }
 
-ebr_status ebr_decode_key(const ebr_index* index, int64_t key, uint32_t* ids, float* w,
-                          int64_t cap, int64_t* len, void* hip_stream) {
+ebr_status ebr_decode_keys(const ebr_index* index, int64_t key_begin, int64_t key_end, uint32_t* ids,
+                           float* w, int64_t cap, int64_t* len, void* hip_stream) {
     if (!index || !len) { set_error("NULL argument"); return EBR_EINVAL; }
-    if (key < 0 || key >= index->n_keys) { set_error("key %lld out of range", (long long)key); return EBR_EINVAL; }
-    const int64_t n = index->key_post_off[key + 1] - index->key_post_off[key];
+    if (key_begin < 0 || key_end < key_begin || key_end > index->n_keys) {
+        set_error("key range [%lld, %lld) outside [0, %lld)", (long long)key_begin, (long long)key_end,
+                  (long long)index->n_keys);
+        return EBR_EINVAL;
+    }
+    const int64_t p0 = index->key_post_off[key_begin], n = index->key_post_off[key_end] - p0;
     *len = n;
-    if (cap < n) { set_error("capacity %lld < list length %lld", (long long)cap, (long long)n); return EBR_ENOMEM; }
+    if (cap < n) { set_error("capacity %lld < %lld postings", (long long)cap, (long long)n); return EBR_ENOMEM; }
     if (n == 0) return EBR_OK;
     if (!ids || !w) { set_error("NULL output"); return EBR_EINVAL; }
-    const uint32_t c0 = index->key_chunk_off[key], c1 = index->key_chunk_off[key + 1];
-    int rc = launch_decode_key(index->chunks, index->words, index->weights, c0, c1 - c0, ids, w, hip_stream);
+    const uint32_t c0 = index->key_chunk_off[key_begin], c1 = index->key_chunk_off[key_end];
+    int rc = launch_decode_key(index->chunks, index->words, index->weights, c0, c1 - c0, (uint32_t)p0,
+                               ids, w, hip_stream);
     if (rc) { set_error("decode launch failed: %s", hipGetErrorString((hipError_t)rc)); return EBR_EDEVICE; }
     HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
     return EBR_OK;
+}
+
+ebr_status ebr_decode_key(const ebr_index* index, int64_t key, uint32_t* ids, float* w,
+                          int64_t cap, int64_t* len, void* hip_stream) {
+    if (index && (key < 0 || key >= index->n_keys)) { set_error("key %lld out of range", (long long)key); return EBR_EINVAL; }
+    return ebr_decode_keys(index, key, key + 1, ids, w, cap, len, hip_stream);
 }
 
 }  // extern "C"
@@ -1049,6 +1061,13 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
     se.n_valid = P.n_sample_valid;
     se.status = status;
     se.only_status = -1;
+    // Test hook: EBR_FORCE_SELECT_ROUND = 1 or 2 makes the first threshold follow the rule of
+    // that revision round (1: the sample's K'-th key; 2: no threshold, every ad a candidate),
+    // so that the rounds' thresholds are exercised on ordinary inputs.
+    if (const char* fr = std::getenv("EBR_FORCE_SELECT_ROUND")) {
+        if (fr[0] == '1' && fr[1] == '\0') se.round = 1;
+        if (fr[0] == '2' && fr[1] == '\0') se.round = 2;
+    }
     se.thresh = thr;
     se.ctl = ctl;
     ScoreArgs ca = score_args(ix, P, batch, ws);
@@ -1126,6 +1145,7 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
         // sample pass and per-query threshold (for K' candidates on approximate scans)
         LAUNCH(launch_score(sa, ix.dim, 1, sh.sample_ranges, ls));
         LAUNCH(launch_select(se, B, ls));
+        se.round = 0;
         e_smp1 = clk.mark();
         // Selection rounds: round r > 0 runs only if round r - 1 left a query unresolved.
         // Queries short of K' candidates first take the sample's K'-th key (which at least

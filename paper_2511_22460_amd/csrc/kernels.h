@@ -166,8 +166,11 @@ int64_t scan_tmp_words(int64_t n);
 int launch_excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, void* stream);
 int launch_decode(const DecodeArgs& a, int place, void* stream);
 int launch_refine(const DecodeArgs& a, void* stream);
+// Decode the chunks [chunk0, chunk0 + n_chunks) of consecutive keys: posting p (index into the
+// index's posting order) goes to ids / w at p - post_base; null weights decode as 1.
 int launch_decode_key(const ChunkHdr* chunks, const uint32_t* words, const float* weights,
-                      uint32_t chunk0, uint32_t n_chunks, uint32_t* ids, float* w, void* stream);
+                      uint32_t chunk0, uint32_t n_chunks, uint32_t post_base, uint32_t* ids,
+                      float* w, void* stream);
 bool score_dim_supported(int dim);
 // Queries per query group of the scoring kernel for this embedding width.
 int score_group_queries(int dim);

@@ -215,18 +215,20 @@ __global__ __launch_bounds__(256) void k_refine(DecodeArgs a) {
     }
 }
 
+// One wavefront per chunk of a run of consecutive keys: posting t of the run (in key order) goes
+// to ids[t] / w[t]; an index without stored weights (unit weights) writes 1.
 __global__ __launch_bounds__(64) void k_decode_key(const ChunkHdr* chunks, const uint32_t* words,
                                                    const float* weights, uint32_t chunk0,
-                                                   uint32_t* ids, float* w) {
+                                                   uint32_t post_base, uint32_t* ids, float* w) {
     const int lane = lane_id();
     const uint32_t chunk = chunk0 + blockIdx.x;
     int count;
     uint32_t post_off;
     const uint32_t id = decode_chunk_lane(chunks, words, chunk, &count, &post_off);
     if (lane < count) {
-        const uint32_t out = blockIdx.x * kChunk + lane;
+        const uint32_t out = post_off - post_base + (uint32_t)lane;
         ids[out] = id;
-        w[out] = weights[post_off + lane];
+        w[out] = weights ? weights[post_off + lane] : 1.0f;
     }
 }
 
@@ -474,10 +476,11 @@ int launch_decode(const DecodeArgs& a, int place, void* stream) {
 }
 
 int launch_decode_key(const ChunkHdr* chunks, const uint32_t* words, const float* weights,
-                      uint32_t chunk0, uint32_t n_chunks, uint32_t* ids, float* w, void* stream) {
+                      uint32_t chunk0, uint32_t n_chunks, uint32_t post_base, uint32_t* ids,
+                      float* w, void* stream) {
     if (n_chunks == 0) return 0;
     hipLaunchKernelGGL(k_decode_key, dim3(n_chunks), dim3(64), 0, (hipStream_t)stream, chunks,
-                       words, weights, chunk0, ids, w);
+                       words, weights, chunk0, post_base, ids, w);
     return last(hipSuccess);
 }
 

@@ -385,7 +385,8 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             s_thr_hi[i] = hi;
             s_thr_lo[i] = in ? a.thresh[2 * q + 1] : 0xffffffffu;
             const bool live = in && a.active[q];
-            s_thr[i] = live ? key_score(hi) : __builtin_nanf("");
+            // key 0 lies below every finite score's key: no threshold, every ad is a candidate
+            s_thr[i] = live ? (hi == 0u ? -__builtin_inff() : key_score(hi)) : __builtin_nanf("");
             s_live[i] = live ? 1u : 0u;
         } else {
             s_live[i] = in ? 1u : 0u;

@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -30,6 +31,8 @@ using Clock = std::chrono::steady_clock;
 
 constexpr int kServerMaxBatch = 4096;
 constexpr int kServerMaxPipeline = 4;
+// Queued queries per batch of max_batch when the options leave the queue bound at 0.
+constexpr int kDefaultQueueBatches = 16;
 // Results per query the pinned staging is sized for (a batch with larger K holds fewer
 // queries; one query of any allowed K always fits).
 constexpr int kStagedK = 2048;
@@ -86,7 +89,11 @@ struct ebr_server {
     uint64_t next_ticket = 1;
     bool stopping = false;
 
-    uint64_t submitted = 0, completed = 0, failed = 0, batches = 0, batched = 0;
+    uint64_t submitted = 0, completed = 0, failed = 0, batches = 0, batched = 0, rejected = 0;
+    // fault injection for tests of the error path: the batch with this index (counted from 0
+    // over the server's life) reports a device error instead of its results; -1: never
+    int64_t fault_batch = -1;
+    uint64_t batches_run = 0;
     std::vector<double> lat_ms;
     double busy_ms = 0.0;
     Clock::time_point t_stats;
@@ -230,6 +237,18 @@ void ebr_server::run_batch(Slot& sl, std::vector<Ticket*>& take) {
             ebr_timings tm{};
             st = run_topk(*ix, &bt, p, ws_bytes, d_ids, d_scores, sl.stream, &tm, sl.graph);
         }
+        bool inject = false;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            inject = fault_batch >= 0 && (int64_t)batches_run == fault_batch;
+            ++batches_run;
+        }
+        if (!st && inject) {
+            (void)hipStreamSynchronize(sl.stream);
+            set_error("device step failed (fault injected by EBR_FAULT_BATCH for batch %lld)",
+                      (long long)fault_batch);
+            st = EBR_EDEVICE;
+        }
         if (!st && n_out > 0) {
             he = hipMemcpyAsync(sl.h_ids, d_ids, 4 * (size_t)n_out, hipMemcpyDeviceToHost, sl.stream);
             if (he == hipSuccess)
@@ -288,6 +307,8 @@ ebr_status ebr_server_create(const ebr_index* index, void* scratch, size_t scrat
     if (o.pipeline == 0) o.pipeline = 2;
     if (o.max_wait_us < 0) o.max_wait_us = 0;
     if (o.f32_below < 0) o.f32_below = 0;
+    if (o.max_queue == 0) o.max_queue = kDefaultQueueBatches * o.max_batch;
+    if (o.max_queue < 1) { set_error("max_queue must be >= 1 (0: the default)"); return EBR_EINVAL; }
     if (o.max_batch < 1 || o.max_batch > kServerMaxBatch) { set_error("max_batch must be in [1, %d]", kServerMaxBatch); return EBR_EINVAL; }
     if (o.pipeline < 1 || o.pipeline > kServerMaxPipeline) { set_error("pipeline must be in [1, %d]", kServerMaxPipeline); return EBR_EINVAL; }
     if (o.scan_dtype != EBR_F32 && o.scan_dtype != EBR_BF16 && o.scan_dtype != EBR_FP8E4M3) { set_error("unknown scan dtype"); return EBR_EINVAL; }
@@ -343,6 +364,11 @@ ebr_status ebr_server_create(const ebr_index* index, void* scratch, size_t scrat
             if (o.graph && ebr_graph_create(&sl.graph) != EBR_OK) return fail("ebr_graph_create", hipErrorUnknown);
         }
         S->t_stats = Clock::now();
+        if (const char* f = std::getenv("EBR_FAULT_BATCH")) {
+            char* end = nullptr;
+            const long long v = std::strtoll(f, &end, 10);
+            if (end != f && *end == '\0' && v >= 0) S->fault_batch = v;
+        }
         for (int i = 0; i < o.pipeline; ++i) S->workers.emplace_back([S, i] { S->worker(i); });
     } catch (const std::exception&) {
         set_error("host out of resources");
@@ -404,6 +430,11 @@ ebr_status ebr_submit(ebr_server* S, const ebr_query* q, uint32_t* ids_out, floa
         {
             std::lock_guard<std::mutex> lk(S->mu);
             if (S->stopping) { set_error("server is shutting down"); return reject(EBR_ESHUTDOWN); }
+            if ((int64_t)S->queue.size() >= (int64_t)S->opt.max_queue) {
+                ++S->rejected;
+                set_error("queue full (%d queries waiting); poll and submit again", S->opt.max_queue);
+                return reject(EBR_EAGAIN);
+            }
             t->id = S->next_ticket++;
             S->tickets[t->id] = t;
             S->queue.push_back(t);
@@ -451,6 +482,7 @@ ebr_status ebr_server_stats(ebr_server* S, ebr_server_info* out) {
         r.completed = S->completed;
         r.failed = S->failed;
         r.queued = S->queue.size();
+        r.rejected = S->rejected;
         r.batches = S->batches;
         r.mean_batch = S->batches ? (double)S->batched / (double)S->batches : 0.0;
         r.busy_ms = S->busy_ms;
@@ -476,7 +508,7 @@ ebr_status ebr_server_stats(ebr_server* S, ebr_server_info* out) {
 ebr_status ebr_server_reset_stats(ebr_server* S) {
     if (!S) { set_error("NULL argument"); return EBR_EINVAL; }
     std::lock_guard<std::mutex> lk(S->mu);
-    S->completed = S->failed = S->batches = S->batched = 0;
+    S->completed = S->failed = S->batches = S->batched = S->rejected = 0;
     S->submitted = S->queue.size();
     S->lat_ms.clear();
     S->busy_ms = 0.0;

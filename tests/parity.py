@@ -69,3 +69,33 @@ def check_topk(ids, scores, k, s_all, *, rel_tol=1e-5, cond_all=None, exact=Fals
             raise ParityError(f"{label}: exact-tie result differs from the oracle's ids")
     hits = np.isin(ids, order[:k]) | (np.abs(s - s_k) <= delta)
     return float(hits.sum()) / k
+
+
+def check_topk_vs_oracle(ids, scores, k, o_ids, o_scores, full_scores, *, rel_tol=1e-5, label=""):
+    """check_topk for one query, given the oracle's own top-K (o_ids, o_scores: FP64, ordered by
+    (score desc, id asc)) so that the scores of all ads are needed only when the two id sets
+    differ. When the sets are equal the set rule holds by itself (the oracle's top-K holds every
+    ad above its K-th score, and nothing below it), so scores and order are checked against the
+    oracle's values; otherwise full_scores() (FP64 scores of all ads) decides by check_topk.
+    Returns recall@k."""
+    ids = np.asarray(ids).astype(np.int64)
+    g = np.asarray(scores, dtype=np.float64)
+    o_ids = np.asarray(o_ids).astype(np.int64)
+    if len(ids) != k or len(g) != k or len(o_ids) != k:
+        raise ParityError(f"{label}: expected {k} results, got {len(ids)}")
+    if k == 0:
+        return 1.0
+    if len(np.unique(ids)) == k and np.array_equal(np.sort(ids), np.sort(o_ids)):
+        s_of = dict(zip(o_ids.tolist(), np.asarray(o_scores, dtype=np.float64).tolist()))
+        s = np.array([s_of[a] for a in ids.tolist()])
+        err = np.abs(g - s)
+        bad = err > rel_tol * np.abs(s)
+        if bad.any():
+            i = int(np.argmax(err - rel_tol * np.abs(s)))
+            raise ParityError(f"{label}: score of ad {ids[i]} is {g[i]!r}, oracle {s[i]!r} "
+                              f"({int(bad.sum())} of {k} outside tolerance)")
+        for i in range(k - 1):
+            if g[i] < g[i + 1] or (g[i] == g[i + 1] and ids[i] > ids[i + 1]):
+                raise ParityError(f"{label}: result not ordered at position {i}")
+        return 1.0
+    return check_topk(ids, scores, k, full_scores(), rel_tol=rel_tol, label=label)

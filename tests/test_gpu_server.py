@@ -182,3 +182,80 @@ def test_destroy_drains_unpolled_tickets(served):
     for q, t, (ids, sc, k) in held:
         a_ids, a_sc = alone(ix, wl, q)
         assert np.array_equal(ids[:k], a_ids)
+
+
+def test_full_queue_returns_eagain_then_accepts_after_polling(served):
+    wl, ix = served
+    # one slot, batches of up to 64 and a long batching window: the worker holds off for a
+    # full second, so the first two submissions stay queued and the third finds the queue full
+    with E.Server(ix, scratch_bytes=256 << 20, max_batch=64, max_wait_us=1_000_000, pipeline=1,
+                  max_queue=2) as srv:
+        t0 = srv.submit(wl.user_emb[0], wl.query_keys(0), int(wl.k[0]))
+        t1 = srv.submit(wl.user_emb[1], wl.query_keys(1), int(wl.k[1]))
+        with pytest.raises(E.EbrError) as ei:
+            srv.submit(wl.user_emb[2], wl.query_keys(2), int(wl.k[2]))
+        assert ei.value.status == E.EBR_EAGAIN
+        st = srv.stats()
+        assert st["rejected"] == 1 and st["submitted"] == 2
+        res = {0: srv.poll(t0), 1: srv.poll(t1)}
+        # the queue has drained into a batch: the same query is accepted now
+        t2 = srv.submit(wl.user_emb[2], wl.query_keys(2), int(wl.k[2]))
+        res[2] = srv.poll(t2)
+        assert srv.stats()["completed"] == 3
+    check_served(wl, ix, res)
+
+
+def test_injected_device_fault_reaches_every_ticket_of_its_batch(served, monkeypatch):
+    wl, ix = served
+    # batch 1 (the second) fails: its four tickets get EBR_EDEVICE, batches 0 and 2 are served
+    monkeypatch.setenv("EBR_FAULT_BATCH", "1")
+    with E.Server(ix, scratch_bytes=256 << 20, max_batch=4, max_wait_us=5_000_000, pipeline=1) as srv:
+        monkeypatch.delenv("EBR_FAULT_BATCH")
+        outcome = {}
+        for b in range(3):
+            qs = list(range(4 * b, 4 * b + 4))
+            t = submit_all(srv, wl, qs)   # four queries: a full batch, launched at once
+            for q, tk in t.items():
+                try:
+                    outcome[q] = srv.poll(tk)
+                except E.EbrError as e:
+                    outcome[q] = e.status
+        st = srv.stats()
+    failed = sorted(q for q, r in outcome.items() if not isinstance(r, tuple))
+    assert failed == [4, 5, 6, 7]
+    assert all(outcome[q] == E.EBR_EDEVICE for q in failed)
+    assert st["failed"] == 4 and st["completed"] == 8 and st["batches"] == 3
+    check_served(wl, ix, {q: r for q, r in outcome.items() if isinstance(r, tuple)})
+
+
+@pytest.mark.timeout(900)
+def test_served_50m_inventory_matches_the_oracle():
+    """The serving inventory: 50M ads x 64-d (FP32 master + BF16 scan copy), ~1.5e9 postings,
+    resident on one GPU; queries with 4..128 features and K in {100, 500, 2000} submitted as
+    the serving benchmark does (BF16 scan with 4 K rescored, batches of at most 16 queries on
+    the FP32 scan): a burst of 40 (batched on the BF16 scan) and four singles. Twelve served
+    results, from the burst and the singles, are checked against the oracle."""
+    from oracle_check import check_batch_vs_oracle
+    dev()
+    wl = W.make("c5", n_queries=44)
+    assert wl.n_ads == 50_000_000 and wl.n_postings > 1_400_000_000
+    assert set(int(k) for k in wl.k) <= {100, 500, 2000}
+    ix = E.Index.from_workload(wl, dtypes=1 | (1 << E.BF16))
+    with E.Server(ix, scratch_bytes=8 << 30, max_batch=256, max_wait_us=20_000, pipeline=2,
+                  scan_dtype=E.BF16, rescore_factor=4, f32_below=16) as srv:
+        t = submit_all(srv, wl, range(40))
+        res = {q: srv.poll(tk) for q, tk in t.items()}
+        st_burst = srv.stats()
+        for q in range(40, 44):
+            res[q] = srv.poll(srv.submit(wl.user_emb[q], wl.query_keys(q), int(wl.k[q])))
+        st = srv.stats()
+    assert st["completed"] == 44 and st["failed"] == 0
+    assert st_burst["mean_batch"] > 16, st_burst   # the burst ran on the BF16 scan
+    qs = [0, 7, 13, 21, 29, 35, 38, 39, 40, 41, 42, 43]
+    sub = wl.subset(qs)
+    ids = np.concatenate([res[q][0] for q in qs])
+    sc = np.concatenate([res[q][1] for q in qs])
+    offs = np.zeros(len(qs) + 1, np.int64)
+    offs[1:] = np.cumsum(sub.k)
+    del ix
+    check_batch_vs_oracle(sub, ids, sc, offs, label="served 50M")

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import workloads as W
+from oracle_check import check_batch_vs_oracle
 from parity import check_topk
 
 pytestmark = pytest.mark.gpu
@@ -72,6 +73,16 @@ def test_decode_every_key_bit_exact(small):
         assert np.array_equal(w.cpu().numpy().view(np.uint32), wl.post_w[s:e].view(np.uint32)), k
     st = ix.stats()
     assert st["n_postings"] == wl.n_postings and st["bytes_per_posting"] < 6.0
+    # the range hook: every list at once, an inner range, an empty range, a bad range
+    ids, w = ix.decode_keys(0, wl.n_keys)
+    assert np.array_equal(ids.cpu().numpy().view(np.uint32), wl.post_ids)
+    assert np.array_equal(w.cpu().numpy().view(np.uint32), wl.post_w.view(np.uint32))
+    ids, w = ix.decode_keys(7, 300)
+    s, e = wl.key_offsets[7], wl.key_offsets[300]
+    assert np.array_equal(ids.cpu().numpy().view(np.uint32), wl.post_ids[s:e])
+    assert ix.decode_keys(5, 5)[0].numel() == 0
+    with pytest.raises(E.EbrError):
+        ix.decode_keys(10, wl.n_keys + 1)
 
 
 # ----------------------------------------------------------------------------- dense terms
@@ -126,6 +137,39 @@ def test_topk_is_deterministic_and_same_alone_as_in_a_mix(small):
         a, b = offs[q], offs[q + 1]
         assert np.array_equal(a_ids, ids1[a:b]), q
         assert np.array_equal(a_sc.view(np.uint32), sc1[a:b].view(np.uint32)), q
+
+
+@pytest.mark.parametrize("rnd", ["1", "2"])
+def test_forced_selection_rounds_give_the_same_result(small, monkeypatch, rnd):
+    """The threshold-revision rounds on ordinary inputs: the first threshold follows round 1's
+    rule (the sample's K'-th key) or round 2's (no threshold: every ad is a candidate, the
+    candidate buffer overflows on 20k ads, and the revised threshold resolves it). The result
+    must be the normal path's, bit for bit, and the oracle's."""
+    wl, ix = small
+    ids, sc, offs = run(ix, wl)
+    monkeypatch.setenv("EBR_FORCE_SELECT_ROUND", rnd)
+    E.set_timing(True)
+    try:
+        f_ids, f_sc, _ = run(ix, wl)
+        rounds = E.last_timings()["rounds"]
+    finally:
+        E.set_timing(False)
+        monkeypatch.delenv("EBR_FORCE_SELECT_ROUND")
+    assert np.array_equal(f_ids, ids) and np.array_equal(f_sc.view(np.uint32), sc.view(np.uint32))
+    if rnd == "2":
+        assert rounds >= 2
+    check_all(wl, f_ids, f_sc, offs, qs=range(0, wl.n_queries, 7), label=f"forced round {rnd}")
+    # a small inventory: every ad fits the candidate buffer, so round 2's rule resolves at once
+    wl2 = small_wl(n_ads=3_001, n_queries=20, k=(1, 200))
+    ix2 = E.Index.from_workload(wl2)
+    ids2, sc2, offs2 = run(ix2, wl2)
+    monkeypatch.setenv("EBR_FORCE_SELECT_ROUND", rnd)
+    try:
+        g_ids, g_sc, _ = run(ix2, wl2)
+    finally:
+        monkeypatch.delenv("EBR_FORCE_SELECT_ROUND")
+    assert np.array_equal(g_ids, ids2) and np.array_equal(g_sc.view(np.uint32), sc2.view(np.uint32))
+    check_all(wl2, g_ids, g_sc, offs2, label=f"forced round {rnd}, 3k ads")
 
 
 def test_small_groups_match_the_matrix_core_path_bit_for_bit(small):
@@ -247,24 +291,38 @@ def c2():
     return wl, ix
 
 
-def test_c2_full_size_sampled_queries(c2):
-    """10M ads, ~4e8 postings, 256 queries x 32 keys, K = 1000, the benchmark's launch.
-    Four sampled queries are checked in full against the oracle."""
+@pytest.mark.timeout(900)
+def test_c2_full_size_every_query(c2):
+    """10M ads, ~4e8 postings, 256 queries x 32 keys, K = 1000, in the benchmark's launch
+    (autotuned shape): every query of the batch is checked against the oracle."""
     wl, ix = c2
     ids, sc, offs = run(ix, wl)
     assert offs[-1] == 256 * 1000
-    check_all(wl, ids, sc, offs, qs=[0, 77, 154, 255], label="c2")
     # the benchmark autotunes the launch shape first: the tuned launch gives the same bits
     U = torch.from_numpy(np.ascontiguousarray(wl.user_emb)).to(dev())
     rep, _ = ix.autotune(U, wl.feat_offsets, wl.feat_keys, wl.k, wl.feat_mult, reps=1)
     t_ids, t_sc, _ = run(ix, wl)
     assert np.array_equal(t_ids, ids) and np.array_equal(t_sc.view(np.uint32), sc.view(np.uint32)), rep
+    check_batch_vs_oracle(wl, ids, sc, offs, rel_tol=REL, label="c2")
 
 
-def test_c2_decode_sampled_keys_bit_exact(c2):
+@pytest.mark.timeout(900)
+def test_c2_decode_every_key_bit_exact(c2):
+    """GPU decode of all 1M lists (~4e8 postings) of the 10M-ad index, in slices of keys,
+    against the arrays the index was built from: ids equal, weights equal bit for bit."""
     wl, ix = c2
-    for k in [0, 1, 2, 17, 500, 12_345, 999_999]:
+    V = wl.n_keys
+    step = 1 << 17
+    for k0 in range(0, V, step):
+        k1 = min(V, k0 + step)
+        ids, w = ix.decode_keys(k0, k1)
+        s, e = int(wl.key_offsets[k0]), int(wl.key_offsets[k1])
+        assert ids.numel() == e - s
+        assert np.array_equal(ids.cpu().numpy().view(np.uint32), wl.post_ids[s:e]), (k0, k1)
+        assert np.array_equal(w.cpu().numpy().view(np.uint32), wl.post_w[s:e].view(np.uint32)), (k0, k1)
+        del ids, w
+    # the single-key hook agrees on the longest and the last list
+    for k in (0, V - 1):
         ids, w = ix.decode_key(k)
         s, e = wl.key_offsets[k], wl.key_offsets[k + 1]
         assert np.array_equal(ids.cpu().numpy().view(np.uint32), wl.post_ids[s:e]), k
-        assert np.array_equal(w.cpu().numpy().view(np.uint32), wl.post_w[s:e].view(np.uint32)), k

@@ -345,3 +345,24 @@ def test_parity_criteria_accept_and_reject():
     assert check_topk(np.array([0], np.uint32), np.array([1.0]), 1, s2) == 1.0
     with pytest.raises(ParityError):          # exact mode has no band
         check_topk(np.array([0], np.uint32), np.array([1.0]), 1, s2, exact=True)
+
+
+def test_parity_against_the_oracles_topk():
+    from parity import check_topk_vs_oracle
+    s = np.array([5.0, 4.0, 4.0 + 1e-9, 3.0, 1.0, 0.5])
+    o_ids = np.array([0, 2, 1], np.int64)          # 4 + 1e-9 ranks before 4
+    o_sc = s[o_ids]
+    full = lambda: s
+    # same set and order: decided without the full scores
+    assert check_topk_vs_oracle(np.array([0, 2, 1]), s[[0, 2, 1]], 3, o_ids, o_sc,
+                                lambda: pytest.fail("full scores not needed")) == 1.0
+    # a swap inside the band: the set differs from nothing, order follows the returned scores
+    assert check_topk_vs_oracle(np.array([0, 1, 2]), np.array([5.0, 4.0, 4.0]), 3, o_ids, o_sc, full) == 1.0
+    with pytest.raises(ParityError):                # wrong order of the returned scores
+        check_topk_vs_oracle(np.array([0, 1, 2]), np.array([5.0, 4.0, 4.00001]), 3, o_ids, o_sc, full)
+    with pytest.raises(ParityError):                # an ad below the band: decided by full scores
+        check_topk_vs_oracle(np.array([0, 2, 3]), s[[0, 2, 3]], 3, o_ids, o_sc, full)
+    with pytest.raises(ParityError):                # a score off by more than the tolerance
+        check_topk_vs_oracle(np.array([0, 2, 1]), np.array([5.0, 4.01, 4.0]), 3, o_ids, o_sc, full)
+    with pytest.raises(ParityError):                # duplicate ids
+        check_topk_vs_oracle(np.array([0, 0, 2]), s[[0, 0, 2]], 3, o_ids, o_sc, full)
