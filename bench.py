@@ -158,6 +158,11 @@ def main():
                     help="skip the autotuner (default launch shapes)")
     ap.add_argument("--batch-steps", type=int, default=5,
                     help="timed batches of the 4096-query uneven batch (0: skip)")
+    ap.add_argument("--leg", choices=("f32", "bf16", "fp8", "uneven", "b1", "b16"),
+                    help="profiling run: only this batch kind on the 10M-ad index (the 256-query "
+                         "batch on FP32 / BF16 / FP8, the 4096-query uneven batch on BF16, or the "
+                         "first 1 / 16 queries on FP32), --warmup + --steps batches with "
+                         "per-phase times, default launch shapes; prints one JSON line of times")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -185,6 +190,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
         return
+    if args.leg:
+        return leg_main(args, np, torch, W, E, dev)
     t0 = time.time()
     wl = W.make(args.config)
     log(f"[bench] generated {args.config}: N={wl.n_ads} V={wl.n_keys} postings={wl.n_postings} "
@@ -443,6 +450,34 @@ def main():
     if parity is not None and not parity["ok"]:
         log("[bench] the timed outputs do not match the oracle")
         sys.exit(3)
+
+
+def leg_main(args, np, torch, W, E, dev):
+    """One batch kind, --warmup + --steps times: the unit a rocprofv3 run profiles."""
+    wl = W.make("c2")
+    ix = E.Index.from_workload(wl, device=dev, dtypes=1 | (1 << E.BF16) | (1 << E.FP8E4M3))
+    q = W.queries_for(wl, "c4") if args.leg == "uneven" else wl
+    if args.leg in ("b1", "b16"):
+        q = wl.subset(range(1 if args.leg == "b1" else 16))
+    sd = {"f32": E.F32, "b1": E.F32, "b16": E.F32, "bf16": E.BF16, "fp8": E.FP8E4M3,
+          "uneven": E.BF16}[args.leg]
+    U = torch.from_numpy(np.ascontiguousarray(q.user_emb)).to(dev)
+    nk = int(np.sum(q.k))
+    out = (torch.empty(nk, dtype=torch.int32, device=dev), torch.empty(nk, dtype=torch.float32, device=dev))
+    E.set_timing(True)
+    times = []
+    for i in range(args.warmup + args.steps):
+        ix.score_topk(U, q.feat_offsets, q.feat_keys, q.k, q.feat_mult, scan_dtype=sd,
+                      rescore_factor=4, out=out)
+        t = E.last_timings()
+        log(f"[leg {args.leg}] batch {i}: score {t['score_ms']:.3f} ms, decode {t['decode_ms']:.3f}, "
+            f"sample {t['sample_ms']:.3f}, finalize {t['finalize_ms']:.3f}, rescore {t['rescore_ms']:.3f}")
+        if i >= args.warmup:
+            times.append(t)
+    torch.cuda.synchronize()
+    keys = ("host_ms", "decode_ms", "sample_ms", "score_ms", "finalize_ms", "rescore_ms")
+    print(json.dumps({"leg": args.leg, "queries": q.n_queries, "steps": args.steps,
+                      "phases_ms": {k: float(np.mean([t[k] for t in times])) for k in keys}}), flush=True)
 
 
 def serve_inventory(args, W, E, dev, n_queries=4096):

@@ -148,7 +148,11 @@ void ebr_free_index(ebr_index* index);
  *  feat_keys     host, keys of each query, distinct within a query, < V.
  *  feat_mult     host FP32 multiplier per feature (the paper's w_hat), or NULL
  *                for 1.0.
- *  k             host, per-query K, 0 <= K_q <= min(N, 8192).
+ *  k             host, per-query K, 0 <= K_q <= N. A query whose K_q (for reduced-precision
+ *                scans rescore_factor * K_q) exceeds 8192, the selection path's in-LDS sort, is
+ *                answered by a full sort of all N of its scores instead (FP32 scan, 64-bit
+ *                cross-term cells; the workspace then holds 24 N bytes more): slower, same
+ *                ordering rules.
  *  scan_dtype    EBR_F32: exact FP32 scan. EBR_BF16 / EBR_FP8E4M3: the scan streams that
  *                copy of the embeddings (EBR_EUNSUPPORTED if the index has none), keeps
  *                the rescore_factor * K_q best approximate candidates, rescores them
@@ -157,8 +161,15 @@ void ebr_free_index(ebr_index* index);
  *                is checked on the GPU, and a query that fails it is rerun with the FP32
  *                scan. The rescore computes each candidate's score with the FP32 scan's
  *                own arithmetic, so the results are the FP32 scan's ids and score bits.
- *  rescore_factor  candidates per result for reduced-precision scans (<= 0: 4);
- *                rescore_factor * K_q <= 8192. Ignored for F32.
+ *  rescore_factor  candidates per result for reduced-precision scans (<= 0: 4). Ignored
+ *                for F32.
+ *  wide64        0: the cross term of Section 3.3 (equation "hitmatch") is summed in 32-bit
+ *                fixed point with one quantum per query (2^-S, S the largest with
+ *                sum_j |m_j| max|W[k_j,:]| 2^S below 2^31); a query whose worst-case
+ *                rounding (F_q / 2 quanta) exceeds 2^-18 of the smallest returned score
+ *                magnitude is rerun, inside the call, with 64-bit cells (quantum near
+ *                2^-62 of that sum). 1: 64-bit cells for every query (FP32 scan only;
+ *                EBR_EINVAL with BF16 / FP8). Results depend on the query alone either way.
  * Results of query q occupy positions [sum_{p<q} K_p, sum_{p<=q} K_p).
  */
 typedef struct {
@@ -170,6 +181,7 @@ typedef struct {
     const int32_t* k;
     ebr_dtype scan_dtype;
     int32_t rescore_factor;
+    int32_t wide64;
 } ebr_batch;
 
 /* Workspace bytes ebr_score_topk / ebr_score_dense need for this batch. Host only. */
@@ -319,10 +331,11 @@ void ebr_graph_destroy(ebr_graph* graph);
  *  rounds       scoring rounds (1 unless a threshold had to be revised)
  *  uncertified  queries of a reduced-precision scan whose recall certificate failed and
  *               that were therefore rerun with the FP32 scan
+ *  imprecise    queries rerun with 64-bit cross-term cells (see ebr_batch.wide64)
  */
 typedef struct {
     double decode_ms, sample_ms, score_ms, finalize_ms, host_ms, score_first_ms, rescore_ms;
-    int32_t rounds, uncertified;
+    int32_t rounds, uncertified, imprecise;
 } ebr_timings;
 
 ebr_status ebr_set_timing(int enable);

@@ -68,7 +68,7 @@ class Timings(ctypes.Structure):
                 ("score_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double),
                 ("host_ms", ctypes.c_double), ("score_first_ms", ctypes.c_double),
                 ("rescore_ms", ctypes.c_double), ("rounds", ctypes.c_int32),
-                ("uncertified", ctypes.c_int32)]
+                ("uncertified", ctypes.c_int32), ("imprecise", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -88,7 +88,8 @@ class Batch(ctypes.Structure):
     _fields_ = [("n_queries", ctypes.c_int32), ("user_emb", ctypes.c_void_p),
                 ("feat_offsets", ctypes.c_void_p), ("feat_keys", ctypes.c_void_p),
                 ("feat_mult", ctypes.c_void_p), ("k", ctypes.c_void_p),
-                ("scan_dtype", ctypes.c_int), ("rescore_factor", ctypes.c_int32)]
+                ("scan_dtype", ctypes.c_int), ("rescore_factor", ctypes.c_int32),
+                ("wide64", ctypes.c_int32)]
 
 
 class LaunchShape(ctypes.Structure):
@@ -366,7 +367,8 @@ class Index:
 
     # -------------------------------------------------------------------------- batches
 
-    def _batch(self, user_emb, feat_offsets, feat_keys, feat_mult, k, scan_dtype, rescore):
+    def _batch(self, user_emb, feat_offsets, feat_keys, feat_mult, k, scan_dtype, rescore,
+               wide64=False):
         import torch
         if not (isinstance(user_emb, torch.Tensor) and user_emb.is_cuda):
             raise TypeError("user_emb must be a CUDA (HIP) tensor")
@@ -385,7 +387,8 @@ class Index:
         keep = (user_emb, offs, keys, mult, kq)
         b = Batch(B, user_emb.data_ptr(), _ptr(offs), _ptr(keys) if len(keys) else None,
                   _ptr(mult) if mult is not None and len(mult) else None,
-                  _ptr(kq) if kq is not None and len(kq) else None, scan_dtype, rescore)
+                  _ptr(kq) if kq is not None and len(kq) else None, scan_dtype, rescore,
+                  1 if wide64 else 0)
         return b, keep
 
     def workspace(self, nbytes: int):
@@ -396,9 +399,9 @@ class Index:
         return self._ws
 
     def workspace_size(self, user_emb, feat_offsets, feat_keys, k, feat_mult=None,
-                       scan_dtype: int = F32, rescore_factor: int = 4) -> int:
+                       scan_dtype: int = F32, rescore_factor: int = 4, wide64: bool = False) -> int:
         b, keep = self._batch(user_emb, feat_offsets, feat_keys, feat_mult, k, scan_dtype,
-                              rescore_factor)
+                              rescore_factor, wide64)
         n = ctypes.c_size_t()
         _check(load().ebr_workspace_size(self._h, ctypes.byref(b), ctypes.byref(n)),
                "ebr_workspace_size")
@@ -406,13 +409,14 @@ class Index:
 
     def score_topk(self, user_emb, feat_offsets, feat_keys, k, feat_mult=None,
                    scan_dtype: int = F32, rescore_factor: int = 4, out=None, stream=None,
-                   graph: Optional["Graph"] = None):
+                   graph: Optional["Graph"] = None, wide64: bool = False):
         """Top-K per query. Returns (ids int32 tensor [sum K], scores float32 tensor [sum K],
         offsets np.int64 [B + 1]); ids are uint32 values stored in int32 (N < 2^31 here).
-        With a Graph handle the batch's device work runs as one captured HIP graph."""
+        With a Graph handle the batch's device work runs as one captured HIP graph; wide64
+        asks for 64-bit cross-term cells for every query (FP32 scan)."""
         import torch
         b, keep = self._batch(user_emb, feat_offsets, feat_keys, feat_mult, k, scan_dtype,
-                              rescore_factor)
+                              rescore_factor, wide64)
         kq = keep[4]
         offs = np.zeros(len(kq) + 1, dtype=np.int64)
         np.cumsum(kq, out=offs[1:])
@@ -484,15 +488,17 @@ class Index:
         return sh.as_dict()
 
     def score_dense(self, user_emb, feat_offsets, feat_keys, feat_mult=None, scan_dtype: int = F32,
-                    stream=None):
-        """Full deep and wide terms [B, N] (FP32 values) as the scan of that dtype computes them."""
+                    stream=None, wide64: bool = False):
+        """Full deep and wide terms [B, N] (FP32 values) as the scan of that dtype computes them
+        (wide64: with 64-bit cross-term cells)."""
         import torch
-        b, keep = self._batch(user_emb, feat_offsets, feat_keys, feat_mult, None, scan_dtype, 0)
+        b, keep = self._batch(user_emb, feat_offsets, feat_keys, feat_mult, None, scan_dtype, 0,
+                              wide64)
         n = ctypes.c_size_t()
         # the dense hook needs no selection buffers; size it through the top-K query with K = 0
         kz = np.zeros(max(1, b.n_queries), np.int32)
         b2 = Batch(b.n_queries, b.user_emb, b.feat_offsets, b.feat_keys, b.feat_mult,
-                   kz.ctypes.data, scan_dtype, 0)
+                   kz.ctypes.data, scan_dtype, 0, b.wide64)
         _check(load().ebr_workspace_size(self._h, ctypes.byref(b2), ctypes.byref(n)),
                "ebr_workspace_size")
         ws = self.workspace(n.value)

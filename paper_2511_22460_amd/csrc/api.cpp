@@ -499,6 +499,7 @@ namespace ebr {
 
 struct Plan {
     int dtype = 0;        // scan copy: 0 FP32, 1 BF16, 2 FP8
+    bool w64 = false;     // 64-bit cross-term cells (FP32 scan, 128-query groups)
     int factor = 1;       // approximate scans: candidates rescored per result
     int B = 0, gq = 256, n_qg = 0, nu = 0;
     std::vector<int32_t> kcnt;  // per query: K (FP32 scan) or K' = min(N, factor K)
@@ -510,7 +511,9 @@ struct Plan {
     std::vector<uint32_t> uk_chunk_begin, uk_chunk_prefix, users_off, users;
     std::vector<int32_t> uk_wshift;
     std::vector<double> qinv;
-    std::vector<int32_t> kq, jq;
+    std::vector<float> werr;    // per query: F_q / 2 quanta, the cross term's rounding bound
+    std::vector<int32_t> kq, jq;  // kq: K of the selection path (0 for full-sort queries)
+    std::vector<int32_t> big;     // queries answered by a full sort (K beyond the LDS sort)
     std::vector<int64_t> out_off;
     std::vector<uint32_t> sample_tiles;
     int64_t n_sample_valid = 0;
@@ -522,9 +525,11 @@ struct Plan {
     size_t o_kc = 0, o_aq = 0, off_ctl = 0, off_cwide = 0, off_rid = 0, off_rwide = 0, off_rst = 0, off_eps = 0,
            off_unc = 0, off_fb_users = 0, off_fb_ids = 0, off_fb_scores = 0, fb_limit = 0;
     size_t o_ukb = 0, o_ukp = 0, o_ukw = 0, o_uoff = 0, o_users = 0, o_qi = 0, o_kq = 0, o_jq = 0,
-           o_oo = 0, o_st = 0;
+           o_oo = 0, o_st = 0, o_werr = 0;
     int64_t n_super = 0;
-    size_t off_stcnt = 0, off_stoff = 0, off_stfill = 0, off_stage = 0;
+    size_t off_stcnt = 0, off_stoff = 0, off_stfill = 0, off_stage = 0, off_cmap = 0;
+    size_t off_big_deep = 0, off_big_wide = 0, off_big_keys = 0, off_big_tmp = 0, off_big_hist = 0,
+           off_big_stmp = 0;
     size_t off_toff = 0, off_stmp = 0, off_bucket = 0, off_skeys = 0,
            off_thr = 0, off_status = 0, off_active = 0, off_ccnt = 0, off_unres = 0, off_cand = 0;
     size_t total = 0;
@@ -556,14 +561,17 @@ static PlanScratch& plan_scratch(int64_t n_keys) {
     return ps;
 }
 
-// Sample tiles of the threshold pre-pass: at least n_tiles / 64 tiles and 16 K' ads.
+// Sample tiles of the threshold pre-pass: at least n_tiles / 128 tiles and 16 K' ads.
 static int64_t sample_tile_count(const Index& ix, int kcmax) {
     const int64_t nt = ix.n_tiles;
-    const int64_t ns = std::max<int64_t>((nt + 63) / 64, (16LL * kcmax + kTileAds - 1) / kTileAds);
+    const int64_t ns = std::max<int64_t>((nt + 127) / 128, (16LL * kcmax + kTileAds - 1) / kTileAds);
     return std::min(ns, nt);
 }
 
-// Workspace sections of one batch; depends only on the batch's sizes.
+static size_t layout_total(const Index& ix, const BatchSizes& z, int dtype, bool w64);
+
+// Workspace sections of one batch; depends only on the batch's sizes (and the scan dtype and
+// cell width, which P holds on entry along with the query-group size).
 static void layout(const Index& ix, bool topk, const BatchSizes& z, Plan* P) {
     const int B = z.B;
     const int nu = z.nu;
@@ -583,6 +591,7 @@ static void layout(const Index& ix, bool topk, const BatchSizes& z, Plan* P) {
     P->o_jq = put(4 * (size_t)B);
     P->o_kc = put(4 * (size_t)B);
     P->o_aq = put(8 * (size_t)B);
+    P->o_werr = put(4 * (size_t)B);
     P->o_oo = put(8 * (size_t)(B + 1));
     P->o_st = put(4 * (size_t)z.n_sample);
     P->plan_bytes = off - P->off_plan;
@@ -592,6 +601,8 @@ static void layout(const Index& ix, bool topk, const BatchSizes& z, Plan* P) {
     P->off_stfill = put(4 * (size_t)(P->n_super + 1));
     P->off_stmp = put(4 * (size_t)scan_tmp_words(P->n_super + 1));
     P->off_stage = put(8 * (size_t)P->bucket_n);
+    // chunks of the batch: sum over keys of ceil(L / 64) <= postings / 64 + keys
+    P->off_cmap = put(8 * ((size_t)P->bucket_n / kChunk + (size_t)nu + 1));
     P->off_toff = put(4 * (size_t)(ix.n_tiles + 1));
     P->off_bucket = put(8 * (size_t)P->bucket_n);
     if (topk) {
@@ -604,20 +615,48 @@ static void layout(const Index& ix, bool topk, const BatchSizes& z, Plan* P) {
         P->off_ctl = put(sizeof(Control));
         P->off_cand = put(8 * (size_t)B * kCandCap);
         if (P->dtype != EBR_F32) {
-            // everything below the fallback region is enough for an FP32 run of any subset
-            P->fb_limit = off;
             P->off_cwide = put(4 * (size_t)B * kCandCap);
             P->off_rid = put(4 * (size_t)B * std::max(1, z.kcmax));
             P->off_rwide = put(4 * (size_t)B * std::max(1, z.kcmax));
             P->off_rst = put(4 * (size_t)B);
             P->off_eps = put(4 * (size_t)B);
             P->off_unc = put(16);
+        }
+        if (!P->w64) {
+            // rerun region: after the batch, a subset of its queries runs again in the bytes
+            // below fb_limit, on the FP32 scan (failed recall certificates) or with 64-bit
+            // cells (imprecise cross terms); the subset's users and results sit above it
+            size_t sub = layout_total(ix, z, EBR_F32, true);
+            if (P->dtype != EBR_F32) sub = std::max(sub, layout_total(ix, z, EBR_F32, false));
+            off = align256(std::max(off, sub));
+            P->fb_limit = off;
             P->off_fb_users = put(4 * (size_t)B * ix.dim);
             P->off_fb_ids = put(4 * (size_t)std::max<int64_t>(1, z.n_out));
             P->off_fb_scores = put(4 * (size_t)std::max<int64_t>(1, z.n_out));
         }
+        if (z.big_n > 0) {
+            // full sort of one query's scores (queries whose K exceeds the LDS sort); its dense
+            // pass runs in the bytes below fb_limit (or the batch's own, 64-bit cells)
+            const size_t n = (size_t)z.big_n, nb = (size_t)sort_blocks(z.big_n);
+            P->off_big_deep = put(4 * n);
+            P->off_big_wide = put(4 * n);
+            P->off_big_keys = put(8 * n);
+            P->off_big_tmp = put(8 * n);
+            P->off_big_hist = put(4 * (256 * nb + 1));
+            P->off_big_stmp = put(4 * (size_t)scan_tmp_words((int64_t)(256 * nb)));
+        }
     }
     P->total = off;
+}
+
+// Total workspace of a top-K batch of sizes z on scan dtype `dtype` with 32- or 64-bit cells.
+static size_t layout_total(const Index& ix, const BatchSizes& z, int dtype, bool w64) {
+    Plan Q;
+    Q.dtype = dtype;
+    Q.w64 = w64;
+    Q.gq = score_group_queries(ix.dim, w64);
+    layout(ix, true, z, &Q);
+    return Q.total;
 }
 
 static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Plan* P) {
@@ -634,9 +673,12 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
                   P->dtype == EBR_BF16 ? "BF16" : "FP8");
         return EBR_EUNSUPPORTED;
     }
+    if (bt->wide64 != 0 && bt->wide64 != 1) { set_error("wide64 must be 0 or 1"); return EBR_EINVAL; }
+    P->w64 = bt->wide64 == 1;
+    if (P->w64 && P->dtype != EBR_F32) { set_error("64-bit cross-term cells need the FP32 scan"); return EBR_EINVAL; }
     P->factor = P->dtype == EBR_F32 ? 1 : (bt->rescore_factor > 0 ? bt->rescore_factor : 4);
     P->B = B;
-    P->gq = score_group_queries(ix.dim);
+    P->gq = score_group_queries(ix.dim, P->w64);
     P->n_qg = (B + P->gq - 1) / P->gq;
     P->n_tiles = ix.n_tiles;
     if (B > 0 && (!bt->user_emb || !bt->feat_offsets || (topk && !bt->k))) { set_error("NULL batch array"); return EBR_EINVAL; }
@@ -665,10 +707,15 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     }
     P->kq.assign(B, 0);
     P->kmax = 0;
+    P->big.clear();
+    std::vector<int64_t> ktrue(B, 0);
     if (topk) {
-        const int64_t kcap = std::min<int64_t>(ix.n_ads, kMaxK);
         for (int q = 0; q < B; ++q) {
-            if (bt->k[q] < 0 || bt->k[q] > kcap) { set_error("query %d: K = %d outside [0, %lld]", q, bt->k[q], (long long)kcap); return EBR_EINVAL; }
+            if (bt->k[q] < 0 || (int64_t)bt->k[q] > ix.n_ads) { set_error("query %d: K = %d outside [0, %lld]", q, bt->k[q], (long long)ix.n_ads); return EBR_EINVAL; }
+            ktrue[q] = bt->k[q];
+            // candidates beyond the LDS sort of the selection path: answered by a full sort
+            const int64_t kc = std::min<int64_t>(ix.n_ads, (int64_t)P->factor * bt->k[q]);
+            if (kc > kMaxK) { P->big.push_back(q); continue; }
             P->kq[q] = bt->k[q];
             P->kmax = std::max(P->kmax, bt->k[q]);
         }
@@ -677,7 +724,6 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     P->kcmax = 0;
     for (int q = 0; q < B; ++q) {
         const int64_t kc = P->kq[q] == 0 ? 0 : std::min<int64_t>(ix.n_ads, (int64_t)P->factor * P->kq[q]);
-        if (kc > kMaxK) { set_error("query %d: rescore_factor x K = %lld exceeds %d", q, (long long)kc, kMaxK); return EBR_EINVAL; }
         P->kcnt[q] = (int32_t)kc;
         P->kcmax = std::max(P->kcmax, (int)kc);
     }
@@ -721,13 +767,18 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j)
             P->users_off[(size_t)slot[j] * nqg + q / P->gq + 1]++;
     for (size_t i = 1; i < P->users_off.size(); ++i) P->users_off[i] += P->users_off[i - 1];
-    // per-query fixed-point scale of the cross term: sum_j |m_j| max|W[k_j,:]| * 2^S < 2^30, so
-    // that every (query, ad) sum of rounded terms fits an int32
+    // per-query fixed-point scale of the cross term: the largest S with
+    // sum_j |m_j| max|W[k_j,:]| 2^S (1 + 2^-23) + F_q + 1 below 2^31 (2^63 for 64-bit cells), so
+    // that every (query, ad) sum of rounded terms fits the cell; a sum's rounding error is at
+    // most F_q / 2 quanta of 2^-S
     std::vector<int> Sq(B, 0);
     P->qinv.assign(B, 1.0);
     P->aq.assign(B, 0.0);
+    P->werr.assign(B, 0.0f);
+    const int cell_bits = P->w64 ? 63 : 31;
     for (int q = 0; q < B; ++q) {
         double A = 0.0;
+        const int64_t F = bt->feat_offsets[q + 1] - bt->feat_offsets[q];
         for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
             const double m = bt->feat_mult ? (double)bt->feat_mult[j] : 1.0;
             A += std::fabs(m) * (double)ix.key_maxw[bt->feat_keys[j]];
@@ -737,10 +788,13 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         if (A > 0.0 && std::isfinite(A)) {
             int e;
             std::frexp(A, &e);  // A < 2^e
-            S = std::max(-100, std::min(100, 30 - e));
+            S = cell_bits - e;
+            if (std::ldexp(A, S) * (1.0 + 0x1p-23) + (double)F + 1.0 >= std::ldexp(1.0, cell_bits)) --S;
+            S = std::max(-126, std::min(126, S));
         }
         Sq[q] = S;
         P->qinv[q] = std::ldexp(1.0, -S);
+        P->werr[q] = (float)std::ldexp((double)F, -S - 1);
     }
     // users: (query within its group, bits of m' = m * 2^(S_q - Sw_k) in FP32), in query order;
     // |m'| <= 2^(e(max|W_k|) - e(A_q) + 1) |m| max|W_k| / max|W_k| stays far from overflow
@@ -762,8 +816,8 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     }
     // output offsets
     P->out_off.assign(B + 1, 0);
-    for (int q = 0; q < B; ++q) P->out_off[q + 1] = P->out_off[q] + P->kq[q];
-    // sample tiles for the threshold: spread evenly, at least n_tiles / 64 and 16 * K ads
+    for (int q = 0; q < B; ++q) P->out_off[q + 1] = P->out_off[q] + ktrue[q];
+    // sample tiles for the threshold: spread evenly, at least n_tiles / 128 and 16 * K ads
     P->jq.assign(B, 0);
     P->sample_tiles.clear();
     if (topk && P->kmax > 0) {
@@ -783,8 +837,9 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
             if (K == 0) continue;
             if (ns == nt) { P->jq[q] = K; continue; }
             // x = K' f sample ads are expected among the K' best; j sits 5 standard deviations
-            // (Poisson) above, so too few survivors (j - x > 5 sqrt(x)) and more than the
-            // 16384-slot buffer (for K' <= 8192 and f >= 1/64) are both rarer than 1e-5
+            // (Poisson) above, so too few survivors (j - x > 5 sqrt(x)) is rarer than 1e-5; the
+            // survivors, about j / f (at most ~12.5 K for K' <= 8192 with either sampling
+            // rule), stay more than 4 standard deviations below the 16384-slot buffer
             const double x = K * f;
             int64_t j = (int64_t)std::ceil(x + 5.0 * std::sqrt(x) + 4.0);
             P->jq[q] = (int32_t)std::min<int64_t>(j, valid);
@@ -798,6 +853,7 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     z.kcmax = P->kcmax;
     z.n_out = P->out_off[B];
     z.n_sample = (int64_t)P->sample_tiles.size();
+    z.big_n = P->big.empty() ? 0 : ix.n_ads;
     layout(ix, topk, z, P);
     return EBR_OK;
 }
@@ -815,6 +871,7 @@ static std::vector<char> pack_plan(const Plan& P) {
     cp(P.o_jq, P.jq.data(), 4 * P.jq.size());
     cp(P.o_kc, P.kcnt.data(), 4 * P.kcnt.size());
     cp(P.o_aq, P.aq.data(), 8 * P.aq.size());
+    cp(P.o_werr, P.werr.data(), 4 * P.werr.size());
     cp(P.o_oo, P.out_off.data(), 8 * P.out_off.size());
     cp(P.o_st, P.sample_tiles.data(), 4 * P.sample_tiles.size());
     return blob;
@@ -871,10 +928,12 @@ static ebr_status run_decode(const Index& ix, const Plan& P, char* ws, hipStream
     d.st_off = stoff;
     d.st_fill = stfill;
     d.stage = (uint32_t*)(ws + P.off_stage);
+    d.chunk_map = (uint2*)(ws + P.off_cmap);
     // one query group: bucket entries carry their key's users range directly
     d.users_off = P.packed ? (const uint32_t*)(ws + P.o_uoff) : nullptr;
     d.tile_off = (uint32_t*)(ws + P.off_toff);
     d.bucket = (uint32_t*)(ws + P.off_bucket);
+    LAUNCH(launch_chunk_map(d, st));
     LAUNCH(launch_decode(d, 0, st));
     LAUNCH(launch_excl_scan_u32(stcnt, stoff, P.n_super, (uint32_t*)(ws + P.off_stmp), st));
     LAUNCH(launch_decode(d, 1, st));
@@ -892,6 +951,7 @@ static ScoreArgs score_args(const Index& ix, const Plan& P, const ebr_batch* bt,
     s.n_queries = P.B;
     s.n_qgroups = P.n_qg;
     s.packed = P.packed ? 1 : 0;
+    s.wide64 = P.w64 ? 1 : 0;
     s.tile_off = (const uint32_t*)(ws + P.off_toff);
     s.bucket = (const uint32_t*)(ws + P.off_bucket);
     s.users_off = (const uint32_t*)(ws + P.o_uoff);
@@ -915,6 +975,10 @@ static ebr_status check_users(const ebr_batch* bt, int B, int dim, hipStream_t s
         if (!std::isfinite(u[i])) { set_error("query %zu: non-finite user embedding", i / dim); return EBR_EINVAL; }
     return EBR_OK;
 }
+
+// Key of the launch-shape table for FP32 batches with 64-bit cross-term cells (the scan dtypes
+// are 0..2).
+constexpr int kShapeKeyWide64 = 3;
 
 // Launch shape of a batch: the override, else the one recorded for (dtype, query groups),
 // else zeros (the defaults).
@@ -1004,296 +1068,360 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
     if ((uintptr_t)ws & 255) { set_error("workspace must be 256-byte aligned"); return EBR_EINVAL; }
     const int64_t n_out = P.out_off[P.B];
     if (n_out > 0 && (!out_ids || !out_scores)) { set_error("NULL output"); return EBR_EINVAL; }
-    if (P.B == 0 || P.kmax == 0) return EBR_OK;
-    const bool approx = P.dtype != EBR_F32;
-    const int64_t ns = (int64_t)P.sample_tiles.size();
-    const ebr_launch_shape sh =
-        effective_shape(ix, shape_for(ix, P.dtype, P.n_qg, opt.shape), ns, P.n_qg);
-    if (sh.score_ranges < 1 || sh.sample_ranges < 1 || sh.decode_chunks < 1 || sh.decode_chunks > 64) {
-        set_error("launch shape out of range");
-        return EBR_EINVAL;
-    }
-    std::vector<char> blob = pack_plan(P);
-    const char* src = blob.data();
-    ebr_graph* g = opt.graph;
-    hipStream_t ls = s;  // the stream the device sequence is enqueued (or captured) on
-    if (g) {
-        if (g->pinned_cap < blob.size()) {
-            if (g->pinned) (void)hipHostFree(g->pinned);
-            g->pinned = nullptr;
-            g->pinned_cap = 0;
-            const size_t cap = std::max<size_t>(blob.size() + blob.size() / 4, 1 << 20);
-            HIP_TRY(hipHostMalloc((void**)&g->pinned, cap, hipHostMallocDefault));
-            g->pinned_cap = cap;
+    if (P.B == 0) return EBR_OK;
+    // the selection path: every query whose candidates fit the LDS sort
+    auto selection = [&]() -> ebr_status {
+        const bool approx = P.dtype != EBR_F32;
+        const int64_t ns = (int64_t)P.sample_tiles.size();
+        const ebr_launch_shape sh =
+            effective_shape(ix, shape_for(ix, P.w64 ? kShapeKeyWide64 : P.dtype, P.n_qg, opt.shape), ns, P.n_qg);
+        if (sh.score_ranges < 1 || sh.sample_ranges < 1 || sh.decode_chunks < 1 || sh.decode_chunks > 64) {
+            set_error("launch shape out of range");
+            return EBR_EINVAL;
         }
-        std::memcpy(g->pinned, blob.data(), blob.size());
-        // the plan goes up on the caller's stream ahead of the graph, which holds kernels only
-        HIP_TRY(hipMemcpyAsync(ws + P.off_plan, g->pinned, blob.size(), hipMemcpyHostToDevice, s));
-        src = nullptr;
-        ls = g->cs;
-    }
-    const double host_ms = ms_since(t_host);
-    PhaseClock clk(ls, !g && (opt.force_timing || g_timing.load() != 0));
-
-    const int B = P.B;
-    uint32_t* thr = (uint32_t*)(ws + P.off_thr);
-    int32_t* status = (int32_t*)(ws + P.off_status);
-    uint32_t* active = (uint32_t*)(ws + P.off_active);
-    uint32_t* ccnt = (uint32_t*)(ws + P.off_ccnt);
-    uint32_t* unres = (uint32_t*)(ws + P.off_unres);
-    uint32_t* unc = (uint32_t*)(ws + P.off_unc);
-    Control* ctl = (Control*)(ws + P.off_ctl);
-    unsigned long long* cand = (unsigned long long*)(ws + P.off_cand);
-
-    ScoreArgs sa = score_args(ix, P, batch, ws);
-    sa.ctl = ctl;
-    sa.n_work = (int32_t)ns;
-    sa.tile_list = (const uint32_t*)(ws + P.o_st);
-    sa.sample_keys = (uint32_t*)(ws + P.off_skeys);
-    sa.sample_ld = ns * kTileAds;
-    SelectArgs se{};
-    se.keys = sa.sample_keys;
-    se.ld = sa.sample_ld;
-    se.n_cols = sa.sample_ld;
-    se.jq = (const int32_t*)(ws + P.o_jq);
-    se.kq = (const int32_t*)(ws + P.o_kq);
-    se.kcnt = (const int32_t*)(ws + P.o_kc);
-    se.n_valid = P.n_sample_valid;
-    se.status = status;
-    se.only_status = -1;
-    // Test hook: EBR_FORCE_SELECT_ROUND = 1 or 2 makes the first threshold follow the rule of
-    // that revision round (1: the sample's K'-th key; 2: no threshold, every ad a candidate),
-    // so that the rounds' thresholds are exercised on ordinary inputs.
-    if (const char* fr = std::getenv("EBR_FORCE_SELECT_ROUND")) {
-        if (fr[0] == '1' && fr[1] == '\0') se.round = 1;
-        if (fr[0] == '2' && fr[1] == '\0') se.round = 2;
-    }
-    se.thresh = thr;
-    se.ctl = ctl;
-    ScoreArgs ca = score_args(ix, P, batch, ws);
-    ca.ctl = ctl;
-    ca.thresh = thr;
-    ca.active = active;
-    ca.cand = cand;
-    ca.cand_wide = approx ? (float*)(ws + P.off_cwide) : nullptr;
-    ca.cand_cnt = ccnt;
-    ca.cap = kCandCap;
-    FinalArgs fa{};
-    fa.ctl = ctl;
-    fa.active = active;
-    fa.kq = (const int32_t*)(ws + P.o_kq);
-    fa.kcnt = (const int32_t*)(ws + P.o_kc);
-    fa.cand_cnt = ccnt;
-    fa.cap = kCandCap;
-    fa.cand = cand;
-    fa.cand_wide = ca.cand_wide;
-    fa.status = status;
-    fa.thresh = thr;
-    fa.prep = approx ? 1 : 0;
-    fa.out_off = (const int64_t*)(ws + P.o_oo);
-    fa.out_ids = out_ids;
-    fa.out_scores = out_scores;
-    if (approx) {
-        fa.r_id = (uint32_t*)(ws + P.off_rid);
-        fa.r_wide = (float*)(ws + P.off_rwide);
-        fa.r_stilde = (float*)(ws + P.off_rst);
-        fa.r_ld = std::max(1, P.kcmax);
-    }
-    RescoreArgs ra{};
-    ra.ctl = ctl;
-    ra.emb = ix.emb_f32;
-    ra.user = batch->user_emb;
-    ra.n_ads = ix.n_ads;
-    ra.kq = fa.kq;
-    ra.kcnt = fa.kcnt;
-    ra.status = status;
-    ra.uncertified = unc;
-    ra.r_id = fa.r_id;
-    ra.r_wide = fa.r_wide;
-    ra.r_stilde = fa.r_stilde;
-    ra.eps = (const float*)(ws + P.off_eps);
-    ra.r_ld = fa.r_ld;
-    ra.out_off = fa.out_off;
-    ra.out_ids = out_ids;
-    ra.out_scores = out_scores;
-
-    int e_dec0 = -1, e_dec1 = -1, e_smp1 = -1, e_rs0 = -1, e_rs1 = -1;
-    std::vector<std::array<int, 3>> round_marks;
-    // The device sequence of the batch, enqueued on ls without host synchronisation.
-    auto enqueue = [&]() -> ebr_status {
-        e_dec0 = clk.mark();
-        ebr_status r = run_decode(ix, P, ws, ls, src, blob.size(), sh.decode_chunks);
-        if (r) return r;
-        e_dec1 = clk.mark();
-        // per-query set-up on the device: user rows finite, status / activity, certificate eps
-        LAUNCH(launch_fill_u32((uint32_t*)ctl, 0u, (int64_t)(sizeof(Control) / 4), ls));
-        PrepArgs pa{};
-        pa.user = batch->user_emb;
-        pa.n_queries = B;
-        pa.dim = ix.dim;
-        pa.kq = (const int32_t*)(ws + P.o_kq);
-        pa.aq = (const double*)(ws + P.o_aq);
-        pa.status = status;
-        pa.active = active;
-        pa.eps = approx ? (float*)(ws + P.off_eps) : nullptr;
-        const int cq = P.dtype == EBR_BF16 ? 0 : 1;
-        pa.q_err2 = ix.q_err2[cq];
-        pa.q_norm2 = ix.q_norm2[cq];
-        pa.e_norm2 = ix.e_norm2;
-        pa.ctl = ctl;
-        LAUNCH(launch_prep(pa, ls));
-        // sample pass and per-query threshold (for K' candidates on approximate scans)
-        LAUNCH(launch_score(sa, ix.dim, 1, sh.sample_ranges, ls));
-        LAUNCH(launch_select(se, B, ls));
-        se.round = 0;
-        e_smp1 = clk.mark();
-        // Selection rounds: round r > 0 runs only if round r - 1 left a query unresolved.
-        // Queries short of K' candidates first take the sample's K'-th key (which at least
-        // K' sample ads reach), then no threshold at all; overflowing queries take the
-        // K'-th largest stored key.
-        for (int rr = 0; rr < kMaxRounds; ++rr) {
-            const uint32_t* gate = rr == 0 ? nullptr : &ctl->unres[rr - 1];
-            if (rr > 0) {
-                se.gate = gate;
-                se.round = rr;
-                se.only_status = kStatusNeedLower;
-                LAUNCH(launch_select(se, B, ls));
+        std::vector<char> blob = pack_plan(P);
+        const char* src = blob.data();
+        ebr_graph* g = opt.graph;
+        hipStream_t ls = s;  // the stream the device sequence is enqueued (or captured) on
+        if (g) {
+            if (g->pinned_cap < blob.size()) {
+                if (g->pinned) (void)hipHostFree(g->pinned);
+                g->pinned = nullptr;
+                g->pinned_cap = 0;
+                const size_t cap = std::max<size_t>(blob.size() + blob.size() / 4, 1 << 20);
+                HIP_TRY(hipHostMalloc((void**)&g->pinned, cap, hipHostMallocDefault));
+                g->pinned_cap = cap;
             }
-            LAUNCH(launch_round_reset(ccnt, B, gate, ls));
-            ca.gate = gate;
-            fa.gate = gate;
-            fa.unresolved = &ctl->unres[rr];
-            const int e0 = clk.mark();
-            LAUNCH(launch_score(ca, ix.dim, 0, sh.score_ranges, ls));
-            const int e1 = clk.mark();
-            LAUNCH(launch_finalize(fa, B, ls));
-            const int e2 = clk.mark();
-            round_marks.push_back({e0, e1, e2});
+            std::memcpy(g->pinned, blob.data(), blob.size());
+            // the plan goes up on the caller's stream ahead of the graph, which holds kernels only
+            HIP_TRY(hipMemcpyAsync(ws + P.off_plan, g->pinned, blob.size(), hipMemcpyHostToDevice, s));
+            src = nullptr;
+            ls = g->cs;
         }
+        const double host_ms = ms_since(t_host);
+        PhaseClock clk(ls, !g && (opt.force_timing || g_timing.load() != 0));
+
+        const int B = P.B;
+        uint32_t* thr = (uint32_t*)(ws + P.off_thr);
+        int32_t* status = (int32_t*)(ws + P.off_status);
+        uint32_t* active = (uint32_t*)(ws + P.off_active);
+        uint32_t* ccnt = (uint32_t*)(ws + P.off_ccnt);
+        uint32_t* unres = (uint32_t*)(ws + P.off_unres);
+        uint32_t* unc = (uint32_t*)(ws + P.off_unc);
+        Control* ctl = (Control*)(ws + P.off_ctl);
+        unsigned long long* cand = (unsigned long long*)(ws + P.off_cand);
+
+        ScoreArgs sa = score_args(ix, P, batch, ws);
+        sa.ctl = ctl;
+        sa.n_work = (int32_t)ns;
+        sa.tile_list = (const uint32_t*)(ws + P.o_st);
+        sa.sample_keys = (uint32_t*)(ws + P.off_skeys);
+        sa.sample_ld = ns * kTileAds;
+        SelectArgs se{};
+        se.keys = sa.sample_keys;
+        se.ld = sa.sample_ld;
+        se.n_cols = sa.sample_ld;
+        se.jq = (const int32_t*)(ws + P.o_jq);
+        se.kq = (const int32_t*)(ws + P.o_kq);
+        se.kcnt = (const int32_t*)(ws + P.o_kc);
+        se.n_valid = P.n_sample_valid;
+        se.status = status;
+        se.only_status = -1;
+        // Test hook: EBR_FORCE_SELECT_ROUND = 1 or 2 makes the first threshold follow the rule of
+        // that revision round (1: the sample's K'-th key; 2: no threshold, every ad a candidate),
+        // so that the rounds' thresholds are exercised on ordinary inputs.
+        if (const char* fr = std::getenv("EBR_FORCE_SELECT_ROUND")) {
+            if (fr[0] == '1' && fr[1] == '\0') se.round = 1;
+            if (fr[0] == '2' && fr[1] == '\0') se.round = 2;
+        }
+        se.thresh = thr;
+        se.ctl = ctl;
+        ScoreArgs ca = score_args(ix, P, batch, ws);
+        ca.ctl = ctl;
+        ca.thresh = thr;
+        ca.active = active;
+        ca.cand = cand;
+        ca.cand_wide = approx ? (float*)(ws + P.off_cwide) : nullptr;
+        ca.cand_cnt = ccnt;
+        ca.cap = kCandCap;
+        FinalArgs fa{};
+        fa.ctl = ctl;
+        fa.active = active;
+        fa.kq = (const int32_t*)(ws + P.o_kq);
+        fa.kcnt = (const int32_t*)(ws + P.o_kc);
+        fa.cand_cnt = ccnt;
+        fa.cap = kCandCap;
+        fa.cand = cand;
+        fa.cand_wide = ca.cand_wide;
+        fa.status = status;
+        fa.thresh = thr;
+        fa.prep = approx ? 1 : 0;
+        fa.out_off = (const int64_t*)(ws + P.o_oo);
+        fa.out_ids = out_ids;
+        fa.out_scores = out_scores;
+        fa.werr = P.w64 ? nullptr : (const float*)(ws + P.o_werr);
+        fa.imprecise = &ctl->imprecise;
         if (approx) {
-            // exact FP32 rescore of the K' candidates, top K, recall certificate; skipped
-            // while a query is still unresolved (then it runs after the extra rounds)
-            LAUNCH(launch_fill_u32(unc, 0u, 1, ls));
-            ra.skip = &ctl->unres[kMaxRounds - 1];
-            e_rs0 = clk.mark();
-            LAUNCH(launch_rescore(ra, ix.dim, B, ls));
-            e_rs1 = clk.mark();
+            fa.r_id = (uint32_t*)(ws + P.off_rid);
+            fa.r_wide = (float*)(ws + P.off_rwide);
+            fa.r_stilde = (float*)(ws + P.off_rst);
+            fa.r_ld = std::max(1, P.kcmax);
+        }
+        RescoreArgs ra{};
+        ra.ctl = ctl;
+        ra.emb = ix.emb_f32;
+        ra.user = batch->user_emb;
+        ra.n_ads = ix.n_ads;
+        ra.kq = fa.kq;
+        ra.kcnt = fa.kcnt;
+        ra.status = status;
+        ra.uncertified = unc;
+        ra.r_id = fa.r_id;
+        ra.r_wide = fa.r_wide;
+        ra.r_stilde = fa.r_stilde;
+        ra.eps = (const float*)(ws + P.off_eps);
+        ra.werr = fa.werr;
+        ra.imprecise = fa.imprecise;
+        ra.r_ld = fa.r_ld;
+        ra.out_off = fa.out_off;
+        ra.out_ids = out_ids;
+        ra.out_scores = out_scores;
+
+        int e_dec0 = -1, e_dec1 = -1, e_smp1 = -1, e_rs0 = -1, e_rs1 = -1;
+        std::vector<std::array<int, 3>> round_marks;
+        // The device sequence of the batch, enqueued on ls without host synchronisation.
+        auto enqueue = [&]() -> ebr_status {
+            e_dec0 = clk.mark();
+            ebr_status r = run_decode(ix, P, ws, ls, src, blob.size(), sh.decode_chunks);
+            if (r) return r;
+            e_dec1 = clk.mark();
+            // per-query set-up on the device: user rows finite, status / activity, certificate eps
+            LAUNCH(launch_fill_u32((uint32_t*)ctl, 0u, (int64_t)(sizeof(Control) / 4), ls));
+            PrepArgs pa{};
+            pa.user = batch->user_emb;
+            pa.n_queries = B;
+            pa.dim = ix.dim;
+            pa.kq = (const int32_t*)(ws + P.o_kq);
+            pa.aq = (const double*)(ws + P.o_aq);
+            pa.status = status;
+            pa.active = active;
+            pa.eps = approx ? (float*)(ws + P.off_eps) : nullptr;
+            const int cq = P.dtype == EBR_BF16 ? 0 : 1;
+            pa.q_err2 = ix.q_err2[cq];
+            pa.q_norm2 = ix.q_norm2[cq];
+            pa.e_norm2 = ix.e_norm2;
+            pa.ctl = ctl;
+            LAUNCH(launch_prep(pa, ls));
+            // sample pass and per-query threshold (for K' candidates on approximate scans)
+            LAUNCH(launch_score(sa, ix.dim, 1, sh.sample_ranges, ls));
+            LAUNCH(launch_select(se, B, ls));
+            se.round = 0;
+            e_smp1 = clk.mark();
+            // Selection rounds: round r > 0 runs only if round r - 1 left a query unresolved.
+            // Queries short of K' candidates first take the sample's K'-th key (which at least
+            // K' sample ads reach), then no threshold at all; overflowing queries take the
+            // K'-th largest stored key.
+            for (int rr = 0; rr < kMaxRounds; ++rr) {
+                const uint32_t* gate = rr == 0 ? nullptr : &ctl->unres[rr - 1];
+                if (rr > 0) {
+                    se.gate = gate;
+                    se.round = rr;
+                    se.only_status = kStatusNeedLower;
+                    LAUNCH(launch_select(se, B, ls));
+                }
+                LAUNCH(launch_round_reset(ccnt, B, gate, ls));
+                ca.gate = gate;
+                fa.gate = gate;
+                fa.unresolved = &ctl->unres[rr];
+                const int e0 = clk.mark();
+                LAUNCH(launch_score(ca, ix.dim, 0, sh.score_ranges, ls));
+                const int e1 = clk.mark();
+                LAUNCH(launch_finalize(fa, B, ls));
+                const int e2 = clk.mark();
+                round_marks.push_back({e0, e1, e2});
+            }
+            if (approx) {
+                // exact FP32 rescore of the K' candidates, top K, recall certificate; skipped
+                // while a query is still unresolved (then it runs after the extra rounds)
+                LAUNCH(launch_fill_u32(unc, 0u, 1, ls));
+                ra.skip = &ctl->unres[kMaxRounds - 1];
+                e_rs0 = clk.mark();
+                LAUNCH(launch_rescore(ra, ix.dim, B, ls));
+                e_rs1 = clk.mark();
+            }
+            return EBR_OK;
+        };
+
+        if (g) {
+            HIP_TRY(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
+            const ebr_status r = enqueue();
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(ls, &graph);
+            if (r || ec != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                if (!r) set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+                return r ? r : EBR_EDEVICE;
+            }
+            st = graph_launch(g, graph, s);
+            if (st) return st;
+        } else {
+            st = enqueue();
+            if (st) return st;
+        }
+
+        Control hc{};
+        uint32_t nunc = 0;
+        HIP_TRY(hipMemcpyAsync(&hc, ctl, sizeof(Control), hipMemcpyDeviceToHost, s));
+        if (approx) HIP_TRY(hipMemcpyAsync(&nunc, unc, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (hc.error & 1u) { set_error("non-finite user embedding in the batch"); return EBR_EINVAL; }
+        int rounds_run = 1;
+        for (int r = 0; r + 1 < kMaxRounds; ++r) rounds_run += hc.unres[r] > 0 ? 1 : 0;
+        // rare: still unresolved after the enqueued rounds; continue round by round
+        const bool extra = hc.unres[kMaxRounds - 1] > 0;
+        for (int r = kMaxRounds; hc.unres[kMaxRounds - 1] > 0; ++r) {
+            if (r >= 64) { set_error("top-K selection did not converge"); return EBR_EDEVICE; }
+            se.gate = nullptr;
+            se.round = 2;
+            se.only_status = kStatusNeedLower;
+            LAUNCH(launch_select(se, B, s));
+            LAUNCH(launch_round_reset(ccnt, B, nullptr, s));
+            ca.gate = nullptr;
+            fa.gate = nullptr;
+            LAUNCH(launch_fill_u32(unres, 0u, 1, s));
+            fa.unresolved = unres;
+            LAUNCH(launch_score(ca, ix.dim, 0, sh.score_ranges, s));
+            LAUNCH(launch_finalize(fa, B, s));
+            uint32_t left = 0;
+            HIP_TRY(hipMemcpyAsync(&left, unres, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            ++rounds_run;
+            hc.unres[kMaxRounds - 1] = left;
+        }
+        if (approx && extra) {
+            ra.skip = nullptr;
+            LAUNCH(launch_fill_u32(unc, 0u, 1, s));
+            LAUNCH(launch_rescore(ra, ix.dim, B, s));
+            HIP_TRY(hipMemcpyAsync(&nunc, unc, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        // cross-term precision checks of the finalize / rescore kernels run after the rounds
+        uint32_t nimp = hc.imprecise;
+        if (extra) {
+            HIP_TRY(hipMemcpyAsync(&nimp, &ctl->imprecise, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        const int n_unc = (int)nunc, n_imp = (int)nimp;
+        if (tm) {
+            tm->host_ms = host_ms;
+            tm->decode_ms = clk.ms(e_dec0, e_dec1);
+            tm->sample_ms = clk.ms(e_dec1, e_smp1);
+            for (const auto& r : round_marks) {
+                tm->score_ms += clk.ms(r[0], r[1]);
+                tm->finalize_ms += clk.ms(r[1], r[2]);
+            }
+            tm->score_first_ms = round_marks.empty() ? 0.0 : clk.ms(round_marks[0][0], round_marks[0][1]);
+            tm->rescore_ms = clk.ms(e_rs0, e_rs1);
+            tm->rounds = rounds_run;
+            tm->uncertified = n_unc;
+            tm->imprecise = n_imp;
+        }
+        if (n_unc > 0 || n_imp > 0) {
+            // rare: queries whose recall certificate failed run again on the FP32 scan, queries
+            // whose 32-bit cross term was too coarse with 64-bit cells; each subset as a batch of
+            // its own in the bytes below fb_limit, results copied into place
+            std::vector<int32_t> sv(B);
+            HIP_TRY(hipMemcpyAsync(sv.data(), status, 4 * (size_t)B, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            float* fu = (float*)(ws + P.off_fb_users);
+            uint32_t* fids = (uint32_t*)(ws + P.off_fb_ids);
+            float* fsc = (float*)(ws + P.off_fb_scores);
+            auto rerun = [&](int want, bool w64) -> ebr_status {
+                std::vector<int> fq;
+                for (int q = 0; q < B; ++q)
+                    if (sv[q] == want) fq.push_back(q);
+                const int nb = (int)fq.size();
+                if (nb == 0) return EBR_OK;
+                std::vector<int64_t> foff(nb + 1, 0);
+                std::vector<int32_t> fkeys, fk(nb);
+                std::vector<float> fmult;
+                for (int i = 0; i < nb; ++i) {
+                    const int q = fq[i];
+                    HIP_TRY(hipMemcpyAsync(fu + (size_t)i * ix.dim, batch->user_emb + (size_t)q * ix.dim,
+                                           4 * (size_t)ix.dim, hipMemcpyDeviceToDevice, s));
+                    for (int64_t j = batch->feat_offsets[q]; j < batch->feat_offsets[q + 1]; ++j) {
+                        fkeys.push_back(batch->feat_keys[j]);
+                        if (batch->feat_mult) fmult.push_back(batch->feat_mult[j]);
+                    }
+                    foff[i + 1] = (int64_t)fkeys.size();
+                    fk[i] = P.kq[q];
+                }
+                ebr_batch fb{};
+                fb.n_queries = nb;
+                fb.user_emb = fu;
+                fb.feat_offsets = foff.data();
+                fb.feat_keys = fkeys.data();
+                fb.feat_mult = batch->feat_mult ? fmult.data() : nullptr;
+                fb.k = fk.data();
+                fb.scan_dtype = EBR_F32;
+                fb.rescore_factor = 0;
+                fb.wide64 = w64 ? 1 : 0;
+                ebr_status r = topk_impl(ix, &fb, ws, P.fb_limit, fids, fsc, s, nullptr);
+                if (r) return r;
+                int64_t pos = 0;
+                for (int i = 0; i < nb; ++i) {
+                    const int q = fq[i];
+                    const size_t n = (size_t)P.kq[q];
+                    HIP_TRY(hipMemcpyAsync(out_ids + P.out_off[q], fids + pos, 4 * n, hipMemcpyDeviceToDevice, s));
+                    HIP_TRY(hipMemcpyAsync(out_scores + P.out_off[q], fsc + pos, 4 * n, hipMemcpyDeviceToDevice, s));
+                    pos += (int64_t)n;
+                }
+                HIP_TRY(hipStreamSynchronize(s));
+                return EBR_OK;
+            };
+            st = rerun(kStatusUncertified, false);
+            if (st) return st;
+            st = rerun(kStatusImprecise, true);
+            if (st) return st;
         }
         return EBR_OK;
     };
-
-    if (g) {
-        HIP_TRY(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal));
-        const ebr_status r = enqueue();
-        hipGraph_t graph = nullptr;
-        const hipError_t ec = hipStreamEndCapture(ls, &graph);
-        if (r || ec != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            if (!r) set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ec));
-            return r ? r : EBR_EDEVICE;
-        }
-        st = graph_launch(g, graph, s);
-        if (st) return st;
-    } else {
-        st = enqueue();
+    if (P.kmax > 0) {
+        st = selection();
         if (st) return st;
     }
-
-    Control hc{};
-    uint32_t nunc = 0;
-    HIP_TRY(hipMemcpyAsync(&hc, ctl, sizeof(Control), hipMemcpyDeviceToHost, s));
-    if (approx) HIP_TRY(hipMemcpyAsync(&nunc, unc, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (hc.error & 1u) { set_error("non-finite user embedding in the batch"); return EBR_EINVAL; }
-    int rounds_run = 1;
-    for (int r = 0; r + 1 < kMaxRounds; ++r) rounds_run += hc.unres[r] > 0 ? 1 : 0;
-    // rare: still unresolved after the enqueued rounds; continue round by round
-    const bool extra = hc.unres[kMaxRounds - 1] > 0;
-    for (int r = kMaxRounds; hc.unres[kMaxRounds - 1] > 0; ++r) {
-        if (r >= 64) { set_error("top-K selection did not converge"); return EBR_EDEVICE; }
-        se.gate = nullptr;
-        se.round = 2;
-        se.only_status = kStatusNeedLower;
-        LAUNCH(launch_select(se, B, s));
-        LAUNCH(launch_round_reset(ccnt, B, nullptr, s));
-        ca.gate = nullptr;
-        fa.gate = nullptr;
-        LAUNCH(launch_fill_u32(unres, 0u, 1, s));
-        fa.unresolved = unres;
-        LAUNCH(launch_score(ca, ix.dim, 0, sh.score_ranges, s));
-        LAUNCH(launch_finalize(fa, B, s));
-        uint32_t left = 0;
-        HIP_TRY(hipMemcpyAsync(&left, unres, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        ++rounds_run;
-        hc.unres[kMaxRounds - 1] = left;
-    }
-    if (approx && extra) {
-        ra.skip = nullptr;
-        LAUNCH(launch_fill_u32(unc, 0u, 1, s));
-        LAUNCH(launch_rescore(ra, ix.dim, B, s));
-        HIP_TRY(hipMemcpyAsync(&nunc, unc, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-    }
-    const int n_unc = (int)nunc;
-    if (tm) {
-        tm->host_ms = host_ms;
-        tm->decode_ms = clk.ms(e_dec0, e_dec1);
-        tm->sample_ms = clk.ms(e_dec1, e_smp1);
-        for (const auto& r : round_marks) {
-            tm->score_ms += clk.ms(r[0], r[1]);
-            tm->finalize_ms += clk.ms(r[1], r[2]);
-        }
-        tm->score_first_ms = round_marks.empty() ? 0.0 : clk.ms(round_marks[0][0], round_marks[0][1]);
-        tm->rescore_ms = clk.ms(e_rs0, e_rs1);
-        tm->rounds = rounds_run;
-        tm->uncertified = n_unc;
-    }
-    if (n_unc > 0) {
-        // queries whose certificate failed: exact FP32 scan of just those queries
-        std::vector<int32_t> sv(B);
-        HIP_TRY(hipMemcpyAsync(sv.data(), status, 4 * (size_t)B, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        std::vector<int> fq;
-        for (int q = 0; q < B; ++q)
-            if (sv[q] == kStatusUncertified) fq.push_back(q);
-        const int nb = (int)fq.size();
-        float* fu = (float*)(ws + P.off_fb_users);
-        uint32_t* fids = (uint32_t*)(ws + P.off_fb_ids);
-        float* fsc = (float*)(ws + P.off_fb_scores);
-        std::vector<int64_t> foff(nb + 1, 0);
-        std::vector<int32_t> fkeys, fk(nb);
-        std::vector<float> fmult;
-        for (int i = 0; i < nb; ++i) {
-            const int q = fq[i];
-            HIP_TRY(hipMemcpyAsync(fu + (size_t)i * ix.dim, batch->user_emb + (size_t)q * ix.dim,
-                                   4 * (size_t)ix.dim, hipMemcpyDeviceToDevice, s));
-            for (int64_t j = batch->feat_offsets[q]; j < batch->feat_offsets[q + 1]; ++j) {
-                fkeys.push_back(batch->feat_keys[j]);
-                if (batch->feat_mult) fmult.push_back(batch->feat_mult[j]);
-            }
-            foff[i + 1] = (int64_t)fkeys.size();
-            fk[i] = P.kq[q];
-        }
-        ebr_batch fb{};
-        fb.n_queries = nb;
-        fb.user_emb = fu;
-        fb.feat_offsets = foff.data();
-        fb.feat_keys = fkeys.data();
-        fb.feat_mult = batch->feat_mult ? fmult.data() : nullptr;
-        fb.k = fk.data();
-        fb.scan_dtype = EBR_F32;
-        fb.rescore_factor = 0;
-        st = topk_impl(ix, &fb, ws, P.fb_limit, fids, fsc, s, nullptr);
+    // queries whose K (or K' = factor x K) exceeds the LDS sort: one full sort each, on the
+    // FP32 scan with 64-bit cross-term cells, written at the query's offsets
+    for (const int q : P.big) {
+        ebr_batch b1{};
+        const int64_t f0 = batch->feat_offsets[q];
+        const int64_t foff[2] = {0, batch->feat_offsets[q + 1] - f0};
+        b1.n_queries = 1;
+        b1.user_emb = batch->user_emb + (size_t)q * ix.dim;
+        b1.feat_offsets = foff;
+        b1.feat_keys = batch->feat_keys ? batch->feat_keys + f0 : nullptr;
+        b1.feat_mult = batch->feat_mult ? batch->feat_mult + f0 : nullptr;
+        b1.scan_dtype = EBR_F32;
+        b1.wide64 = 1;
+        st = check_users(&b1, 1, ix.dim, s);
         if (st) return st;
-        int64_t pos = 0;
-        for (int i = 0; i < nb; ++i) {
-            const int q = fq[i];
-            const size_t n = (size_t)P.kq[q];
-            HIP_TRY(hipMemcpyAsync(out_ids + P.out_off[q], fids + pos, 4 * n, hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipMemcpyAsync(out_scores + P.out_off[q], fsc + pos, 4 * n, hipMemcpyDeviceToDevice, s));
-            pos += (int64_t)n;
-        }
+        Plan Pd;
+        st = plan_batch(ix, &b1, false, &Pd);
+        if (st) return st;
+        if (Pd.total > P.off_big_deep) { set_error("full-sort plan exceeds its workspace"); return EBR_EDEVICE; }
+        const std::vector<char> blob = pack_plan(Pd);
+        st = run_decode(ix, Pd, ws, s, blob.data(), blob.size(), kDefaultDecodeChunks);
+        if (st) return st;
+        float* deep = (float*)(ws + P.off_big_deep);
+        float* wide = (float*)(ws + P.off_big_wide);
+        ScoreArgs a = score_args(ix, Pd, &b1, ws);
+        a.deep_out = deep;
+        a.wide_out = wide;
+        LAUNCH(launch_score(a, ix.dim, 2, score_ranges((int)ix.n_tiles, Pd.n_qg, score_ctas()), s));
+        const int64_t o = P.out_off[q], k = P.out_off[q + 1] - o;
+        LAUNCH(launch_full_sort_topk(deep, wide, ix.n_ads, k, (unsigned long long*)(ws + P.off_big_keys),
+                                     (unsigned long long*)(ws + P.off_big_tmp), (uint32_t*)(ws + P.off_big_hist),
+                                     (uint32_t*)(ws + P.off_big_stmp), out_ids + o, out_scores + o, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
     return EBR_OK;
@@ -1311,12 +1439,8 @@ ebr_status run_topk(const Index& ix, const ebr_batch* batch, char* ws, size_t ws
 }
 
 size_t topk_workspace_bytes(const Index& ix, int dtype, BatchSizes z) {
-    Plan P;
-    P.dtype = dtype;
-    P.gq = score_group_queries(ix.dim);
     z.n_sample = z.n_out > 0 ? sample_tile_count(ix, z.kcmax) : 0;
-    layout(ix, true, z, &P);
-    return P.total;
+    return layout_total(ix, z, dtype, false);
 }
 
 }  // namespace ebr
@@ -1479,7 +1603,7 @@ ebr_status ebr_autotune(ebr_index* index, const ebr_batch* batch, void* ws_v, si
         rep.best_ms = best_ms;
         {
             std::lock_guard<std::mutex> lk(index->shape_mu);
-            index->shapes[{P.dtype, nqg}] = best;
+            index->shapes[{P.w64 ? kShapeKeyWide64 : P.dtype, nqg}] = best;
         }
         // leave the winner's results in the outputs
         o.shape = &best;

@@ -83,6 +83,15 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
     return v;
 }
 
+// Whether a query's 32-bit cross term is precise enough for its result: the rounding bound
+// werr (half a quantum per feature) against the returned scores g0 >= ... >= gk must stay
+// within kWideTau of the smallest returned magnitude (gk for positive scores, |g0| for
+// negative ones, zero when the scores change sign).
+__device__ __forceinline__ bool wide_precise(float werr, float g0, float gk) {
+    const float mn = gk > 0.0f ? gk : (g0 < 0.0f ? -g0 : 0.0f);
+    return werr <= kWideTau * mn;
+}
+
 // FP32 -> BF16 bits, round to nearest even (finite inputs).
 __device__ __forceinline__ uint32_t bf16_bits(float x) {
     const uint32_t u = __float_as_uint(x);

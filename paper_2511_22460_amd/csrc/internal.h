@@ -132,6 +132,7 @@ struct BatchSizes {
     int kcmax = 0;          // largest K' (K, or the rescore factor times K) of the batch
     int64_t n_out = 0;      // sum of K
     int64_t n_sample = 0;   // sample tiles (derived; ignored by topk_workspace_bytes)
+    int64_t big_n = 0;      // ads to sort for queries whose K exceeds the LDS sort (0: none)
 };
 
 // Exact workspace bytes of a top-K batch of these sizes on scan dtype `dtype`.

@@ -12,6 +12,13 @@ constexpr int kStatusPending = 1;
 constexpr int kStatusNeedLower = 2;
 constexpr int kStatusOverflow = 3;
 constexpr int kStatusUncertified = 4;
+constexpr int kStatusImprecise = 5;
+
+// A 32-bit fixed-point cross term is accepted for a query when its worst-case rounding (half a
+// quantum per feature) is at most this fraction of every returned score's magnitude: 2^-18,
+// the worst-case relative error of a 64-term FP32 dot product (64 * 2^-24), a quarter of the
+// 1e-5 tolerance. Queries that miss it are rerun with 64-bit cells.
+constexpr float kWideTau = 0x1p-18f;
 
 // Threshold-revision rounds enqueued per batch without host synchronisation; a round whose
 // predecessor left no query unresolved exits at once.
@@ -22,7 +29,8 @@ struct Control {
     uint32_t error;                   // bit 0: non-finite user row; bit 1: not converged
     uint32_t unres[kMaxRounds];       // queries left unresolved by round r
     uint32_t uncertified;             // reduced-precision scans: failed certificates
-    uint32_t pad[10];
+    uint32_t imprecise;               // queries whose 32-bit cross term missed kWideTau
+    uint32_t pad[9];
 };
 
 struct DecodeArgs {
@@ -41,6 +49,7 @@ struct DecodeArgs {
     const uint32_t* st_off;           // n_super + 1 exclusive prefix
     uint32_t* st_fill;                // place pass: running fill per super-tile
     uint32_t* stage;                  // place pass: pairs ((slot << 10) | ad & 1023, w' bits)
+    uint2* chunk_map;                 // per batch chunk: (slot, chunk index in the index)
     const uint32_t* users_off;        // non-null: final entries carry their key's users range
     uint32_t* tile_off;               // refine: n_tiles + 1 offsets into bucket
     uint32_t* bucket;                 // refine: pairs (users range or slot | ad & 31, w' bits)
@@ -55,6 +64,7 @@ struct ScoreArgs {
     int32_t n_queries;
     int32_t n_qgroups;
     int32_t packed;                   // bucket entries carry users ranges (one query group)
+    int32_t wide64;                   // 64-bit cross-term cells (FP32 scans; 128-query groups)
     const uint32_t* tile_off;         // n_tiles + 1
     const uint32_t* bucket;           // pairs
     const uint32_t* users_off;        // n_ukeys * n_qgroups + 1
@@ -117,6 +127,9 @@ struct FinalArgs {
     float* out_scores;
     const uint32_t* gate;             // run only if null or *gate != 0
     const Control* ctl;               // nothing is written after an input error
+    const float* werr;                // output mode: per-query bound on the cross term's
+                                      // fixed-point rounding, or null (no check)
+    uint32_t* imprecise;              // count of queries that missed kWideTau
     uint32_t* r_id;                   // prep: B x r_ld ids in approximate rank order
     float* r_wide;                    // prep: their cross-term values
     float* r_stilde;                  // prep: the K'-th approximate score per query
@@ -135,6 +148,8 @@ struct RescoreArgs {
     const float* r_wide;
     const float* r_stilde;
     const float* eps;                 // per query: bound on |approximate - exact| score
+    const float* werr;                // per query: cross-term rounding bound, or null
+    uint32_t* imprecise;
     const Control* ctl;
     const uint32_t* skip;             // non-null and nonzero: selection unfinished, do nothing
     int32_t r_ld;
@@ -164,6 +179,8 @@ int launch_prep(const PrepArgs& a, void* stream);
 int launch_round_reset(uint32_t* cand_cnt, int32_t n, const uint32_t* gate, void* stream);
 int64_t scan_tmp_words(int64_t n);
 int launch_excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, void* stream);
+// Per batch chunk, its distinct-key slot and index chunk (before the decode passes).
+int launch_chunk_map(const DecodeArgs& a, void* stream);
 int launch_decode(const DecodeArgs& a, int place, void* stream);
 int launch_refine(const DecodeArgs& a, void* stream);
 // Decode the chunks [chunk0, chunk0 + n_chunks) of consecutive keys: posting p (index into the
@@ -172,11 +189,19 @@ int launch_decode_key(const ChunkHdr* chunks, const uint32_t* words, const float
                       uint32_t chunk0, uint32_t n_chunks, uint32_t post_base, uint32_t* ids,
                       float* w, void* stream);
 bool score_dim_supported(int dim);
-// Queries per query group of the scoring kernel for this embedding width.
-int score_group_queries(int dim);
+// Queries per query group of the scoring kernel for this embedding width and cell width.
+int score_group_queries(int dim, bool wide64 = false);
 int score_ranges(int n_work, int n_qgroups, int ctas);
 int launch_score(const ScoreArgs& a, int dim, int mode, int ranges, void* stream);
 int launch_select(const SelectArgs& a, int n_queries, void* stream);
+// Blocks of the full sort over n keys (its histogram holds 256 x blocks + 1 words).
+int64_t sort_blocks(int64_t n);
+// One query's top-K by a full sort of its n scores deep[a] + wide[a] (order: score descending,
+// id ascending): keys and tmp hold n 64-bit keys each, hist 256 x sort_blocks(n) + 1 words,
+// scan_tmp scan_tmp_words(256 x sort_blocks(n)) words; ids / scores receive K entries.
+int launch_full_sort_topk(const float* deep, const float* wide, int64_t n, int64_t k,
+                          unsigned long long* keys, unsigned long long* tmp, uint32_t* hist,
+                          uint32_t* scan_tmp, uint32_t* ids, float* scores, void* stream);
 int launch_finalize(const FinalArgs& a, int n_queries, void* stream);
 int launch_rescore(const RescoreArgs& a, int dim, int n_queries, void* stream);
 

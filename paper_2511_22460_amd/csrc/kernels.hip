@@ -1,11 +1,15 @@
 // gfx950 (CDNA4) kernels of libebr.
 //
 // One batch of queries runs as:
-//   1. k_decode (count)  - every chunk of every distinct key of the batch is decoded by one
-//                          wavefront; postings are counted per 32-ad tile.
-//   2. scan              - exclusive scan of the tile counts.
+//   0. k_chunk_map       - per chunk of the batch's distinct keys, its key slot and index
+//                          chunk.
+//   1. k_decode (count)  - every chunk is decoded by one wavefront (eight chunks' loads in
+//                          flight together); postings are counted per 1024-ad super-tile.
+//   2. scan              - exclusive scan of the super-tile counts.
 //   3. k_decode (place)  - decode again and place each posting (key slot, ad, weight) into
-//                          its tile's bucket: the batch's postings, tile-major.
+//                          its super-tile's staging range.
+//   3b. k_refine         - per super-tile, a counting sort by 32-ad tile in LDS: the batch's
+//                          postings, tile-major (the bucket).
 //   4. k_score (sample)  - full scores of an evenly spread sample of tiles.
 //   5. k_select          - per query, a radix select over the sample gives a score
 //                          threshold that at least j sample ads reach.
@@ -16,14 +20,18 @@
 //                          K written out; queries whose candidate count fell outside
 //                          [K, capacity] get a tighter or safer threshold and run again.
 //
-// The cross term of Section 3.3 (equation "hitmatch") is accumulated as 32-bit fixed point.
-// Each posting weight of key k is scaled exactly to w' = w * 2^Sw_k (|w'| < 2^30) when it is
-// placed into its bucket, and each (query, key) multiplier on the host to m' = m * 2^(S_q -
-// Sw_k), so that m' * w' = m * w * 2^S_q at one per-query scale with sum_j |m_j| max|W_kj|
-// 2^S_q < 2^30. A (query, posting) pair adds round(fl(m' * w')) to an int32 accumulator; the
-// integer sum is exact and does not depend on the order of the adds, so scores are
-// bit-identical across passes, tile schedules and batch compositions.
+// The cross term of Section 3.3 (equation "hitmatch") is accumulated in fixed point. Each
+// posting weight of key k is scaled exactly to w' = w * 2^Sw_k (|w'| < 2^30) when it is placed
+// into its bucket, and each (query, key) multiplier on the host to m' = m * 2^(S_q - Sw_k), so
+// that m' * w' = m * w * 2^S_q at one per-query scale with sum_j |m_j| max|W_kj| 2^S_q below
+// 2^31 (32-bit cells) or 2^63 (64-bit cells). A (query, posting) pair adds round(fl(m' * w'))
+// to its cell; the integer sum is exact and does not depend on the order of the adds, so
+// scores are bit-identical across passes, tile schedules and batch compositions. A query whose
+// 32-bit quantum is coarse against its returned scores is rerun with 64-bit cells.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <utility>
 
 #include "device_util.h"
 
@@ -98,7 +106,172 @@ __global__ __launch_bounds__(kScanNT) void k_scan_apply(const uint32_t* in, int6
 
 // ------------------------------------------------------------------ chunk decode
 
-// Decode chunk `chunk`: returns this lane's id (lanes >= count return garbage, valid=false).
+// One wavefront per distinct key of the batch: for each of the key's chunks, in batch order
+// (chunk gc = uk_chunk_prefix[u] + i), its slot u and its chunk index in the index.
+__global__ __launch_bounds__(256) void k_chunk_map(DecodeArgs a) {
+    const int lane = lane_id();
+    const int u = (int)(blockIdx.x * 4u + (threadIdx.x >> 6));
+    if (u >= a.n_ukeys) return;
+    const uint32_t p0 = a.uk_chunk_prefix[u], p1 = a.uk_chunk_prefix[u + 1];
+    const uint32_t c0 = a.uk_chunk_begin[u];
+    for (uint32_t gc = p0 + (uint32_t)lane; gc < p1; gc += 64u)
+        a.chunk_map[gc] = make_uint2((uint32_t)u, c0 + (gc - p0));
+}
+
+// Chunks whose loads one decode wavefront issues together (headers, then every gap word and
+// weight of the group), so that a group costs one chain of dependent loads.
+constexpr int kDecGroup = 8;
+
+// One wavefront decodes a.chunks_per_wave consecutive chunks of the batch's distinct keys and
+// counts (place == 0) or places (place == 1) their postings into 1024-ad super-tile buckets.
+// Runs of postings in the same super-tile are aggregated into one atomic per run. A placed
+// entry is ((slot << 10) | ad & 1023, w' bits); k_refine orders each super-tile by 32-ad tile.
+__global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
+    const int lane = lane_id();
+    const uint32_t gw = blockIdx.x * 4u + (threadIdx.x >> 6);
+    const uint32_t c_begin = gw * a.chunks_per_wave;
+    if (c_begin >= a.total_chunks) return;
+    const uint32_t c_end = min(a.total_chunks, c_begin + a.chunks_per_wave);
+    for (uint32_t g0 = c_begin; g0 < c_end; g0 += kDecGroup) {
+        const int n = (int)min((uint32_t)kDecGroup, c_end - g0);
+        // lane i < n: chunk g0 + i's slot and index chunk, then its header
+        uint2 m = make_uint2(0u, 0u);
+        uint4 h = make_uint4(0u, 0u, 0u, 0u);
+        if (lane < n) {
+            m = a.chunk_map[g0 + (uint32_t)lane];
+            h = *reinterpret_cast<const uint4*>(a.chunks + m.y);
+        }
+        // every chunk's gap words (and weights) for this lane, loads in flight together
+        uint32_t lo[kDecGroup], hi[kDecGroup];
+        float wt[kDecGroup];
+        #pragma unroll
+        for (int i = 0; i < kDecGroup; ++i) {
+            lo[i] = hi[i] = 0u;
+            wt[i] = 0.0f;
+            if (i < n) {  // wave-uniform
+                const uint32_t info = (uint32_t)__builtin_amdgcn_readlane((int)h.y, i);
+                const uint32_t woff = (uint32_t)__builtin_amdgcn_readlane((int)h.z, i);
+                const uint32_t poff = (uint32_t)__builtin_amdgcn_readlane((int)h.w, i);
+                const int b = (int)(info & 63u), count = (int)((info >> 8) & 127u);
+                if (lane >= 1 && lane < count && b > 0) {
+                    const uint32_t* w = a.words + woff + (((uint32_t)(lane - 1) * (uint32_t)b) >> 5);
+                    lo[i] = w[0];
+                    hi[i] = w[1];
+                }
+                if (place && lane < count) wt[i] = a.weights[poff + (uint32_t)lane];
+            }
+        }
+        #pragma unroll
+        for (int i = 0; i < kDecGroup; ++i) {
+            if (i >= n) break;
+            const uint32_t first = (uint32_t)__builtin_amdgcn_readlane((int)h.x, i);
+            const uint32_t info = (uint32_t)__builtin_amdgcn_readlane((int)h.y, i);
+            const uint32_t u = (uint32_t)__builtin_amdgcn_readlane((int)m.x, i);
+            const int b = (int)(info & 63u), count = (int)((info >> 8) & 127u);
+            uint32_t gap = 0;
+            if (lane >= 1 && lane < count && b > 0) {
+                const uint32_t sh = ((uint32_t)(lane - 1) * (uint32_t)b) & 31u;
+                const uint64_t v = (((uint64_t)hi[i] << 32) | (uint64_t)lo[i]) >> sh;
+                gap = (b == 32) ? (uint32_t)v : ((uint32_t)v & ((1u << b) - 1u));
+            }
+            const uint32_t delta = (lane >= 1 && lane < count) ? gap + 1u : 0u;
+            const uint32_t id = first + wave_incl_scan(delta);
+            const bool valid = lane < count;
+            const uint32_t st = id >> kSuperShift;
+            const uint32_t prev = __shfl_up(st, 1, 64);
+            const bool head = valid && (lane == 0 || st != prev);
+            const uint64_t heads = __ballot(head);
+            const uint64_t above = (lane == 63) ? 0ull : (heads & (~0ull << (lane + 1)));
+            const int next = above ? (int)__builtin_ctzll(above) : count;
+            const int run = next - lane;
+            if (!place) {
+                if (head) atomicAdd(&a.st_cnt[st], (uint32_t)run);
+                continue;
+            }
+            uint32_t base = 0;
+            if (head) base = atomicAdd(&a.st_fill[st], (uint32_t)run);
+            const uint64_t upto = (lane == 63) ? heads : (heads & ((2ull << lane) - 1ull));
+            const int my_head = upto ? 63 - (int)__builtin_clzll(upto) : 0;
+            base = __shfl(base, my_head, 64);
+            if (valid) {
+                const uint32_t pos = a.st_off[st] + base + (uint32_t)(lane - my_head);
+                const float ws = ldexpf(wt[i], a.uk_wshift[u]);  // exact: a power-of-two scale
+                reinterpret_cast<uint2*>(a.stage)[pos] =
+                    make_uint2((u << kSuperShift) | (id & (kSuperAds - 1)), __float_as_uint(ws));
+            }
+        }
+    }
+}
+
+// Entries of one super-tile a k_refine work-group keeps in registers (per thread) when they
+// fit; larger super-tiles are read twice.
+constexpr int kRefineNT = 1024, kRefineRegs = 16;
+
+// One work-group per super-tile: counting sort of its entries by 32-ad tile (LDS counters),
+// the tile offsets, and the final entry format read by k_score: x = (u0 << 13) |
+// ((cnt - 1) << 5) | ad & 31 when the batch is one query group (users[u0, u0 + cnt) are the
+// key's users), else (slot << 5) | ad & 31; y = the bits of w'.
+__global__ __launch_bounds__(kRefineNT) void k_refine(DecodeArgs a) {
+    __shared__ uint32_t s_cnt[kTilesPerSuper], s_off[kTilesPerSuper];
+    const uint32_t st = blockIdx.x;
+    const uint32_t beg = a.st_off[st], end = a.st_off[st + 1];
+    const int tid = (int)threadIdx.x;
+    if (tid < kTilesPerSuper) s_cnt[tid] = 0u;
+    __syncthreads();
+    const uint2* in = reinterpret_cast<const uint2*>(a.stage);
+    const bool regs = end - beg <= (uint32_t)(kRefineNT * kRefineRegs);
+    uint2 e[kRefineRegs];
+    auto tile_of = [](uint2 v) { return (v.x >> kTileShift) & (kTilesPerSuper - 1); };
+    if (regs) {
+        #pragma unroll
+        for (int r = 0; r < kRefineRegs; ++r) {
+            const uint32_t i = beg + (uint32_t)tid + (uint32_t)(r * kRefineNT);
+            if (i < end) e[r] = in[i];
+        }
+        #pragma unroll
+        for (int r = 0; r < kRefineRegs; ++r)
+            if (beg + (uint32_t)tid + (uint32_t)(r * kRefineNT) < end) atomicAdd(&s_cnt[tile_of(e[r])], 1u);
+    } else {
+        for (uint32_t i = beg + (uint32_t)tid; i < end; i += kRefineNT) atomicAdd(&s_cnt[tile_of(in[i])], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = beg;
+        for (int t = 0; t < kTilesPerSuper; ++t) {
+            s_off[t] = run;
+            run += s_cnt[t];
+            s_cnt[t] = 0u;
+        }
+    }
+    __syncthreads();
+    if (tid < kTilesPerSuper) {
+        const uint64_t tile = (uint64_t)st * kTilesPerSuper + (uint64_t)tid;
+        if (tile < (uint64_t)a.n_tiles) a.tile_off[tile] = s_off[tid];
+    }
+    if (st == gridDim.x - 1 && tid == 0) a.tile_off[a.n_tiles] = end;
+    uint2* out = reinterpret_cast<uint2*>(a.bucket);
+    auto place = [&](uint2 v) {
+        const uint32_t t = tile_of(v);
+        const uint32_t pos = s_off[t] + atomicAdd(&s_cnt[t], 1u);
+        const uint32_t u = v.x >> kSuperShift, o = v.x & (kTileAds - 1);
+        uint32_t x = (u << kTileShift) | o;
+        if (a.users_off) {
+            const uint32_t u0 = a.users_off[u];
+            x = (u0 << 13) | ((a.users_off[u + 1] - u0 - 1u) << kTileShift) | o;
+        }
+        out[pos] = make_uint2(x, v.y);
+    };
+    if (regs) {
+        #pragma unroll
+        for (int r = 0; r < kRefineRegs; ++r)
+            if (beg + (uint32_t)tid + (uint32_t)(r * kRefineNT) < end) place(e[r]);
+    } else {
+        for (uint32_t i = beg + (uint32_t)tid; i < end; i += kRefineNT) place(in[i]);
+    }
+}
+
+// Decode chunk `chunk` (test hook path): returns this lane's id (lanes >= count return
+// garbage).
 __device__ __forceinline__ uint32_t decode_chunk_lane(const ChunkHdr* chunks, const uint32_t* words,
                                                       uint32_t chunk, int* count_out,
                                                       uint32_t* post_off_out) {
@@ -119,100 +292,6 @@ __device__ __forceinline__ uint32_t decode_chunk_lane(const ChunkHdr* chunks, co
     *count_out = count;
     *post_off_out = h.w;
     return id;
-}
-
-// One wavefront decodes a.chunks_per_wave consecutive chunks of the batch's distinct keys and
-// counts (place == 0) or places (place == 1) their postings into 1024-ad super-tile buckets.
-// Runs of postings in the same super-tile are aggregated into one atomic per run. A placed
-// entry is ((slot << 10) | ad & 1023, w' bits); k_refine orders each super-tile by 32-ad tile.
-__global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
-    const int lane = lane_id();
-    const uint32_t gw = blockIdx.x * 4u + (threadIdx.x >> 6);
-    const uint32_t c_begin = gw * a.chunks_per_wave;
-    if (c_begin >= a.total_chunks) return;
-    const uint32_t c_end = min(a.total_chunks, c_begin + a.chunks_per_wave);
-    // distinct-key slot owning the first chunk: the last u with prefix[u] <= c_begin
-    int lo = 0, hi = a.n_ukeys;
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (a.uk_chunk_prefix[mid] <= c_begin) lo = mid; else hi = mid;
-    }
-    uint32_t u = (uint32_t)lo;
-    for (uint32_t gc = c_begin; gc < c_end; ++gc) {
-        while (a.uk_chunk_prefix[u + 1] <= gc) ++u;
-        const uint32_t chunk = a.uk_chunk_begin[u] + (gc - a.uk_chunk_prefix[u]);
-        int count;
-        uint32_t post_off;
-        const uint32_t id = decode_chunk_lane(a.chunks, a.words, chunk, &count, &post_off);
-        const bool valid = lane < count;
-        const uint32_t st = id >> kSuperShift;
-        const uint32_t prev = __shfl_up(st, 1, 64);
-        const bool head = valid && (lane == 0 || st != prev);
-        const uint64_t heads = __ballot(head);
-        const uint64_t above = (lane == 63) ? 0ull : (heads & (~0ull << (lane + 1)));
-        const int next = above ? (int)__builtin_ctzll(above) : count;
-        const int run = next - lane;
-        if (!place) {
-            if (head) atomicAdd(&a.st_cnt[st], (uint32_t)run);
-            continue;
-        }
-        uint32_t base = 0;
-        if (head) base = atomicAdd(&a.st_fill[st], (uint32_t)run);
-        const uint64_t upto = (lane == 63) ? heads : (heads & ((2ull << lane) - 1ull));
-        const int my_head = upto ? 63 - (int)__builtin_clzll(upto) : 0;
-        base = __shfl(base, my_head, 64);
-        if (valid) {
-            const uint32_t pos = a.st_off[st] + base + (uint32_t)(lane - my_head);
-            const float w = a.weights[post_off + lane];
-            const float ws = ldexpf(w, a.uk_wshift[u]);  // exact: a power-of-two scale
-            reinterpret_cast<uint2*>(a.stage)[pos] =
-                make_uint2((u << kSuperShift) | (id & (kSuperAds - 1)), __float_as_uint(ws));
-        }
-    }
-}
-
-// One work-group per super-tile: counting sort of its entries by 32-ad tile (LDS counters),
-// the tile offsets, and the final entry format read by k_score: x = (u0 << 13) |
-// ((cnt - 1) << 5) | ad & 31 when the batch is one query group (users[u0, u0 + cnt) are the
-// key's users), else (slot << 5) | ad & 31; y = the bits of w'.
-__global__ __launch_bounds__(256) void k_refine(DecodeArgs a) {
-    __shared__ uint32_t s_cnt[kTilesPerSuper], s_off[kTilesPerSuper];
-    const uint32_t st = blockIdx.x;
-    const uint32_t beg = a.st_off[st], end = a.st_off[st + 1];
-    const int tid = (int)threadIdx.x;
-    if (tid < kTilesPerSuper) s_cnt[tid] = 0u;
-    __syncthreads();
-    const uint2* in = reinterpret_cast<const uint2*>(a.stage);
-    for (uint32_t i = beg + (uint32_t)tid; i < end; i += 256u)
-        atomicAdd(&s_cnt[(in[i].x >> kTileShift) & (kTilesPerSuper - 1)], 1u);
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t run = beg;
-        for (int t = 0; t < kTilesPerSuper; ++t) {
-            s_off[t] = run;
-            run += s_cnt[t];
-            s_cnt[t] = 0u;
-        }
-    }
-    __syncthreads();
-    if (tid < kTilesPerSuper) {
-        const uint64_t tile = (uint64_t)st * kTilesPerSuper + (uint64_t)tid;
-        if (tile < (uint64_t)a.n_tiles) a.tile_off[tile] = s_off[tid];
-    }
-    if (st == gridDim.x - 1 && tid == 0) a.tile_off[a.n_tiles] = end;
-    uint2* out = reinterpret_cast<uint2*>(a.bucket);
-    for (uint32_t i = beg + (uint32_t)tid; i < end; i += 256u) {
-        const uint2 e = in[i];
-        const uint32_t t = (e.x >> kTileShift) & (kTilesPerSuper - 1);
-        const uint32_t pos = s_off[t] + atomicAdd(&s_cnt[t], 1u);
-        const uint32_t u = e.x >> kSuperShift, o = e.x & (kTileAds - 1);
-        uint32_t x = (u << kTileShift) | o;
-        if (a.users_off) {
-            const uint32_t u0 = a.users_off[u];
-            x = (u0 << 13) | ((a.users_off[u + 1] - u0 - 1u) << kTileShift) | o;
-        }
-        out[pos] = make_uint2(x, e.y);
-    }
 }
 
 // One wavefront per chunk of a run of consecutive keys: posting t of the run (in key order) goes
@@ -338,6 +417,7 @@ __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
         }
         return;
     }
+    int done = kStatusDone;
     if (!a.prep) {
         const int K = a.kq[q];
         const int64_t o = a.out_off[q];
@@ -346,6 +426,9 @@ __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
             a.out_ids[o + i] = 0xffffffffu - (uint32_t)t;
             a.out_scores[o + i] = key_score((uint32_t)(t >> 32));
         }
+        if (a.werr && !wide_precise(a.werr[q], key_score((uint32_t)(s[0] >> 32)),
+                                    key_score((uint32_t)(s[K - 1] >> 32))))
+            done = kStatusImprecise;
     } else {
         // the Kc best by approximate key, in rank order, with their carried cross terms
         const unsigned long long T = s[Kc - 1];
@@ -364,9 +447,98 @@ __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
         }
         if (tid == 0) a.r_stilde[q] = key_score((uint32_t)(T >> 32));
     }
-    if (tid == 0) { a.status[q] = kStatusDone; a.active[q] = 0u; }
+    if (tid == 0) {
+        a.status[q] = done;
+        a.active[q] = 0u;
+        if (done == kStatusImprecise) atomicAdd(a.imprecise, 1u);
+    }
 }
 
+
+// ------------------------------------------------------------------ full sort (K > 8192)
+
+// A query whose K exceeds the candidate buffer's sort is answered by sorting all of its
+// scores: ck[a] = (~score_key(deep + wide) << 32) | a, so that ascending ck is the order
+// (score descending, id ascending); the sum is the scan's own score (deep + wide is one FP32
+// rounding, as fma(cell, 2^-S, deep) with the exact wide term).
+__global__ void k_sort_keys(const float* deep, const float* wide, int64_t n, unsigned long long* ck) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        ck[i] = ((unsigned long long)(~score_key(deep[i] + wide[i])) << 32) | (unsigned long long)(uint32_t)i;
+}
+
+// LSD radix sort of 64-bit keys, 8 bits per pass, ascending and stable: each block of
+// kSortTile keys counts its digits (hist[digit * blocks + block]); an exclusive scan of hist
+// gives every (digit, block) its first output slot; the scatter ranks equal digits inside the
+// block in index order (wave match by ballots, then per-wave counts in LDS).
+constexpr int kSortNT = 256, kSortPer = 16, kSortTile = kSortNT * kSortPer;
+
+__global__ __launch_bounds__(kSortNT) void k_sort_hist(const unsigned long long* in, int64_t n, int shift,
+                                                       uint32_t* hist, int64_t nblk) {
+    __shared__ uint32_t h[256];
+    const int tid = (int)threadIdx.x;
+    h[tid] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int j = 0; j < kSortPer; ++j) {
+        const int64_t i = base + (int64_t)j * kSortNT + tid;
+        if (i < n) atomicAdd(&h[(uint32_t)(in[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)tid * nblk + blockIdx.x] = h[tid];
+}
+
+__global__ __launch_bounds__(kSortNT) void k_sort_scatter(const unsigned long long* in, unsigned long long* out,
+                                                          int64_t n, int shift, const uint32_t* offs,
+                                                          int64_t nblk) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kSortNT / 64][256];
+    const int tid = (int)threadIdx.x, lane = lane_id(), w = tid >> 6;
+    run[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int j = 0; j < kSortPer; ++j) {
+        #pragma unroll
+        for (int k = 0; k < kSortNT / 64; ++k) wcnt[k][tid] = 0u;
+        __syncthreads();
+        const int64_t i = base + (int64_t)j * kSortNT + tid;
+        const bool ok = i < n;
+        const unsigned long long x = ok ? in[i] : 0ull;
+        const uint32_t d = (uint32_t)(x >> shift) & 255u;
+        // lanes of this wave holding the same digit
+        uint64_t peers = __ballot(ok);
+        #pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const uint64_t below = peers & ((1ull << lane) - 1ull);
+        const uint32_t rank = (uint32_t)__builtin_popcountll(below);
+        if (ok && below == 0ull) wcnt[w][d] = (uint32_t)__builtin_popcountll(peers);
+        __syncthreads();
+        if (ok) {
+            uint32_t pos = run[d] + rank;
+            for (int k = 0; k < w; ++k) pos += wcnt[k][d];
+            out[pos] = x;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        #pragma unroll
+        for (int k = 0; k < kSortNT / 64; ++k) add += wcnt[k][tid];
+        run[tid] += add;
+    }
+}
+
+// The first K of the sorted keys as ids and scores.
+__global__ void k_sort_out(const unsigned long long* ck, int64_t k, uint32_t* ids, float* scores) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < k; i += stride) {
+        const unsigned long long v = ck[i];
+        ids[i] = (uint32_t)v;
+        scores[i] = key_score(~(uint32_t)(v >> 32));
+    }
+}
 
 // ------------------------------------------------------------------ per-query set-up
 
@@ -462,7 +634,13 @@ int launch_excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t*
 
 int launch_refine(const DecodeArgs& a, void* stream) {
     if (a.n_super <= 0) return 0;
-    hipLaunchKernelGGL(k_refine, dim3((unsigned)a.n_super), dim3(256), 0, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(k_refine, dim3((unsigned)a.n_super), dim3(kRefineNT), 0, (hipStream_t)stream, a);
+    return last(hipSuccess);
+}
+
+int launch_chunk_map(const DecodeArgs& a, void* stream) {
+    if (a.n_ukeys <= 0 || a.total_chunks == 0) return 0;
+    hipLaunchKernelGGL(k_chunk_map, dim3((unsigned)((a.n_ukeys + 3) / 4)), dim3(256), 0, (hipStream_t)stream, a);
     return last(hipSuccess);
 }
 
@@ -485,7 +663,7 @@ int launch_decode_key(const ChunkHdr* chunks, const uint32_t* words, const float
 }
 
 
-int score_group_queries(int dim) { return dim <= 64 ? 256 : 128; }
+int score_group_queries(int dim, bool wide64) { return (dim <= 64 && !wide64) ? 256 : 128; }
 
 bool score_dim_supported(int dim) {
     switch (dim) {
@@ -521,6 +699,30 @@ int launch_score(const ScoreArgs& a_in, int dim, int mode, int ranges, void* str
         case 128: launch_score_d<128>(a, mode, dt, grid, st); break;
         default: return (int)hipErrorInvalidValue;
     }
+    return last(hipSuccess);
+}
+
+int64_t sort_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+int launch_full_sort_topk(const float* deep, const float* wide, int64_t n, int64_t k,
+                          unsigned long long* keys, unsigned long long* tmp, uint32_t* hist,
+                          uint32_t* scan_tmp, uint32_t* ids, float* scores, void* stream) {
+    if (n <= 0 || k <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nb = sort_blocks(n);
+    const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_sort_keys, dim3(g), dim3(256), 0, st, deep, wide, n, keys);
+    unsigned long long* a = keys;
+    unsigned long long* b = tmp;
+    for (int shift = 0; shift < 64; shift += 8) {
+        hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)nb), dim3(kSortNT), 0, st, a, n, shift, hist, nb);
+        const int rc = launch_excl_scan_u32(hist, hist, 256 * nb, scan_tmp, stream);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)nb), dim3(kSortNT), 0, st, a, b, n, shift, hist, nb);
+        std::swap(a, b);
+    }
+    const unsigned go = (unsigned)std::min<int64_t>((k + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_sort_out, dim3(go), dim3(256), 0, st, a, k, ids, scores);
     return last(hipSuccess);
 }
 

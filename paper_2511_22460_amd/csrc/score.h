@@ -27,16 +27,59 @@ namespace ebr {
 // Accumulator layout of v_mfma_f32_32x32x2_f32: register r of lane l holds row
 // 8 * (r >> 2) + 4 * (l >> 5) + (r & 3), column l & 31.
 //
-// Cross-term accumulators: int64 per (query, ad) in LDS (layout: acc_idx below).
+// Cross-term accumulators: one fixed-point cell per (query, ad) in LDS (layout: acc_idx
+// below), 32-bit, or 64-bit (W64) for queries whose 32-bit quantum is too coarse.
 constexpr int kProducerWaves = 8;
+// Producer waves: one stager (embedding blocks into LDS), the others accumulate the cross term.
+constexpr int kStageWaves = 1;
+constexpr int kCrossWaves = kProducerWaves - kStageWaves;
+constexpr int kStageThreads = 64 * kStageWaves;
 
-// Queries per group: 256 (8 consumer waves) up to d = 64, 128 (4 consumer waves) above, so
-// that the U operand and the LDS buffers fit.
-template <int D> struct ScoreShape {
-    static constexpr int GQ = D <= 64 ? 256 : 128;
+template <bool W64> using AccT = typename std::conditional<W64, unsigned long long, uint32_t>::type;
+
+// Queries per group: 256 (8 consumer waves) up to d = 64 with 32-bit cells, else 128 (4
+// consumer waves), so that the U operand and the LDS buffers fit.
+template <int D, bool W64 = false> struct ScoreShape {
+    static constexpr int GQ = (D <= 64 && !W64) ? 256 : 128;
     static constexpr int CW = GQ / 32;
     static constexpr int NT = 64 * (CW + kProducerWaves);
+    // (query, multiplier) pairs of a one-group batch copied to LDS when they fit
+    static constexpr int USERS_LDS = (D > 64 && W64) ? 4096 : 8192;
 };
+
+// FP32 -> int64, round to nearest even; |p| <= 2^62 (the planner's bound for 64-bit cells).
+// The integer value rint(p) is split exactly into 32-bit halves of its magnitude.
+__device__ __forceinline__ long long f32_to_i64_rn(float p) {
+    const float r = rintf(p);
+    const float m = fabsf(r);
+    const float hi = floorf(m * 0x1p-32f);   // <= 2^30
+    const float lo = fmaf(hi, -0x1p32f, m);  // m - hi 2^32: exact, in [0, 2^32)
+    const unsigned long long v =
+        ((unsigned long long)(uint32_t)hi << 32) | (unsigned long long)(uint32_t)lo;
+    return r < 0.0f ? -(long long)v : (long long)v;
+}
+
+// A cell's fixed-point sum as FP32 (one rounding, to nearest even).
+__device__ __forceinline__ float acc_value(uint32_t v) { return (float)(int)v; }
+__device__ __forceinline__ float acc_value(unsigned long long v) { return (float)(long long)v; }
+
+// Four consecutive cells (one lane's rows r .. r + 3 of a column): read, and clear.
+__device__ __forceinline__ void read4(const uint32_t* p, uint32_t* v) {
+    const uint4 x = *reinterpret_cast<const uint4*>(p);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+__device__ __forceinline__ void read4(const unsigned long long* p, unsigned long long* v) {
+    const ulonglong2 x = reinterpret_cast<const ulonglong2*>(p)[0];
+    const ulonglong2 y = reinterpret_cast<const ulonglong2*>(p)[1];
+    v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+}
+__device__ __forceinline__ void clear4(uint32_t* p) {
+    *reinterpret_cast<uint4*>(p) = make_uint4(0u, 0u, 0u, 0u);
+}
+__device__ __forceinline__ void clear4(unsigned long long* p) {
+    reinterpret_cast<ulonglong2*>(p)[0] = make_ulonglong2(0ull, 0ull);
+    reinterpret_cast<ulonglong2*>(p)[1] = make_ulonglong2(0ull, 0ull);
+}
 
 // Accumulator cell of (query row q, ad offset o): rows are grouped by four so that the four
 // consecutive rows one lane of the 32x32 matrix-core tile owns are adjacent (two 16-byte
@@ -70,26 +113,35 @@ __device__ __attribute__((noinline)) void store_dense(float* deep_out, float* wi
 
 // Bucket entry: x = (u0 << 13) | ((cnt - 1) << 5) | ad offset when the batch is one query
 // group (the key's users are users[u0, u0 + cnt)), else (slot << 5) | ad offset; y = w' bits.
-// Producer wave pw owns entries beg + pw + 8 * (lane + 64 r) of each tile; round r = 0 is
-// prefetched one tile ahead.
+// Cross-term wave xw owns entries beg + xw + kCrossWaves * (lane + 64 r) of each tile; round
+// r = 0 is prefetched one tile ahead.
 struct ProdTile {
     uint32_t beg, end;  // the tile's bucket range
     uint2 e0;           // this lane's round-0 entry (valid if beg + pw + 8 * lane < end)
 };
 
+// Users one lane adds per item: an item is (bucket entry, up to kUserChunk of the users of the
+// entry's key), so a lane runs kUserChunk independent (load, multiply, LDS add) sequences per
+// item and the cost of assigning items to lanes is shared by that many pairs. An entry with
+// cnt users has nch = ceil(cnt / 8) items; item c takes the users c + j nch (j = 0..7, below
+// cnt), so that the lanes holding an entry's consecutive items read consecutive users (one
+// LDS bank each) at every j.
+constexpr int kUserChunk = 8;
 
-// Up to 64 bucket entries of one tile (one per lane) flattened into their (entry, user) pairs,
-// 64 pairs per step: an exclusive scan of the entries' user counts places each entry's pairs;
-// each entry writes its lane into the slot of its first pair in this wave's LDS row `mark`,
-// a running maximum over the row gives every pair its entry, whose fields come from its lane.
-// Each pair costs one users[] load, one 32 x 32 -> 64-bit multiply and one LDS atomic add.
-struct EntryLanes {
-    uint32_t cnt, pre, total;  // users of this lane's entry, pairs before it, pairs in all
-    int base, o, w;            // users index of pair p is base + p; ad offset; weight
+// Up to 64 bucket entries of one tile (one per lane) cut into items and laid out 64 items per
+// step: an exclusive scan of the entries' item counts places each entry's items; each entry
+// writes (first item << 6 | lane) into the slot of its first item in this wave's LDS row
+// `mark`, and a running maximum over the row gives every item its entry and, from the high
+// bits, its chunk within the entry.
+struct EntryItems {
+    uint32_t nch, pre, total;  // items of this lane's entry, items before it, items in all
+    uint32_t u0;               // users index of the entry's first user
+    uint32_t co;               // (users count << 5) | ad offset
+    uint32_t w;                // w' bits
 };
 
-__device__ __forceinline__ EntryLanes entry_lanes(const ScoreArgs& a, int g, uint2 e, bool valid) {
-    EntryLanes t;
+__device__ __forceinline__ EntryItems entry_items(const ScoreArgs& a, int g, uint2 e, bool valid) {
+    EntryItems t;
     uint32_t cnt = 0, u0 = 0;
     if (valid) {
         if (a.packed) {
@@ -101,54 +153,53 @@ __device__ __forceinline__ EntryLanes entry_lanes(const ScoreArgs& a, int g, uin
             cnt = a.users_off[slot + 1] - u0;
         }
     }
-    const uint32_t incl = wave_incl_sum(cnt);
-    t.cnt = cnt;
-    t.pre = incl - cnt;
+    t.nch = (cnt + (kUserChunk - 1)) / kUserChunk;
+    const uint32_t incl = wave_incl_sum(t.nch);
+    t.pre = incl - t.nch;
     t.total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    t.base = (int)(u0 - t.pre);
-    t.o = (int)(e.x & (kTileAds - 1));
-    t.w = (int)e.y;
+    t.u0 = u0;
+    t.co = (cnt << kTileShift) | (e.x & (kTileAds - 1));
+    t.w = e.y;
     return t;
 }
 
-// Entries (lanes) of the pairs of K consecutive steps s0 .. s0 + K - 1 (step s: pairs 64 s ..
-// 64 s + 63), with one LDS row of 64 slots per step, so that the rows of all K steps are
-// cleared, marked and read back in one round trip. carry is the entry of pair 64 s0 - 1 on
-// entry (-1 before the first step) and of the last pair of the last step on return.
-constexpr int kMarkRows = 4;
-template <int K>
-__device__ __forceinline__ void steps_entries(const EntryLanes& t, uint32_t s0, int* mark, int& carry,
-                                              int* m) {
-    static_assert(K <= kMarkRows, "one row per step");
+// Owner of item 64 s + lane: (first item of the owning entry << 6) | its lane, or -1 past the
+// items. carry is the owner of item 64 s - 1 on entry (-1 before the first step) and of item
+// 64 s + 63 on return.
+__device__ __forceinline__ int step_owner(const EntryItems& t, uint32_t s, int* mark, int& carry) {
     const int lane = lane_id();
     // LDS operations of one wave complete in the order issued: clear, mark, read back. Lanes
-    // exchange values through the rows, so the compiler must neither reorder nor elide these
+    // exchange values through the row, so the compiler must neither reorder nor elide these
     // accesses (it sees them as one thread's accesses to unrelated addresses): compiler
     // barriers between them.
-    #pragma unroll
-    for (int k = 0; k < K; ++k) mark[k * 64 + lane] = -1;
+    mark[lane] = -1;
     __asm__ __volatile__("" ::: "memory");
-    if (t.cnt > 0u && t.pre >= 64u * s0 && t.pre < 64u * (s0 + K)) mark[t.pre - 64u * s0] = lane;
+    if (t.nch > 0u && t.pre >= 64u * s && t.pre < 64u * (s + 1))
+        mark[t.pre - 64u * s] = (int)((t.pre << 6) | (uint32_t)lane);
     __asm__ __volatile__("" ::: "memory");
-    int mk[K];
-    #pragma unroll
-    for (int k = 0; k < K; ++k) mk[k] = mark[k * 64 + lane];
+    int mk = mark[lane];
     __asm__ __volatile__("" ::: "memory");
-    #pragma unroll
-    for (int k = 0; k < K; ++k) mk[k] = wave_incl_max(mk[k]);
-    #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        m[k] = max(mk[k], carry);
-        carry = __builtin_amdgcn_readlane(m[k], 63);
-    }
+    const int m = max(wave_incl_max(mk), carry);
+    carry = __builtin_amdgcn_readlane(m, 63);
+    return m;
 }
 
-// One (query, posting) pair: round(fl(m' * w')) into the query's cell (users hold m' bits,
-// bucket entries w' bits).
-__device__ __forceinline__ void pair_add(uint32_t* acc, uint2 ue, int o, int w) {
-    const float p = __uint_as_float(ue.y) * __uint_as_float((uint32_t)w);
-    atomicAdd(&acc[acc_idx((int)ue.x, o)], (uint32_t)__float2int_rn(p));
+// owner of item 64 s_begin - 1: the last lane with items whose first item lies before it
+__device__ __forceinline__ int carry_before(const EntryItems& t, uint32_t s_begin) {
+    if (s_begin == 0) return -1;
+    const uint64_t before = __ballot(t.nch > 0u && t.pre < 64u * s_begin);
+    if (!before) return -1;
+    const int l = 63 - (int)__builtin_clzll(before);
+    return __builtin_amdgcn_readlane((int)((t.pre << 6) | (uint32_t)lane_id()), l);
 }
+
+// One item mapped to this lane: its users' (query row, m') pairs loaded, the entry's ad offset
+// and weight; bit j of valid: user j exists (0: no item).
+struct ItemLoad {
+    uint2 ue[kUserChunk];
+    int o, w;
+    uint32_t valid;
+};
 
 // The (query, multiplier) pairs of a one-group batch copied to LDS: an LDS-typed pointer, so
 // that its loads are LDS reads (a generic pointer would make them flat loads).
@@ -165,80 +216,104 @@ __device__ __forceinline__ uint2 user_at(const ScoreArgs& a, lds_uint2* lds_user
     }
 }
 
-// Pairs of steps [s_begin, end) of a set of entries, four steps mapped before their loads.
 template <bool LU>
-__device__ __forceinline__ void cross_steps(const ScoreArgs& a, const EntryLanes& t, uint32_t s_begin,
-                                            int* mark, uint32_t* acc, lds_uint2* lds_users) {
+__device__ __forceinline__ ItemLoad item_load(const ScoreArgs& a, const EntryItems& t, uint32_t s, int m,
+                                              lds_uint2* lds_users) {
+    ItemLoad it;
     const int lane = lane_id();
-    // entry of pair 64 s_begin - 1: the last lane with a non-empty entry starting before it
-    int carry = -1;
-    if (s_begin > 0) {
-        const uint64_t before = __ballot(t.cnt > 0u && t.pre < 64u * s_begin);
-        carry = before ? 63 - (int)__builtin_clzll(before) : -1;
+    const uint32_t k = 64u * s + (uint32_t)lane;
+    const int ml = m & 63;
+    const uint32_t u0 = (uint32_t)__shfl((int)t.u0, ml, 64);
+    const uint32_t co = (uint32_t)__shfl((int)t.co, ml, 64);
+    it.w = __shfl((int)t.w, ml, 64);
+    it.o = (int)(co & (kTileAds - 1));
+    const uint32_t c = k - ((uint32_t)m >> 6);  // item (chunk) index within its entry
+    const uint32_t cnt = co >> kTileShift;
+    const uint32_t nch = (cnt + (kUserChunk - 1)) / kUserChunk;
+    const bool on = k < t.total && m >= 0;
+    it.valid = 0u;
+    #pragma unroll
+    for (int j = 0; j < kUserChunk; ++j) {
+        const uint32_t uj = c + (uint32_t)j * nch;
+        const bool ok = on && uj < cnt;
+        it.valid |= ok ? (1u << j) : 0u;
+        it.ue[j] = ok ? user_at<LU>(a, lds_users, u0 + uj) : make_uint2(0u, 0u);
     }
-    constexpr int kSteps = kMarkRows;
-    for (uint32_t s = s_begin; 64u * s < t.total; s += kSteps) {
-        int m[kSteps], ub[kSteps], uo[kSteps], uw[kSteps];
-        steps_entries<kSteps>(t, s, mark, carry, m);
-        #pragma unroll
-        for (int k = 0; k < kSteps; ++k) {
-            ub[k] = __shfl(t.base, m[k], 64);
-            uo[k] = __shfl(t.o, m[k], 64);
-            uw[k] = __shfl(t.w, m[k], 64);
-        }
-        uint2 ue[kSteps];
-        #pragma unroll
-        for (int k = 0; k < kSteps; ++k) {
-            const uint32_t p = 64u * (s + k) + (uint32_t)lane;
-            if (p < t.total) ue[k] = user_at<LU>(a, lds_users, (uint32_t)ub[k] + p);
-        }
-        #pragma unroll
-        for (int k = 0; k < kSteps; ++k)
-            if (64u * (s + k) + (uint32_t)lane < t.total) pair_add(acc, ue[k], uo[k], uw[k]);
+    return it;
+}
+
+// Every entry of the wave has at most kUserChunk users (one item each): the item of lane l is
+// lane l's own entry, with no search.
+template <bool LU>
+__device__ __forceinline__ ItemLoad own_item_load(const ScoreArgs& a, const EntryItems& t, lds_uint2* lds_users) {
+    ItemLoad it;
+    const uint32_t cnt = t.co >> kTileShift;
+    it.o = (int)(t.co & (kTileAds - 1));
+    it.w = (int)t.w;
+    it.valid = 0u;
+    #pragma unroll
+    for (int j = 0; j < kUserChunk; ++j) {
+        const bool ok = (uint32_t)j < cnt;
+        it.valid |= ok ? (1u << j) : 0u;
+        it.ue[j] = ok ? user_at<LU>(a, lds_users, t.u0 + (uint32_t)j) : make_uint2(0u, 0u);
+    }
+    return it;
+}
+
+// One (query, posting) pair: round(fl(m' * w')) into the query's cell (users hold m' bits,
+// bucket entries w' bits).
+template <bool W64>
+__device__ __forceinline__ void pair_add(AccT<W64>* acc, uint2 ue, int o, int w) {
+    const float p = __uint_as_float(ue.y) * __uint_as_float((uint32_t)w);
+    if constexpr (W64)
+        atomicAdd(&acc[acc_idx((int)ue.x, o)], (unsigned long long)f32_to_i64_rn(p));
+    else
+        atomicAdd(&acc[acc_idx((int)ue.x, o)], (uint32_t)__float2int_rn(p));
+}
+
+template <bool W64>
+__device__ __forceinline__ void item_add(AccT<W64>* acc, const ItemLoad& it) {
+    #pragma unroll
+    for (int j = 0; j < kUserChunk; ++j)
+        if ((it.valid >> j) & 1u) pair_add<W64>(acc, it.ue[j], it.o, it.w);
+}
+
+// Items of steps [s_begin, end) of a set of entries.
+template <bool LU, bool W64>
+__device__ __forceinline__ void item_steps(const ScoreArgs& a, const EntryItems& t, uint32_t s_begin,
+                                           int* mark, AccT<W64>* acc, lds_uint2* lds_users) {
+    if (s_begin == 0 && __ballot(t.nch > 1u) == 0ull) {
+        item_add<W64>(acc, own_item_load<LU>(a, t, lds_users));
+        return;
+    }
+    int carry = carry_before(t, s_begin);
+    for (uint32_t s = s_begin; 64u * s < t.total; ++s) {
+        const int m = step_owner(t, s, mark, carry);
+        item_add<W64>(acc, item_load<LU>(a, t, s, m, lds_users));
     }
 }
 
-// The first kAheadSteps steps of a tile's round-0 entries, mapped and their users[] loads
-// issued one tile before the adds (the loads' latency then hides behind a whole tile).
-constexpr int kAheadSteps = 6;
-// (query, multiplier) pairs of one query group that are copied to LDS when they fit.
-constexpr int kUsersLds = 8192;
-struct PairsAhead {
-    uint2 ue[kAheadSteps];
-    int uo[kAheadSteps], uw[kAheadSteps];
+// The first step (64 items) of a tile's round-0 entries, mapped and their users loaded one
+// tile before the adds (the loads' latency then hides behind a whole tile).
+struct ItemsAhead {
+    ItemLoad it;
     uint32_t total;
 };
 
 template <bool LU>
-__device__ __forceinline__ PairsAhead pairs_ahead(const ScoreArgs& a, int g, uint2 e, bool valid,
+__device__ __forceinline__ ItemsAhead items_ahead(const ScoreArgs& a, int g, uint2 e, bool valid,
                                                   int* mark, lds_uint2* lds_users) {
-    const int lane = lane_id();
-    const EntryLanes t = entry_lanes(a, g, e, valid);
-    PairsAhead pa;
-    pa.total = t.total;
-    int carry = -1;
-    int m[kAheadSteps] = {};
-    static_assert(kMarkRows == 4 && kAheadSteps > kMarkRows && kAheadSteps <= 2 * kMarkRows,
-                  "two groups of steps");
-    // as many rows as the tile's pairs need (small batches have a few pairs per tile)
-    if (t.total > 128u) steps_entries<4>(t, 0, mark, carry, m);
-    else if (t.total > 64u) steps_entries<2>(t, 0, mark, carry, m);
-    else if (t.total > 0u) steps_entries<1>(t, 0, mark, carry, m);
-    if (t.total > 64u * kMarkRows) steps_entries<kAheadSteps - kMarkRows>(t, kMarkRows, mark, carry, m + kMarkRows);
-    #pragma unroll
-    for (int k = 0; k < kAheadSteps; ++k) {
-        pa.uo[k] = 0;
-        pa.uw[k] = 0;
-        pa.ue[k] = make_uint2(0u, 0u);
-        if (64u * k < t.total) {  // wave-uniform
-            const int ub = __shfl(t.base, m[k], 64);
-            pa.uo[k] = __shfl(t.o, m[k], 64);
-            pa.uw[k] = __shfl(t.w, m[k], 64);
-            const uint32_t p = 64u * k + (uint32_t)lane;
-            if (p < t.total) pa.ue[k] = user_at<LU>(a, lds_users, (uint32_t)ub + p);
-        }
+    const EntryItems t = entry_items(a, g, e, valid);
+    ItemsAhead ia;
+    ia.total = t.total;
+    if (__ballot(t.nch > 1u) == 0ull) {
+        ia.it = own_item_load<LU>(a, t, lds_users);
+        return ia;
     }
-    return pa;
+    int carry = -1;
+    const int m = t.total > 0u ? step_owner(t, 0, mark, carry) : -1;
+    ia.it = item_load<LU>(a, t, 0, m, lds_users);
+    return ia;
 }
 
 __device__ __forceinline__ uint2 prod_bounds(const ScoreArgs& a, uint32_t tile) {
@@ -249,41 +324,39 @@ __device__ __forceinline__ ProdTile prod_entries(const ScoreArgs& a, uint2 b, in
     ProdTile t;
     t.beg = b.x;
     t.end = b.y;
-    const uint32_t ei = t.beg + (uint32_t)pw + kProducerWaves * (uint32_t)lane_id();
+    const uint32_t ei = t.beg + (uint32_t)pw + kCrossWaves * (uint32_t)lane_id();
     t.e0 = ei < t.end ? reinterpret_cast<const uint2*>(a.bucket)[ei] : make_uint2(0u, 0u);
     return t;
 }
 
-// Cross term of one tile (this wave's share): the prefetched round-0 pairs, the rest of
-// round 0, then later rounds of entries.
-template <bool LU>
+// Cross term of one tile (this wave's share): the prefetched first step of round 0, the rest
+// of round 0, then later rounds of entries.
+template <bool LU, bool W64>
 __device__ __forceinline__ void prod_tile(const ScoreArgs& a, int g, int pw, const ProdTile& t,
-                                          const PairsAhead& pa, int* mark, uint32_t* acc,
+                                          const ItemsAhead& ia, int* mark, AccT<W64>* acc,
                                           lds_uint2* lds_users) {
     const int lane = lane_id();
     const uint2* bucket = reinterpret_cast<const uint2*>(a.bucket);
-    constexpr uint32_t kRound = kProducerWaves * 64u;
+    constexpr uint32_t kRound = kCrossWaves * 64u;
     const uint32_t first = t.beg + (uint32_t)pw;
     if (first >= t.end) return;
-    #pragma unroll
-    for (int k = 0; k < kAheadSteps; ++k)
-        if (64u * k + (uint32_t)lane < pa.total) pair_add(acc, pa.ue[k], pa.uo[k], pa.uw[k]);
-    if (pa.total > 64u * kAheadSteps)
-        cross_steps<LU>(a, entry_lanes(a, g, t.e0, first + kProducerWaves * (uint32_t)lane < t.end),
-                        kAheadSteps, mark, acc, lds_users);
+    item_add<W64>(acc, ia.it);
+    if (ia.total > 64u)
+        item_steps<LU, W64>(a, entry_items(a, g, t.e0, first + kCrossWaves * (uint32_t)lane < t.end), 1u,
+                       mark, acc, lds_users);
     for (uint32_t base = first + kRound; base < t.end; base += kRound) {
-        const uint32_t ei = base + kProducerWaves * (uint32_t)lane;
+        const uint32_t ei = base + kCrossWaves * (uint32_t)lane;
         const bool ok = ei < t.end;
         const uint2 e = ok ? bucket[ei] : make_uint2(0u, 0u);
-        cross_steps<LU>(a, entry_lanes(a, g, e, ok), 0, mark, acc, lds_users);
+        item_steps<LU, W64>(a, entry_items(a, g, e, ok), 0u, mark, acc, lds_users);
     }
 }
 
 template <bool LU>
-__device__ __forceinline__ PairsAhead prod_ahead(const ScoreArgs& a, int g, int pw, const ProdTile& t,
+__device__ __forceinline__ ItemsAhead prod_ahead(const ScoreArgs& a, int g, int pw, const ProdTile& t,
                                                  int* mark, lds_uint2* lds_users) {
     const uint32_t first = t.beg + (uint32_t)pw;
-    return pairs_ahead<LU>(a, g, t.e0, first + kProducerWaves * (uint32_t)lane_id() < t.end, mark, lds_users);
+    return items_ahead<LU>(a, g, t.e0, first + kCrossWaves * (uint32_t)lane_id() < t.end, mark, lds_users);
 }
 
 
@@ -315,7 +388,6 @@ __device__ __forceinline__ f32x4 fp8x8_to_bf16x8(uint2 v) {
 // per-ad scale applied to the finished dot product).
 template <int D, int DT> struct EmbStage {
     static constexpr int UNITS = DT == 0 ? (D / 8) * 64 : (D / 16) * 64;  // 16-byte LDS units
-    static constexpr int PER = (UNITS + 64 * kProducerWaves - 1) / (64 * kProducerWaves);
 };
 
 // One work-group per (query group, contiguous range of tiles), persistent over its range;
@@ -326,24 +398,25 @@ template <int D, int DT> struct EmbStage {
 // Work-group ids are laid out for the 8 XCDs of the chip (consecutive ids go to consecutive
 // XCDs): all query groups of one tile range run on the same XCD, so the range's embedding
 // blocks and bucket entries are fetched from HBM once and then served by that XCD's L2.
-template <int D, int MODE, int DT>
-__global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
+template <int D, int MODE, int DT, bool W64>
+__global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs a) {
     constexpr int NQ = D / 8;
-    constexpr int GQ = ScoreShape<D>::GQ;
-    constexpr int CW = ScoreShape<D>::CW;
-    constexpr int NT = ScoreShape<D>::NT;
-    constexpr int kProdThreads = 64 * kProducerWaves;
+    using Acc = AccT<W64>;
+    constexpr int GQ = ScoreShape<D, W64>::GQ;
+    constexpr int CW = ScoreShape<D, W64>::CW;
+    constexpr int NT = ScoreShape<D, W64>::NT;
+    constexpr int kUsersLds = ScoreShape<D, W64>::USERS_LDS;
     constexpr int UNITS = EmbStage<D, DT>::UNITS;
-    constexpr int PER = EmbStage<D, DT>::PER;
-    __shared__ __attribute__((aligned(16))) uint32_t s_acc[2][GQ * kTileAds];
+    constexpr int SPER = (UNITS + kStageThreads - 1) / kStageThreads;  // units per stager lane
+    __shared__ __attribute__((aligned(16))) Acc s_acc[2][GQ * kTileAds];
     __shared__ f32x4 s_emb[2][NQ * 64];
-    __shared__ float s_escale[2][kTileAds];
+    __shared__ __attribute__((aligned(16))) float s_escale[2][kTileAds];
     __shared__ __attribute__((aligned(16))) float s_qscale[GQ];
     __shared__ __attribute__((aligned(16))) float s_thr[GQ];
     __shared__ uint32_t s_thr_hi[GQ];
     __shared__ uint32_t s_thr_lo[GQ];
     __shared__ uint32_t s_live[GQ];
-    __shared__ int s_mark[kProducerWaves][kMarkRows * 64];
+    __shared__ int s_mark[kCrossWaves][64];
     __shared__ uint2 s_users[kUsersLds];
 
     const int tid = (int)threadIdx.x, lane = lane_id(), wave = tid >> 6;
@@ -368,7 +441,7 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     const int n_it = (int)(((int64_t)a.n_work * (range + 1)) / a.n_ranges) - first;
     if (n_it <= 0) return;
 
-    for (int i = tid; i < 2 * GQ * kTileAds; i += NT) (&s_acc[0][0])[i] = 0u;
+    for (int i = tid; i < 2 * GQ * kTileAds; i += NT) (&s_acc[0][0])[i] = 0;
     // one query group: its (query, multiplier) users fit in LDS when few enough
     const bool users_in_lds = a.packed && a.n_users <= (uint32_t)kUsersLds;
     lds_uint2* lu = (lds_uint2*)s_users;
@@ -399,63 +472,81 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     __syncthreads();
 
     if (producer) {
-        // the producer is instantiated for users in LDS and in global memory (uniform choice)
-        auto produce = [&](auto lds_tag) {
-            constexpr bool LU = decltype(lds_tag)::value;
-            const int pw = wave - CW;
-            const int ptid = tid - 64 * CW;
-            // pipeline: bucket bounds two tiles ahead, round-0 entries one tile ahead, the
-            // embedding block in registers two tiles ahead (written to LDS one tile ahead)
+        const int pw = wave - CW;
+        if (pw < kStageWaves) {
+            // Stager wave: the embedding block (and FP8 row scales) of tile u is loaded into
+            // registers two iterations before the consumers read it and written to LDS one
+            // iteration before; two register sets, for odd and even u. This wave issues no
+            // other global loads, so each wait covers exactly the block it needs.
+            const int sl = pw * 64 + lane;
             struct Raw {
-                f32x4 u[PER];    // FP32 / BF16 units
-                uint2 c[PER];    // FP8 codes
-                float scale;     // FP8: the scale of ad (ptid) of the tile
+                f32x4 u[SPER];   // FP32 / BF16 units
+                uint2 c[SPER];   // FP8 codes
+                float scale;     // FP8: the scale of ad sl of the tile
             };
             auto emb_load = [&](uint32_t t, Raw& r) {
                 #pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int j = ptid + k * kProdThreads;
+                for (int k = 0; k < SPER; ++k) {
+                    const int j = sl + k * kStageThreads;
                     if (j < UNITS) {
                         if (DT == 2) r.c[k] = reinterpret_cast<const uint2*>(a.emb)[(int64_t)t * UNITS + j];
                         else r.u[k] = reinterpret_cast<const f32x4*>(a.emb)[(int64_t)t * UNITS + j];
                     }
                 }
-                if (DT == 2 && ptid < kTileAds) r.scale = a.fp8_scale[(int64_t)t * kTileAds + ptid];
+                if (DT == 2 && sl < kTileAds) r.scale = a.fp8_scale[(int64_t)t * kTileAds + sl];
             };
             auto emb_store = [&](int buf, const Raw& r) {
                 #pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int j = ptid + k * kProdThreads;
-                    if (UNITS % kProdThreads == 0 || j < UNITS)
+                for (int k = 0; k < SPER; ++k) {
+                    const int j = sl + k * kStageThreads;
+                    if (UNITS % kStageThreads == 0 || j < UNITS)
                         s_emb[buf][j] = DT == 2 ? fp8x8_to_bf16x8(r.c[k]) : r.u[k];
                 }
-                if (DT == 2 && ptid < kTileAds) s_escale[buf][ptid] = r.scale;
+                if (DT == 2 && sl < kTileAds) s_escale[buf][sl] = r.scale;
             };
-            const uint32_t t0 = tile_at(0);
-            {
-                Raw e0;
-                emb_load(t0, e0);
-                emb_store(0, e0);
-                const ProdTile p0 = prod_entries(a, prod_bounds(a, t0), pw);
-                prod_tile<LU>(a, g, pw, p0, prod_ahead<LU>(a, g, pw, p0, s_mark[pw], lu), s_mark[pw], s_acc[0], lu);
+            Raw ro, re;
+            emb_load(tile_at(0), ro);
+            emb_store(0, ro);
+            if (1 < n_it) emb_load(tile_at(1), ro);
+            if (2 < n_it) emb_load(tile_at(2), re);
+            __syncthreads();
+            auto step = [&](int u, Raw& r) {
+                emb_store(u & 1, r);
+                if (u + 2 < n_it) emb_load(tile_at(u + 2), r);
+                __syncthreads();
+            };
+            for (int u = 1; u < n_it; u += 2) {
+                step(u, ro);
+                if (u + 1 < n_it) step(u + 1, re);
             }
-            // Tiles u = 1 .. n_it - 1 are filled in iteration u - 1. Every load is issued two
-            // iterations before its first use, so the state is kept in two sets, for odd and even
-            // u. Before the step for tile u its set holds: the embedding block of u (loaded), the
-            // first pairs of u (loaded), the entries of u and of u + 2, the bounds of u + 4.
+            __syncthreads();  // the consumers' last iteration
+            return;
+        }
+        // Cross-term waves (instantiated for users in LDS and in global memory, a uniform
+        // choice): bucket bounds four tiles ahead, entries two tiles ahead, the first step of
+        // items (mapped, users loaded) one tile ahead.
+        const int xw = pw - kStageWaves;
+        auto cross = [&](auto lds_tag) {
+            constexpr bool LU = decltype(lds_tag)::value;
+            int* mark = s_mark[xw];
+            {
+                const ProdTile p0 = prod_entries(a, prod_bounds(a, tile_at(0)), xw);
+                prod_tile<LU, W64>(a, g, xw, p0, prod_ahead<LU>(a, g, xw, p0, mark, lu), mark, s_acc[0], lu);
+            }
+            // Tiles u = 1 .. n_it - 1 are filled in iteration u - 1, with the state kept in two
+            // sets (odd and even u). Before the step for tile u its set holds: the first items
+            // of u (mapped, loaded), the entries of u and of u + 2, the bounds of u + 4.
             struct Set {
-                Raw e;
-                PairsAhead pa;
+                ItemsAhead pa;
                 ProdTile pc, pn;
                 uint2 bn;
             };
             Set so{}, se{};
-            auto entries_of = [&](int u) { return prod_entries(a, prod_bounds(a, tile_at(u)), pw); };
+            auto entries_of = [&](int u) { return prod_entries(a, prod_bounds(a, tile_at(u)), xw); };
             auto fill = [&](Set& st, int u) {  // prologue: the state before the step for tile u
                 if (u >= n_it) return;
-                emb_load(tile_at(u), st.e);
                 st.pc = entries_of(u);
-                st.pa = prod_ahead<LU>(a, g, pw, st.pc, s_mark[pw], lu);
+                st.pa = prod_ahead<LU>(a, g, xw, st.pc, mark, lu);
                 if (u + 2 < n_it) st.pn = entries_of(u + 2);
                 if (u + 4 < n_it) st.bn = prod_bounds(a, tile_at(u + 4));
             };
@@ -464,14 +555,12 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             __syncthreads();
             auto step = [&](int u, Set& st) {
                 const int nb = u & 1;  // buffer of tile u (the consumers read it in iteration u)
-                emb_store(nb, st.e);
-                if (u + 2 < n_it) emb_load(tile_at(u + 2), st.e);
-                prod_tile<LU>(a, g, pw, st.pc, st.pa, s_mark[pw], s_acc[nb], lu);
+                prod_tile<LU, W64>(a, g, xw, st.pc, st.pa, mark, s_acc[nb], lu);
                 if (u + 2 < n_it) {
-                    st.pa = prod_ahead<LU>(a, g, pw, st.pn, s_mark[pw], lu);
+                    st.pa = prod_ahead<LU>(a, g, xw, st.pn, mark, lu);
                     st.pc = st.pn;
                 }
-                if (u + 4 < n_it) st.pn = prod_entries(a, st.bn, pw);
+                if (u + 4 < n_it) st.pn = prod_entries(a, st.bn, xw);
                 if (u + 6 < n_it) st.bn = prod_bounds(a, tile_at(u + 6));
                 __syncthreads();
             };
@@ -481,8 +570,8 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             }
             __syncthreads();  // the consumers' last iteration
         };
-        if (users_in_lds) produce(std::true_type{});
-        else produce(std::false_type{});
+        if (users_in_lds) cross(std::true_type{});
+        else cross(std::false_type{});
         return;
     }
 
@@ -502,10 +591,10 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
 #pragma unroll
         for (int d = 0; d < D; ++d) us[d] = qok ? a.user[(int64_t)q * D + d] : 0.0f;
         __syncthreads();
-        for (int it = 0; it < n_it; ++it) {
+        auto iter = [&](int it) {
             if (wave_on) {
                 const int cur = it & 1;
-                uint32_t* acc = s_acc[cur];
+                Acc* acc = s_acc[cur];
                 const f32x4* eb = s_emb[cur];
                 float deep = 0.0f;
 #pragma unroll
@@ -519,10 +608,10 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
                     }
                 }
                 const int cell = acc_idx(row, o);
-                const uint32_t wv = acc[cell];
-                acc[cell] = 0u;
+                const float wv = acc_value(acc[cell]);
+                acc[cell] = 0;
                 const float sq = s_qscale[row];
-                const float sc = fmaf((float)(int)wv, sq, deep);
+                const float sc = fmaf(wv, sq, deep);
                 const int64_t ad = (int64_t)tile_at(it) * kTileAds + o;
                 const bool ad_ok = ad < a.n_ads;
                 if (MODE == 1) {
@@ -536,12 +625,13 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
                         const uint32_t key = score_key(sc);
                         if (key > s_thr_hi[row] || (key == s_thr_hi[row] && idk >= s_thr_lo[row]))
                             append_candidate(a.cand, a.cand_cnt, a.cand_wide, a.cap, q, key, idk,
-                                             (float)(int)wv * sq);
+                                             wv * sq);
                     }
                 }
             }
             __syncthreads();
-        }
+        };
+        for (int it = 0; it < n_it; ++it) iter(it);
         return;
     }
 
@@ -586,20 +676,19 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
     // this lane's rows: group g4 (0..3) holds rows rg(g4) .. rg(g4) + 3 of the group's 256
     auto rg = [&](int g4) { return wave * 32 + 8 * g4 + 4 * (lane >> 5); };
     const int o = lane & 31;
-    for (int it = 0; it < n_it; ++it) {
+    auto iter = [&](int it) {
         const int cur = it & 1;
-        uint32_t* acc = s_acc[cur];
+        Acc* acc = s_acc[cur];
         if (!wave_live) {
             // rows of queries in the batch but inactive in this round still receive cross
             // terms: keep the buffer clear for its next use. Rows past the batch are never
             // written (the buffers start cleared), so their waves only keep the barrier count.
             if (q0 < B) {
                 #pragma unroll
-                for (int g4 = 0; g4 < 4; ++g4)
-                    *reinterpret_cast<uint4*>(acc + acc_idx(rg(g4), o)) = make_uint4(0u, 0u, 0u, 0u);
+                for (int g4 = 0; g4 < 4; ++g4) clear4(acc + acc_idx(rg(g4), o));
             }
             __syncthreads();
-            continue;
+            return;
         }
         // products first: the tile's B operands are read from LDS up to eight quads ahead of
         // the products that use them, so one LDS latency is exposed per tile
@@ -629,27 +718,21 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
         }
         // then the cross term of this lane's 16 cells: read (all reads in flight together),
         // cleared for the buffer's next use, converted to FP32
-        float wd[16];
+        float wd[16];  // the row's scale is applied below
         {
-            uint4 av[4];
+            Acc av[16];
             #pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) av[g4] = *reinterpret_cast<const uint4*>(acc + acc_idx(rg(g4), o));
+            for (int g4 = 0; g4 < 4; ++g4) read4(acc + acc_idx(rg(g4), o), av + 4 * g4);
             #pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4)
-                *reinterpret_cast<uint4*>(acc + acc_idx(rg(g4), o)) = make_uint4(0u, 0u, 0u, 0u);
+            for (int g4 = 0; g4 < 4; ++g4) clear4(acc + acc_idx(rg(g4), o));
             #pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-                wd[4 * g4] = (float)(int)av[g4].x;  // the row's scale is applied below
-                wd[4 * g4 + 1] = (float)(int)av[g4].y;
-                wd[4 * g4 + 2] = (float)(int)av[g4].z;
-                wd[4 * g4 + 3] = (float)(int)av[g4].w;
-            }
+            for (int r = 0; r < 16; ++r) wd[r] = acc_value(av[r]);
         }
         const float escale = DT == 2 ? s_escale[cur][o] : 1.0f;
         const int64_t ad = (int64_t)tile * kTileAds + o;
         const bool ad_ok = ad < a.n_ads;
         float sc[16];
-        bool pass = false;
+        uint64_t pass = 0;  // lanes with a cell at or above its row's threshold
         // sample pass: row base of this wave's block plus a 32-bit offset per row
         uint32_t* skeys = MODE == 1 ? a.sample_keys + (int64_t)q0 * a.sample_ld : nullptr;
         const uint32_t scol = (uint32_t)(first + it) * kTileAds + (uint32_t)o;
@@ -674,13 +757,13 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
                         skeys[(uint32_t)rl * (uint32_t)a.sample_ld + scol] = ad_ok ? score_key(fmaf(wd[4 * g4 + k], sq[k], deep)) : 0u;
                 } else {
                     sc[4 * g4 + k] = fmaf(wd[4 * g4 + k], sq[k], deep);
-                    pass |= sc[4 * g4 + k] >= th[k];  // NaN threshold: never
+                    pass |= __ballot(sc[4 * g4 + k] >= th[k]);  // NaN threshold: never
                 }
             }
         }
-        if (MODE == 0 && __ballot(pass && ad_ok) != 0ull) {
+        if (MODE == 0 && (pass & __ballot(ad_ok)) != 0ull) {
             // rare: exact (key, id) comparison against the threshold, then append
-            if (pass && ad_ok) {
+            if (ad_ok) {
                 const uint32_t idk = 0xffffffffu - (uint32_t)ad;
                 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
@@ -695,7 +778,8 @@ __global__ __launch_bounds__(ScoreShape<D>::NT, 1) void k_score(ScoreArgs a) {
             }
         }
         __syncthreads();
-    }
+    };
+    for (int it = 0; it < n_it; ++it) iter(it);
 }
 
 // Exact FP32 rescore of the Kc approximate-best candidates of query q (one work-group): each
@@ -779,23 +863,34 @@ __global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
         if (!cert) {
             a.status[q] = kStatusUncertified;
             atomicAdd(a.uncertified, 1u);
+        } else if (a.werr && !wide_precise(a.werr[q], key_score((uint32_t)(s[0] >> 32)),
+                                           key_score((uint32_t)(s[K - 1] >> 32)))) {
+            a.status[q] = kStatusImprecise;
+            atomicAdd(a.imprecise, 1u);
         }
     }
 }
 
-template <int D, int DT>
+template <int D, int DT, bool W64>
 static void launch_score_dt(const ScoreArgs& a, int mode, dim3 grid, hipStream_t st) {
-    constexpr int NT = ScoreShape<D>::NT;
-    if (mode == 0) hipLaunchKernelGGL((k_score<D, 0, DT>), grid, dim3(NT), 0, st, a);
-    else if (mode == 1) hipLaunchKernelGGL((k_score<D, 1, DT>), grid, dim3(NT), 0, st, a);
-    else hipLaunchKernelGGL((k_score<D, 2, DT>), grid, dim3(NT), 0, st, a);
+    constexpr int NT = ScoreShape<D, W64>::NT;
+    if (mode == 0) hipLaunchKernelGGL((k_score<D, 0, DT, W64>), grid, dim3(NT), 0, st, a);
+    else if (mode == 1) hipLaunchKernelGGL((k_score<D, 1, DT, W64>), grid, dim3(NT), 0, st, a);
+    else hipLaunchKernelGGL((k_score<D, 2, DT, W64>), grid, dim3(NT), 0, st, a);
 }
 
+// 64-bit cells only for FP32 scans (the rerun of queries whose 32-bit quantum is too coarse,
+// and callers that ask for them).
 template <int D>
 void launch_score_d(const ScoreArgs& a, int mode, int dt, dim3 grid, hipStream_t st) {
-    if (dt == 0) launch_score_dt<D, 0>(a, mode, grid, st);
-    else if (dt == 1) launch_score_dt<D, 1>(a, mode, grid, st);
-    else launch_score_dt<D, 2>(a, mode, grid, st);
+    if (dt == 0) {
+        if (a.wide64) launch_score_dt<D, 0, true>(a, mode, grid, st);
+        else launch_score_dt<D, 0, false>(a, mode, grid, st);
+    } else if (dt == 1) {
+        launch_score_dt<D, 1, false>(a, mode, grid, st);
+    } else {
+        launch_score_dt<D, 2, false>(a, mode, grid, st);
+    }
 }
 
 template <int D>

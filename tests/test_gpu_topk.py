@@ -227,6 +227,22 @@ def test_topk_k_edge_cases():
     assert offs[-1] == 0
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_topk_k_beyond_the_lds_sort(dtype):
+    # K above 8192 (or rescore_factor x K above it) is answered by a full sort of the query's
+    # scores; K = N returns every ad. Scores near zero make the tolerance condition-relative.
+    wl = small_wl(n_ads=50_021, n_queries=6, k=1)
+    wl.k = np.array([50_021, 8193, 20_000, 100, 0, 12_345], np.int32)
+    ix = E.Index.from_workload(wl, dtypes=1 | (1 << E.BF16))
+    sd = E.F32 if dtype == "f32" else E.BF16
+    ids, sc, offs = run(ix, wl, scan_dtype=sd)
+    check_all(wl, ids, sc, offs, cond=True, label=f"large K {dtype}")
+    # the full-sort queries give the same result alone and in the batch
+    i1, s1, _ = run(ix, wl.subset([2]), scan_dtype=sd)
+    assert np.array_equal(i1, ids[offs[2]:offs[3]])
+    assert np.array_equal(s1.view(np.uint32), sc[offs[2]:offs[3]].view(np.uint32))
+
+
 def test_topk_exact_ties_integer_counts():
     # u = 0 and unit weights: every score is an integer hit count, exact in FP32; massive ties
     # are broken by the smaller ad id, so the result must equal the oracle's exactly.
