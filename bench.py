@@ -86,7 +86,7 @@ def check_outputs(wl, leg, ids, sc, offs, label):
         a, b = int(offs[q]), int(offs[q + 1])
 
         def full(q=q):
-            d, w, _ = oracle.scores(leg["index"], wl.user_emb[q], wl.query_keys(q))
+            d, w, _ = oracle.scores(leg["index"], wl.user_emb[q], wl.query_keys(q), wl.query_mults(q))
             return d + w
         try:
             rec.append(check_topk_vs_oracle(ids[a:b], sc[a:b], int(wl.k[q]), o_ids, o_sc, full,
@@ -158,10 +158,14 @@ def main():
                     help="skip the autotuner (default launch shapes)")
     ap.add_argument("--batch-steps", type=int, default=5,
                     help="timed batches of the 4096-query uneven batch (0: skip)")
-    ap.add_argument("--leg", choices=("f32", "bf16", "fp8", "uneven", "b1", "b16"),
+    ap.add_argument("--binary-steps", type=int, default=5,
+                    help="timed batches of the same queries on an ids-only copy of the index "
+                         "(the paper's binary L, multipliers w x per feature; 0: skip)")
+    ap.add_argument("--leg", choices=("f32", "bf16", "fp8", "uneven", "b1", "b16", "binary"),
                     help="profiling run: only this batch kind on the 10M-ad index (the 256-query "
                          "batch on FP32 / BF16 / FP8, the 4096-query uneven batch on BF16, or the "
-                         "first 1 / 16 queries on FP32), --warmup + --steps batches with "
+                         "first 1 / 16 queries on FP32, or the 256-query batch on an ids-only "
+                         "index), --warmup + --steps batches with "
                          "per-phase times, default launch shapes; prints one JSON line of times")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -334,6 +338,47 @@ def main():
                 "mean_abs": float(err.mean()), "max_rel_to_c": float(rel.max()), "mean_rel_to_c": float(rel.mean())}
             del deep
 
+    # the paper's binary L: the same lists stored as ids only (no weights), each query
+    # feature with its multiplier w x; FP32 scan, checked against the oracle on a few queries
+    binary = None
+    if args.binary_steps > 0:
+        wbin = W.binary(wl)
+        t1 = time.time()
+        ixb = E.Index.from_workload(wbin, device=dev)
+        sb = ixb.stats()
+        log(f"[bench] ids-only index built in {time.time() - t1:.1f}s: {sb['bytes_per_posting']:.2f} "
+            f"B/posting (weighted {st['bytes_per_posting']:.2f})")
+        for i in range(2):
+            ixb.score_topk(U, wbin.feat_offsets, wbin.feat_keys, wbin.k, wbin.feat_mult, out=out)
+        torch.cuda.synchronize()
+        tt = []
+        t1 = time.perf_counter()
+        for i in range(args.binary_steps):
+            ixb.score_topk(U, wbin.feat_offsets, wbin.feat_keys, wbin.k, wbin.feat_mult, out=out)
+            tt.append(E.last_timings())
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        ob = (out[0].cpu().numpy().view(np.uint32).copy(), out[1].cpu().numpy().copy())
+        qb = B * args.binary_steps / el
+        binary = {
+            "workload": "the same 256 queries and lists, lists stored as ids only (binary L), "
+                        "multipliers w x per feature, FP32 scan",
+            "queries_per_s": qb, "ms_per_batch": 1000 * el / args.binary_steps,
+            "bytes_per_posting": sb["bytes_per_posting"],
+            "weighted_bytes_per_posting": st["bytes_per_posting"],
+            "arena_bytes": sb["arena_bytes"], "weighted_arena_bytes": st["arena_bytes"],
+            "phases_ms": {k: float(np.mean([t[k] for t in tt]))
+                          for k in ("decode_ms", "sample_ms", "score_ms", "finalize_ms")},
+            "weighted_phases_ms": {k: phase[k] for k in ("decode_ms", "sample_ms", "score_ms", "finalize_ms")},
+        }
+        if args.cpu_seconds > 0:
+            bleg = oracle_leg(wbin, 1e9, max_queries=8)
+            binary["parity"] = check_outputs(wbin, bleg, ob[0], ob[1], out_offs, "binary")
+            del bleg
+        ixb.close()
+        log(f"[bench] binary L: {qb:.0f} queries/s, decode {binary['phases_ms']['decode_ms']:.3f} ms "
+            f"(weighted {phase['decode_ms']:.3f}), k_score {binary['phases_ms']['score_ms']:.3f} ms")
+
     # uneven batching: 4096 queries in one launch on the same index, F ~ U{4..128},
     # K ~ U{100..2000}, BF16 scan with 4 K rescored exactly
     batching = None
@@ -407,6 +452,8 @@ def main():
                          f"ads scored/s = {leg['queries'] / el * N:.3e}"}
         log(f"[bench] cpu oracle: {leg['queries']} queries in {el:.1f}s on {leg['threads']} threads")
         parity = {name: check_outputs(wl, leg, o[0], o[1], out_offs, name) for name, o in outputs.items()}
+        if binary is not None and "parity" in binary:
+            parity["binary_L"] = binary["parity"]
         parity["ok"] = all(v["failures"] == 0 for v in parity.values() if isinstance(v, dict))
         log(f"[bench] parity of the timed outputs vs the oracle: {parity}")
         del leg
@@ -444,6 +491,7 @@ def main():
         "parity": parity,
         "precision": precision,
         "batching": batching,
+        "binary_L": binary,
         "serving": serving,
     }
     print(json.dumps(res), flush=True)
@@ -455,12 +503,15 @@ def main():
 def leg_main(args, np, torch, W, E, dev):
     """One batch kind, --warmup + --steps times: the unit a rocprofv3 run profiles."""
     wl = W.make("c2")
-    ix = E.Index.from_workload(wl, device=dev, dtypes=1 | (1 << E.BF16) | (1 << E.FP8E4M3))
+    if args.leg == "binary":
+        wl = W.binary(wl)
+    ix = E.Index.from_workload(wl, device=dev, dtypes=1 if args.leg == "binary" else
+                               1 | (1 << E.BF16) | (1 << E.FP8E4M3))
     q = W.queries_for(wl, "c4") if args.leg == "uneven" else wl
     if args.leg in ("b1", "b16"):
         q = wl.subset(range(1 if args.leg == "b1" else 16))
     sd = {"f32": E.F32, "b1": E.F32, "b16": E.F32, "bf16": E.BF16, "fp8": E.FP8E4M3,
-          "uneven": E.BF16}[args.leg]
+          "uneven": E.BF16, "binary": E.F32}[args.leg]
     U = torch.from_numpy(np.ascontiguousarray(q.user_emb)).to(dev)
     nk = int(np.sum(q.k))
     out = (torch.empty(nk, dtype=torch.int32, device=dev), torch.empty(nk, dtype=torch.float32, device=dev))

@@ -69,8 +69,9 @@ typedef struct ebr_index ebr_index; /* opaque; immutable after build but for its
  *               postings [key_offsets[k], key_offsets[k+1]). Total < 2^32.
  *  post_ids     ad ids, strictly increasing within each key, < N (lists are
  *               sets, Algorithm 1 takes their union).
- *  post_w       FP32 cross weights per posting, or NULL for unit weights
- *               (the paper's binary L).
+ *  post_w       FP32 cross weights per posting, or NULL for unit weights: the paper's
+ *               binary L (Section 3.3, equation "hitmatch"; Algorithm 1 stores ids only),
+ *               an ids-only index that stores and streams no weights.
  *  dtypes       bitmask of (1u << ebr_dtype) scan copies to build; FP32 is
  *               always built (it is also the exact rescore source). BF16 is
  *               round-to-nearest-even; FP8 is OCP e4m3fn with one FP32 scale per

@@ -83,7 +83,9 @@ class Index:
 
     @classmethod
     def of(cls, wl):
-        return cls(wl.ad_emb, wl.key_offsets, wl.post_ids, wl.post_w)
+        # a binary L (ids only) is the weighted form with every weight 1 (Section 3.3)
+        w = wl.post_w if wl.post_w is not None else np.ones(len(wl.post_ids), np.float32)
+        return cls(wl.ad_emb, wl.key_offsets, wl.post_ids, w)
 
 
 def scores(ix: Index, u, keys, mult=None):

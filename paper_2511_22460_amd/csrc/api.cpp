@@ -187,7 +187,8 @@ static ebr_status measure(const ebr_build_desc* d, Measured* m) {
     p.bytes_emb_f32 = (size_t)n_blk * kTileAds * d->dim * 4;
     p.bytes_chunks = std::max<size_t>(16, (size_t)c * 16);
     p.bytes_words = (size_t)(w + 2) * 4;
-    p.bytes_weights = std::max<size_t>(4, (size_t)n_post * 4);
+    // an index without weights (the paper's binary L) stores ids only
+    p.bytes_weights = d->post_w ? std::max<size_t>(4, (size_t)n_post * 4) : 0;
     size_t off = 0;
     p.off_emb_f32 = off; off = align256(off + p.bytes_emb_f32);
     if (d->dtypes & (1u << EBR_BF16)) {
@@ -202,7 +203,8 @@ static ebr_status measure(const ebr_build_desc* d, Measured* m) {
     }
     p.off_chunks = off; off = align256(off + p.bytes_chunks);
     p.off_words = off; off = align256(off + p.bytes_words);
-    p.off_weights = off; off = align256(off + p.bytes_weights);
+    p.off_weights = off;
+    if (p.bytes_weights) off = align256(off + p.bytes_weights);
     p.total = off;
     return EBR_OK;
 }
@@ -306,8 +308,6 @@ ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t a
         }
         std::vector<float> emb(p.bytes_emb_f32 / 4);
         swizzle_f32(desc->ad_emb, desc->n_ads, desc->dim, emb.data());
-        std::vector<float> ones;
-        if (!desc->post_w) ones.assign((size_t)std::max<int64_t>(1, n_post), 1.0f);
         // reduced-precision copies and their error summaries
         const bool want_bf16 = desc->dtypes & (1u << EBR_BF16);
         const bool want_fp8 = desc->dtypes & (1u << EBR_FP8E4M3);
@@ -387,9 +387,9 @@ ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t a
         if (p.n_chunks > 0)
             HIP_TRY(hipMemcpyAsync(base + p.off_chunks, hdr.data(), (size_t)p.n_chunks * 16, hipMemcpyHostToDevice, stream));
         HIP_TRY(hipMemcpyAsync(base + p.off_words, words.data(), p.bytes_words, hipMemcpyHostToDevice, stream));
-        if (n_post > 0)
-            HIP_TRY(hipMemcpyAsync(base + p.off_weights, desc->post_w ? desc->post_w : ones.data(),
-                                   (size_t)n_post * 4, hipMemcpyHostToDevice, stream));
+        if (n_post > 0 && desc->post_w)
+            HIP_TRY(hipMemcpyAsync(base + p.off_weights, desc->post_w, (size_t)n_post * 4,
+                                   hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         const double up_ms = ms_since(t1);
 
@@ -411,7 +411,7 @@ ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t a
         ix->e_norm2 = e_norm2;
         ix->chunks = (const ChunkHdr*)(base + p.off_chunks);
         ix->words = (const uint32_t*)(base + p.off_words);
-        ix->weights = (const float*)(base + p.off_weights);
+        ix->weights = desc->post_w ? (const float*)(base + p.off_weights) : nullptr;  // null: W = 1
         ix->key_chunk_off = std::move(m.key_chunk_off);
         ix->key_post_off.assign(desc->key_offsets ? desc->key_offsets : nullptr,
                                 desc->key_offsets ? desc->key_offsets + V + 1 : nullptr);
@@ -443,7 +443,7 @@ ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t a
         s.max_err_fp8 = q_err2[1];
         s.bytes_chunk_headers = (uint64_t)p.n_chunks * 16;
         s.bytes_packed_ids = (uint64_t)p.n_words * 4;
-        s.bytes_weights = (uint64_t)n_post * 4;
+        s.bytes_weights = desc->post_w ? (uint64_t)n_post * 4 : 0;
         s.bits_per_id = n_post ? (double)(s.bytes_chunk_headers + s.bytes_packed_ids) * 8.0 / (double)n_post : 0.0;
         s.bytes_per_posting = n_post ? (double)(s.bytes_chunk_headers + s.bytes_packed_ids + s.bytes_weights) / (double)n_post : 0.0;
         s.encode_ms = enc_ms;

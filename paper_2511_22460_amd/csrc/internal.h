@@ -65,7 +65,7 @@ struct Index {
     double q_err2[2] = {0.0, 0.0}, q_norm2[2] = {0.0, 0.0}, e_norm2 = 0.0;
     const ChunkHdr* chunks = nullptr;
     const uint32_t* words = nullptr;
-    const float* weights = nullptr;
+    const float* weights = nullptr;  // null: an ids-only index (every weight 1)
     // host copies for planning
     std::vector<uint32_t> key_chunk_off;  // V + 1
     std::vector<int64_t> key_post_off;    // V + 1

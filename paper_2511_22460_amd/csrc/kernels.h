@@ -36,7 +36,7 @@ struct Control {
 struct DecodeArgs {
     const ChunkHdr* chunks;
     const uint32_t* words;
-    const float* weights;
+    const float* weights;             // null: an ids-only index (every weight 1)
     const uint32_t* uk_chunk_begin;   // per distinct key: its first chunk in the index
     const uint32_t* uk_chunk_prefix;  // n_ukeys + 1 prefix sums of chunk counts
     const int32_t* uk_wshift;         // per distinct key: Sw_k, weights enter sums as w * 2^Sw_k

@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
                     lo[i] = w[0];
                     hi[i] = w[1];
                 }
-                if (place && lane < count) wt[i] = a.weights[poff + (uint32_t)lane];
+                if (place && lane < count) wt[i] = a.weights ? a.weights[poff + (uint32_t)lane] : 1.0f;
             }
         }
         #pragma unroll

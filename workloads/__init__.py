@@ -97,7 +97,7 @@ class Workload:
     ad_emb: np.ndarray          # float32 [n_ads, dim], row-major
     key_offsets: np.ndarray     # int64 [n_keys + 1], CSR over postings
     post_ids: np.ndarray        # uint32, strictly increasing within a key
-    post_w: np.ndarray          # float32, same length
+    post_w: Optional[np.ndarray]  # float32, same length; None for a binary L (ids only)
     user_emb: np.ndarray        # float32 [B, dim]
     feat_offsets: np.ndarray    # int64 [B + 1]
     feat_keys: np.ndarray       # int32, distinct within a query
@@ -240,6 +240,22 @@ def queries_for(wl: Workload, name: str, **over) -> Workload:
     recipe.update({"queries": name, "query_seed": seed, **{k: spec[k] for k in ("n_queries", "feats", "k")}})
     return Workload(wl.name + "+" + name, wl.n_ads, wl.dim, wl.n_keys, wl.ad_emb, wl.key_offsets,
                     wl.post_ids, wl.post_w, U, offs, fk, None, kq, recipe)
+
+
+def binary(wl: Workload, seed_tag: int = 7) -> Workload:
+    """The same lists and queries in the paper's binary form (Section 3.3, equation
+    "hitmatch"): the lists carry ids only (post_w None, every weight 1) and each query
+    feature carries its multiplier w_hat = w x, a learned weight w ~ N(0, 0.1) times a user
+    statistic x ~ U(0.5, 2), drawn per (query, feature) from SeedSequence(seed + seed_tag)."""
+    seed = int(wl.recipe.get("query_seed", wl.recipe.get("seed", BASE_SEED))) + seed_tag
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    n = len(wl.feat_keys)
+    mult = (rng.normal(0.0, 0.1, n) * rng.uniform(0.5, 2.0, n)).astype(np.float32)
+    recipe = dict(wl.recipe)
+    recipe.update({"binary": True, "mult_seed": seed})
+    return Workload(wl.name + "+binary", wl.n_ads, wl.dim, wl.n_keys, wl.ad_emb, wl.key_offsets,
+                    wl.post_ids, None, wl.user_emb, wl.feat_offsets, wl.feat_keys, mult, wl.k,
+                    recipe)
 
 
 def make(name: str = "c1", **over) -> Workload:
