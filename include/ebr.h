@@ -218,6 +218,26 @@ ebr_status ebr_score_topk(const ebr_index* index, const ebr_batch* batch, void* 
 ebr_status ebr_score_dense(const ebr_index* index, const ebr_batch* batch, void* ws,
                            size_t ws_bytes, float* deep, float* wide, void* hip_stream);
 
+/* ------------------------------------------------------------------------ no allocation */
+
+/* Bytes of the device scratch behind ebr_score_topk_noalloc (256 MiB per GPU). */
+#define EBR_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/*
+ * For callers that cannot allocate device memory or hand over a workspace (work under HIP
+ * stream capture, serving loops and harnesses that forbid hipMalloc): ebr_score_topk with
+ * its workspace taken from a fixed array of EBR_NOALLOC_SCRATCH_BYTES bytes of device memory
+ * inside the library, one per GPU, which exists while the library is loaded (for the life of
+ * the process). Arguments as ebr_score_topk without the workspace; the results are identical
+ * to ebr_score_topk's. The call allocates nothing: a batch whose workspace
+ * (ebr_workspace_size) exceeds the array is refused with EBR_ENOMEM before any device work
+ * (ebr_score_topk then serves it). Every call on one GPU uses that GPU's array, which keeps
+ * the last call's contents (each call initialises what it reads): calls that overlap on one
+ * GPU, from several threads or streams, race on it and must be serialised by the caller.
+ */
+ebr_status ebr_score_topk_noalloc(const ebr_index* index, const ebr_batch* batch,
+                                  uint32_t* out_ids, float* out_scores, void* hip_stream);
+
 /* ------------------------------------------------------------------------ launch shapes */
 
 /*

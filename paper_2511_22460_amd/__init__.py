@@ -20,6 +20,8 @@ _lib = None
 EBR_OK, EBR_EINVAL, EBR_ENOMEM, EBR_EDEVICE, EBR_EAGAIN, EBR_ENOTFOUND, EBR_ESHUTDOWN, \
     EBR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 F32, BF16, FP8E4M3 = 0, 1, 2
+# device scratch of ebr_score_topk_noalloc (EBR_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 256 << 20
 _STATUS = {0: "EBR_OK", -1: "EBR_EINVAL", -2: "EBR_ENOMEM", -3: "EBR_EDEVICE", -4: "EBR_EAGAIN",
            -5: "EBR_ENOTFOUND", -6: "EBR_ESHUTDOWN", -7: "EBR_EUNSUPPORTED"}
 
@@ -31,7 +33,7 @@ EXPORTS = ("ebr_index_size", "ebr_build_index", "ebr_index_stats", "ebr_decode_k
            "ebr_quantize_fp8", "ebr_dequantize_fp8", "ebr_server_create", "ebr_submit",
            "ebr_poll", "ebr_server_stats", "ebr_server_reset_stats", "ebr_server_destroy",
            "ebr_autotune", "ebr_set_launch_shape", "ebr_get_launch_shape", "ebr_graph_create",
-           "ebr_score_topk_graph", "ebr_graph_stats", "ebr_graph_destroy")
+           "ebr_score_topk_graph", "ebr_graph_stats", "ebr_graph_destroy", "ebr_score_topk_noalloc")
 
 
 class EbrError(RuntimeError):
@@ -177,6 +179,7 @@ def load():
         "ebr_free_index": ([P], None),
         "ebr_workspace_size": ([P, P, ctypes.POINTER(sz)], st),
         "ebr_score_topk": ([P, P, P, sz, P, P, P], st),
+        "ebr_score_topk_noalloc": ([P, P, P, P, P], st),
         "ebr_score_dense": ([P, P, P, sz, P, P, P], st),
         "ebr_codec_size": ([P, i64, ctypes.POINTER(sz)], st),
         "ebr_codec_encode": ([P, i64, P, sz, ctypes.POINTER(sz)], st),
