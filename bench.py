@@ -158,6 +158,8 @@ def main():
                     help="skip the autotuner (default launch shapes)")
     ap.add_argument("--batch-steps", type=int, default=5,
                     help="timed batches of the 4096-query uneven batch (0: skip)")
+    ap.add_argument("--refresh-runs", type=int, default=2,
+                    help="device builds of the benchmark index (online refresh) to time (0: skip)")
     ap.add_argument("--binary-steps", type=int, default=5,
                     help="timed batches of the same queries on an ids-only copy of the index "
                          "(the paper's binary L, multipliers w x per feature; 0: skip)")
@@ -379,6 +381,38 @@ def main():
         log(f"[bench] binary L: {qb:.0f} queries/s, decode {binary['phases_ms']['decode_ms']:.3f} ms "
             f"(weighted {phase['decode_ms']:.3f}), k_score {binary['phases_ms']['score_ms']:.3f} ms")
 
+    # online refresh: the same index rebuilt on the GPU from lists and embeddings already in
+    # device memory (ebr_build_index_device), against the host build's encode + upload
+    refresh = None
+    if args.refresh_runs > 0:
+        t1 = time.perf_counter()
+        e_d = torch.from_numpy(np.ascontiguousarray(wl.ad_emb)).to(dev)
+        ko_d = torch.from_numpy(wl.key_offsets).to(dev)
+        ids_d = torch.from_numpy(wl.post_ids.view(np.int32)).to(dev)
+        w_d = torch.from_numpy(wl.post_w).to(dev)
+        torch.cuda.synchronize()
+        up = time.perf_counter() - t1
+        runs = []
+        for i in range(args.refresh_runs):
+            ixr, ms = E.Index.build_on_device(e_d, ko_d, ids_d, w_d, dtypes=dtypes)
+            runs.append(ms)
+            same = bool(torch.equal(ixr.arena[:st["arena_bytes"]], ix.arena[:st["arena_bytes"]]))
+            ixr.close()
+            del ixr
+        del e_d, ko_d, ids_d, w_d
+        torch.cuda.empty_cache()
+        refresh = {
+            "workload": "the benchmark index (lists, weights, FP32 rows and the scan copies) rebuilt "
+                        "on the GPU from device-resident inputs",
+            "device_build_ms": float(np.median(runs)), "runs": len(runs),
+            "identical_to_host_build": same,
+            "host_build_ms": st["encode_ms"] + st["upload_ms"], "host_encode_ms": st["encode_ms"],
+            "host_upload_ms": st["upload_ms"], "raw_inputs_upload_ms": 1000 * up,
+            "postings": wl.n_postings, "n_ads": N,
+        }
+        log(f"[bench] refresh: device build {refresh['device_build_ms']:.1f} ms (host build "
+            f"{refresh['host_build_ms']:.0f} ms), identical={same}")
+
     # uneven batching: 4096 queries in one launch on the same index, F ~ U{4..128},
     # K ~ U{100..2000}, BF16 scan with 4 K rescored exactly
     batching = None
@@ -492,6 +526,7 @@ def main():
         "precision": precision,
         "batching": batching,
         "binary_L": binary,
+        "refresh": refresh,
         "serving": serving,
     }
     print(json.dumps(res), flush=True)

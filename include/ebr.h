@@ -120,6 +120,32 @@ ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t a
 
 ebr_status ebr_index_stats(const ebr_index* index, ebr_index_info* out);
 
+/* ------------------------------------------------------------------------ online refresh */
+
+/*
+ * Device-side build, for refreshing the index online: the paper rebuilds its GPU inverted
+ * list whenever the feature-to-ad matrix is updated, every few minutes (Section 3.4), with a
+ * parallel build of the lists (Algorithm 1; its preprocessing time is in Table 2). These
+ * calls build the same index as ebr_build_index, arena byte for byte, with every step on the
+ * GPU: list validation, chunk shapes and bit packing, per-key weight scales, the FP32 copy in
+ * the matrix-core layout and the BF16 / FP8 copies. desc is as for ebr_build_index except
+ * that its arrays (key_offsets, post_ids, post_w, ad_emb) are DEVICE pointers; only the
+ * n_keys + 1 list offsets and a few counts travel to the host.
+ *
+ * scratch: device memory of ebr_device_build_scratch_size bytes (256-byte aligned), owned by
+ * the caller, free again when the call returns. ebr_device_index_size gives the arena size
+ * (as ebr_index_size does for host inputs); ebr_build_index_device fills dev_arena and
+ * returns the handle (free it with ebr_free_index). Both synchronise hip_stream. Invalid
+ * inputs (decreasing list offsets, ids not strictly increasing or >= n_ads, non-finite
+ * weights or embeddings) give EBR_EINVAL, found on the GPU; the arena is then unspecified.
+ */
+ebr_status ebr_device_build_scratch_size(int64_t n_keys, int64_t n_postings, size_t* bytes);
+ebr_status ebr_device_index_size(const ebr_build_desc* desc, void* scratch, size_t scratch_bytes,
+                                 void* hip_stream, size_t* arena_bytes);
+ebr_status ebr_build_index_device(const ebr_build_desc* desc, void* scratch, size_t scratch_bytes,
+                                  void* dev_arena, size_t arena_bytes, void* hip_stream,
+                                  ebr_index** out);
+
 /*
  * Test hook: decode key's list on the GPU from the compressed arena into the
  * device arrays ids / w of capacity cap; *len (host) receives the list length.
@@ -483,6 +509,18 @@ ebr_status ebr_poll(ebr_server* server, uint64_t ticket, int32_t timeout_us);
 
 ebr_status ebr_server_stats(ebr_server* server, ebr_server_info* out);
 ebr_status ebr_server_reset_stats(ebr_server* server);
+
+/*
+ * Online refresh of a serving loop (the paper refreshes the index while serving, Section
+ * 3.4): queries submitted after this call run on `next`; each query submitted before it runs
+ * on the index it was submitted to (a batch never mixes indexes). Returns once every query of
+ * the previous index has completed (its results are in the caller's buffers, polled or not),
+ * so the caller may then free that index and its arena; `next` must stay alive while the
+ * server uses it. next must have the same ads and width as the current index and hold the
+ * server's scan copy (EBR_EINVAL / EBR_EUNSUPPORTED otherwise); EBR_EAGAIN while another
+ * swap is waiting. Thread-safe with submit and poll; blocks the calling thread.
+ */
+ebr_status ebr_server_swap_index(ebr_server* server, const ebr_index* next);
 
 /*
  * Stop accepting queries, finish every queued and running one, release the

@@ -33,7 +33,9 @@ EXPORTS = ("ebr_index_size", "ebr_build_index", "ebr_index_stats", "ebr_decode_k
            "ebr_quantize_fp8", "ebr_dequantize_fp8", "ebr_server_create", "ebr_submit",
            "ebr_poll", "ebr_server_stats", "ebr_server_reset_stats", "ebr_server_destroy",
            "ebr_autotune", "ebr_set_launch_shape", "ebr_get_launch_shape", "ebr_graph_create",
-           "ebr_score_topk_graph", "ebr_graph_stats", "ebr_graph_destroy", "ebr_score_topk_noalloc")
+           "ebr_score_topk_graph", "ebr_graph_stats", "ebr_graph_destroy", "ebr_score_topk_noalloc",
+           "ebr_device_build_scratch_size", "ebr_device_index_size", "ebr_build_index_device",
+           "ebr_server_swap_index")
 
 
 class EbrError(RuntimeError):
@@ -180,6 +182,10 @@ def load():
         "ebr_workspace_size": ([P, P, ctypes.POINTER(sz)], st),
         "ebr_score_topk": ([P, P, P, sz, P, P, P], st),
         "ebr_score_topk_noalloc": ([P, P, P, P, P], st),
+        "ebr_device_build_scratch_size": ([i64, i64, ctypes.POINTER(sz)], st),
+        "ebr_device_index_size": ([P, P, sz, P, ctypes.POINTER(sz)], st),
+        "ebr_build_index_device": ([P, P, sz, P, sz, P, ctypes.POINTER(P)], st),
+        "ebr_server_swap_index": ([P, P], st),
         "ebr_score_dense": ([P, P, P, sz, P, P, P], st),
         "ebr_codec_size": ([P, i64, ctypes.POINTER(sz)], st),
         "ebr_codec_encode": ([P, i64, P, sz, ctypes.POINTER(sz)], st),
@@ -311,7 +317,8 @@ class Index:
         desc, keep = _desc(ad_emb, key_offsets, post_ids, post_w, dtypes)
         n = ctypes.c_size_t()
         _check(load().ebr_index_size(ctypes.byref(desc), ctypes.byref(n)), "ebr_index_size")
-        self.arena = torch.empty(max(256, n.value), dtype=torch.uint8, device=self.device)
+        # zeroed: the alignment gaps between sections are then deterministic too
+        self.arena = torch.zeros(max(256, n.value), dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
         _check(load().ebr_build_index(ctypes.byref(desc), self.arena.data_ptr(), self.arena.numel(),
                                       _stream(stream), ctypes.byref(h)), "ebr_build_index")
@@ -323,6 +330,45 @@ class Index:
     @classmethod
     def from_workload(cls, wl, **kw):
         return cls(wl.ad_emb, wl.key_offsets, wl.post_ids, wl.post_w, **kw)
+
+    @classmethod
+    def build_on_device(cls, ad_emb, key_offsets, post_ids, post_w=None, dtypes: int = 1, stream=None):
+        """The same index built on the GPU (ebr_build_index_device) from device tensors:
+        ad_emb float32 [N, d], key_offsets int64 [V + 1], post_ids int32/uint32 bits, post_w
+        float32 or None. Returns (index, device milliseconds of the size and build calls)."""
+        import time
+        import torch
+        lib = load()
+        dev = ad_emb.device
+        for t in (ad_emb, key_offsets, post_ids) + ((post_w,) if post_w is not None else ()):
+            if t.device != dev or not t.is_contiguous():
+                raise ValueError("device build inputs: contiguous tensors on one device")
+        V = key_offsets.numel() - 1
+        desc = BuildDesc(ad_emb.shape[0], ad_emb.shape[1], ad_emb.data_ptr(), V, key_offsets.data_ptr(),
+                         post_ids.data_ptr() if post_ids.numel() else None,
+                         post_w.data_ptr() if post_w is not None and post_w.numel() else None, dtypes)
+        sb = ctypes.c_size_t()
+        _check(lib.ebr_device_build_scratch_size(V, post_ids.numel(), ctypes.byref(sb)),
+               "ebr_device_build_scratch_size")
+        scratch = torch.empty(max(256, sb.value), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        n = ctypes.c_size_t()
+        _check(lib.ebr_device_index_size(ctypes.byref(desc), scratch.data_ptr(), scratch.numel(), _stream(stream),
+                                         ctypes.byref(n)), "ebr_device_index_size")
+        self = cls.__new__(cls)
+        self.device = dev
+        self.arena = torch.zeros(max(256, n.value), dtype=torch.uint8, device=dev)
+        h = ctypes.c_void_p()
+        _check(lib.ebr_build_index_device(ctypes.byref(desc), scratch.data_ptr(), scratch.numel(),
+                                          self.arena.data_ptr(), self.arena.numel(), _stream(stream),
+                                          ctypes.byref(h)), "ebr_build_index_device")
+        ms = 1000.0 * (time.perf_counter() - t0)
+        self._h = h
+        self.n_ads, self.dim = int(ad_emb.shape[0]), int(ad_emb.shape[1])
+        self.n_keys = V
+        self._ws = None
+        return self, ms
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -593,6 +639,12 @@ class Server:
         ids, sc, k = self._pending.pop(ticket, (None, None, 0))
         _check(rc, "ebr_poll")
         return ids[:k], sc[:k]
+
+    def swap_index(self, index: "Index"):
+        """Online refresh: later submissions run on `index`; returns once every query of the
+        previous index has completed (the previous Index may then be freed)."""
+        _check(load().ebr_server_swap_index(self._h, index._h), "ebr_server_swap_index")
+        self.index = index
 
     def stats(self) -> dict:
         st = ServerStats()

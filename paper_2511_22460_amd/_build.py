@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libebr.so")
 OBJ = os.path.join(PKG, "_build")
 WIDTHS = (16, 32, 48, 64, 80, 96, 112, 128)
-SOURCES = ["api.cpp", "codec.cpp", "quant.cpp", "server.cpp", "kernels.hip", "noalloc.hip"] + \
+SOURCES = ["api.cpp", "codec.cpp", "quant.cpp", "server.cpp", "kernels.hip", "noalloc.hip", "build.hip"] + \
           [f"score_d{d}.hip" for d in WIDTHS]
 ARCH = "gfx950"
 

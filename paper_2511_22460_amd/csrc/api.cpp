@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "build.h"
 #include "kernels.h"
 
 namespace ebr {
@@ -43,6 +44,15 @@ const char* last_error() { return g_err.c_str(); }
             set_error("%s failed: %s", #expr, hipGetErrorString(e_));              \
             return EBR_EDEVICE;                                                    \
         }                                                                          \
+    } while (0)
+
+#define LAUNCH(expr)                                                                       \
+    do {                                                                                   \
+        int rc_ = (expr);                                                                  \
+        if (rc_) {                                                                         \
+            set_error("%s failed: %s", #expr, hipGetErrorString((hipError_t)rc_));         \
+            return EBR_EDEVICE;                                                            \
+        }                                                                                  \
     } while (0)
 
 // ------------------------------------------------------------------ phase timing
@@ -179,24 +189,30 @@ static ebr_status measure(const ebr_build_desc* d, Measured* m) {
     }
     m->key_chunk_off[V] = (uint32_t)c;
     m->key_word_off[V] = w;
-    ArenaPlan& p = m->plan;
-    const int64_t n_blk = (d->n_ads + kTileAds - 1) / kTileAds;
     const int64_t n_post = V > 0 ? d->key_offsets[V] : 0;
-    p.n_chunks = (int64_t)c;
-    p.n_words = (int64_t)w;
-    p.bytes_emb_f32 = (size_t)n_blk * kTileAds * d->dim * 4;
-    p.bytes_chunks = std::max<size_t>(16, (size_t)c * 16);
-    p.bytes_words = (size_t)(w + 2) * 4;
+    m->plan = arena_plan(d->n_ads, d->dim, d->dtypes, n_post, (int64_t)c, (int64_t)w, d->post_w != nullptr);
+    return EBR_OK;
+}
+
+ArenaPlan arena_plan(int64_t n_ads, int32_t dim, uint32_t dtypes, int64_t n_post, int64_t n_chunks,
+                     int64_t n_words, bool weights) {
+    ArenaPlan p;
+    const int64_t n_blk = (n_ads + kTileAds - 1) / kTileAds;
+    p.n_chunks = n_chunks;
+    p.n_words = n_words;
+    p.bytes_emb_f32 = (size_t)n_blk * kTileAds * dim * 4;
+    p.bytes_chunks = std::max<size_t>(16, (size_t)n_chunks * 16);
+    p.bytes_words = (size_t)(n_words + 2) * 4;
     // an index without weights (the paper's binary L) stores ids only
-    p.bytes_weights = d->post_w ? std::max<size_t>(4, (size_t)n_post * 4) : 0;
+    p.bytes_weights = weights ? std::max<size_t>(4, (size_t)n_post * 4) : 0;
     size_t off = 0;
     p.off_emb_f32 = off; off = align256(off + p.bytes_emb_f32);
-    if (d->dtypes & (1u << EBR_BF16)) {
-        p.bytes_emb_bf16 = (size_t)n_blk * kTileAds * d->dim * 2;
+    if (dtypes & (1u << EBR_BF16)) {
+        p.bytes_emb_bf16 = (size_t)n_blk * kTileAds * dim * 2;
         p.off_emb_bf16 = off; off = align256(off + p.bytes_emb_bf16);
     }
-    if (d->dtypes & (1u << EBR_FP8E4M3)) {
-        p.bytes_emb_fp8 = (size_t)n_blk * kTileAds * d->dim;
+    if (dtypes & (1u << EBR_FP8E4M3)) {
+        p.bytes_emb_fp8 = (size_t)n_blk * kTileAds * dim;
         p.off_emb_fp8 = off; off = align256(off + p.bytes_emb_fp8);
         p.bytes_fp8_scale = (size_t)n_blk * kTileAds * 4;
         p.off_fp8_scale = off; off = align256(off + p.bytes_fp8_scale);
@@ -206,7 +222,7 @@ static ebr_status measure(const ebr_build_desc* d, Measured* m) {
     p.off_weights = off;
     if (p.bytes_weights) off = align256(off + p.bytes_weights);
     p.total = off;
-    return EBR_OK;
+    return p;
 }
 
 // FP32 copy in the matrix-core layout (see k_score in score.h).
@@ -225,6 +241,165 @@ static void swizzle_f32(const float* E, int64_t n_ads, int32_t d, float* out) {
                     }
         }
     }, 64);
+}
+
+// The index object over a filled arena (host build and device build alike).
+static ebr_index* finish_index(int64_t n_ads, int32_t dim, uint32_t dtypes, int64_t V, int64_t n_post, bool has_w,
+                               const ArenaPlan& p, char* base, std::vector<uint32_t> key_chunk_off,
+                               const int64_t* key_offsets, std::vector<float> maxw, const double* q_err2,
+                               const double* q_norm2, double e_norm2, double enc_ms, double up_ms) {
+    ebr_index* ix = new ebr_index();
+    ix->n_ads = n_ads;
+    ix->n_keys = V;
+    ix->n_postings = n_post;
+    ix->n_chunks = p.n_chunks;
+    ix->dim = dim;
+    ix->n_tiles = (n_ads + kTileAds - 1) / kTileAds;
+    ix->dtypes = 1u | dtypes;
+    ix->emb_f32 = base + p.off_emb_f32;
+    if ((dtypes & (1u << EBR_BF16))) ix->emb_bf16 = base + p.off_emb_bf16;
+    if ((dtypes & (1u << EBR_FP8E4M3))) {
+        ix->emb_fp8 = base + p.off_emb_fp8;
+        ix->fp8_scale = (const float*)(base + p.off_fp8_scale);
+    }
+    for (int c = 0; c < 2; ++c) { ix->q_err2[c] = q_err2[c]; ix->q_norm2[c] = q_norm2[c]; }
+    ix->e_norm2 = e_norm2;
+    ix->chunks = (const ChunkHdr*)(base + p.off_chunks);
+    ix->words = (const uint32_t*)(base + p.off_words);
+    ix->weights = has_w ? (const float*)(base + p.off_weights) : nullptr;  // null: W = 1
+    ix->key_chunk_off = std::move(key_chunk_off);
+    ix->key_post_off.assign(key_offsets ? key_offsets : nullptr, key_offsets ? key_offsets + V + 1 : nullptr);
+    if (ix->key_post_off.empty()) ix->key_post_off.assign(1, 0);
+    ix->key_maxw = std::move(maxw);
+    // per-key weight scale: |w| * 2^Sw < 2^30 with max |w| * 2^Sw >= 2^29
+    ix->key_wshift.assign((size_t)V, 0);
+    for (int64_t k = 0; k < V; ++k) {
+        if (ix->key_maxw[k] > 0.0f) {
+            int e;
+            std::frexp((double)ix->key_maxw[k], &e);  // max|w| < 2^e
+            ix->key_wshift[k] = (int8_t)std::max(-120, std::min(120, 30 - e));
+        }
+    }
+    if (hipGetDevice(&ix->device) != hipSuccess) ix->device = 0;
+    ebr_index_info& s = ix->stats;
+    s.n_ads = ix->n_ads;
+    s.n_keys = V;
+    s.n_postings = n_post;
+    s.n_chunks = p.n_chunks;
+    s.n_tiles = ix->n_tiles;
+    s.dim = ix->dim;
+    s.tile_ads = kTileAds;
+    s.arena_bytes = p.total;
+    s.bytes_emb_f32 = p.bytes_emb_f32;
+    s.bytes_emb_bf16 = p.bytes_emb_bf16;
+    s.bytes_emb_fp8 = p.bytes_emb_fp8 + p.bytes_fp8_scale;
+    s.max_err_bf16 = q_err2[0];
+    s.max_err_fp8 = q_err2[1];
+    s.bytes_chunk_headers = (uint64_t)p.n_chunks * 16;
+    s.bytes_packed_ids = (uint64_t)p.n_words * 4;
+    s.bytes_weights = has_w ? (uint64_t)n_post * 4 : 0;
+    s.bits_per_id = n_post ? (double)(s.bytes_chunk_headers + s.bytes_packed_ids) * 8.0 / (double)n_post : 0.0;
+    s.bytes_per_posting = n_post ? (double)(s.bytes_chunk_headers + s.bytes_packed_ids + s.bytes_weights) / (double)n_post : 0.0;
+    s.encode_ms = enc_ms;
+    s.upload_ms = up_ms;
+    return ix;
+}
+
+// ------------------------------------------------------------------ device build (refresh)
+
+
+// Scratch sections of a device build of n_keys lists holding n_post postings.
+struct BuildScratch {
+    size_t o_kc = 0, o_kco = 0, o_maxw = 0, o_ck = 0, o_cw = 0, o_wo = 0, o_ci = 0, o_flags = 0, o_stats = 0,
+           o_tmp = 0, total = 0;
+};
+
+static BuildScratch build_scratch(int64_t V, int64_t n_post) {
+    BuildScratch b;
+    const int64_t chunks = n_post / kChunk + V + 1;  // sum over lists of ceil(L / 64)
+    size_t off = 0;
+    auto put = [&](size_t bytes) { size_t o = off; off = align256(off + std::max<size_t>(bytes, 16)); return o; };
+    b.o_kc = put(4 * (size_t)(V + 1));
+    b.o_kco = put(4 * (size_t)(V + 1));
+    b.o_maxw = put(4 * (size_t)std::max<int64_t>(1, V));
+    b.o_ck = put(4 * (size_t)chunks);
+    b.o_cw = put(4 * (size_t)(chunks + 1));
+    b.o_wo = put(4 * (size_t)(chunks + 1));
+    b.o_ci = put(4 * (size_t)chunks);
+    b.o_flags = put(16);
+    b.o_stats = put(64);
+    b.o_tmp = put(4 * (size_t)scan_tmp_words(std::max<int64_t>(V, chunks) + 1));
+    b.total = off;
+    return b;
+}
+
+// Validate the host-visible sizes and the list offsets (copied to the host), then find every
+// list's chunks and every chunk's shape on the device. Leaves the sizes in *n_chunks, *n_words.
+static ebr_status device_shapes(const ebr_build_desc* d, char* scr, size_t scr_bytes, hipStream_t st, BuildArgs* a,
+                         std::vector<int64_t>* key_off, int64_t* n_chunks, int64_t* n_words) {
+    if (!d) { set_error("desc is NULL"); return EBR_EINVAL; }
+    if (d->n_ads < 1 || d->n_ads > 0xffffffffLL) { set_error("n_ads must be in [1, 2^32)"); return EBR_EINVAL; }
+    if (!dim_ok(d->dim)) { set_error("dim %d unsupported: need a multiple of 16 in [16, 128]", d->dim); return EBR_EINVAL; }
+    if (!d->ad_emb) { set_error("ad_emb is NULL"); return EBR_EINVAL; }
+    if (d->n_keys < 0) { set_error("n_keys < 0"); return EBR_EINVAL; }
+    if (d->n_keys > 0 && !d->key_offsets) { set_error("key_offsets is NULL"); return EBR_EINVAL; }
+    if (d->dtypes & ~7u) { set_error("unknown dtype bits in %u", d->dtypes); return EBR_EINVAL; }
+    const int64_t V = d->n_keys;
+    key_off->assign((size_t)V + 1, 0);
+    if (V > 0) {
+        HIP_TRY(hipMemcpyAsync(key_off->data(), d->key_offsets, 8 * (size_t)(V + 1), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if ((*key_off)[0] != 0) { set_error("key_offsets[0] != 0"); return EBR_EINVAL; }
+        for (int64_t k = 0; k < V; ++k)
+            if ((*key_off)[k + 1] < (*key_off)[k]) { set_error("key_offsets decrease at key %lld", (long long)k); return EBR_EINVAL; }
+        if ((*key_off)[V] > 0xffffffffLL - 64) { set_error("more than 2^32 postings"); return EBR_EINVAL; }
+        if ((*key_off)[V] > 0 && !d->post_ids) { set_error("post_ids is NULL"); return EBR_EINVAL; }
+    }
+    const int64_t n_post = (*key_off)[V];
+    const BuildScratch bs = build_scratch(V, n_post);
+    if (!scr || scr_bytes < bs.total) { set_error("scratch too small: need %zu bytes, got %zu", bs.total, scr_bytes); return EBR_ENOMEM; }
+    if ((uintptr_t)scr & 255) { set_error("scratch must be 256-byte aligned"); return EBR_EINVAL; }
+    *a = BuildArgs{};
+    a->n_ads = d->n_ads;
+    a->dim = d->dim;
+    a->n_keys = V;
+    a->key_offsets = d->key_offsets;
+    a->post_ids = d->post_ids;
+    a->post_w = d->post_w;
+    a->emb = d->ad_emb;
+    a->key_chunks = (uint32_t*)(scr + bs.o_kc);
+    a->key_chunk_off = (uint32_t*)(scr + bs.o_kco);
+    a->key_maxw = (float*)(scr + bs.o_maxw);
+    a->chunk_key = (uint32_t*)(scr + bs.o_ck);
+    a->chunk_words = (uint32_t*)(scr + bs.o_cw);
+    a->word_off = (uint32_t*)(scr + bs.o_wo);
+    a->chunk_info = (uint32_t*)(scr + bs.o_ci);
+    a->flags = (unsigned long long*)(scr + bs.o_flags);
+    a->stats = (unsigned long long*)(scr + bs.o_stats);
+    uint32_t* tmp = (uint32_t*)(scr + bs.o_tmp);
+    LAUNCH(launch_fill_u32((uint32_t*)a->flags, 0xffffffffu, 4, st));
+    LAUNCH(launch_fill_u32((uint32_t*)a->stats, 0u, 16, st));
+    LAUNCH(launch_build_lists(*a, st));
+    LAUNCH(launch_excl_scan_u32(a->key_chunks, a->key_chunk_off, V, tmp, st));
+    unsigned long long bad = 0;
+    uint32_t nc = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, a->flags, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&nc, a->key_chunk_off + V, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (bad != ~0ull) {
+        set_error("postings of key %llu are not strictly increasing ids < n_ads with finite weights", bad);
+        return EBR_EINVAL;
+    }
+    a->n_chunks = nc;
+    LAUNCH(launch_build_chunks(*a, st));
+    LAUNCH(launch_excl_scan_u32(a->chunk_words, a->word_off, nc, tmp, st));
+    uint32_t nw = 0;
+    HIP_TRY(hipMemcpyAsync(&nw, a->word_off + nc, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (nw > 0xfffffff0u) { set_error("index too large for 32-bit word offsets"); return EBR_EINVAL; }
+    *n_chunks = nc;
+    *n_words = nw;
+    return EBR_OK;
 }
 
 }  // namespace ebr
@@ -393,62 +568,91 @@ ebr_status ebr_build_index(const ebr_build_desc* desc, void* dev_arena, size_t a
         HIP_TRY(hipStreamSynchronize(stream));
         const double up_ms = ms_since(t1);
 
-        ebr_index* ix = new ebr_index();
-        ix->n_ads = desc->n_ads;
-        ix->n_keys = V;
-        ix->n_postings = n_post;
-        ix->n_chunks = p.n_chunks;
-        ix->dim = desc->dim;
-        ix->n_tiles = (desc->n_ads + kTileAds - 1) / kTileAds;
-        ix->dtypes = 1u | desc->dtypes;
-        ix->emb_f32 = base + p.off_emb_f32;
-        if (want_bf16) ix->emb_bf16 = base + p.off_emb_bf16;
-        if (want_fp8) {
-            ix->emb_fp8 = base + p.off_emb_fp8;
-            ix->fp8_scale = (const float*)(base + p.off_fp8_scale);
-        }
-        for (int c = 0; c < 2; ++c) { ix->q_err2[c] = q_err2[c]; ix->q_norm2[c] = q_norm2[c]; }
-        ix->e_norm2 = e_norm2;
-        ix->chunks = (const ChunkHdr*)(base + p.off_chunks);
-        ix->words = (const uint32_t*)(base + p.off_words);
-        ix->weights = desc->post_w ? (const float*)(base + p.off_weights) : nullptr;  // null: W = 1
-        ix->key_chunk_off = std::move(m.key_chunk_off);
-        ix->key_post_off.assign(desc->key_offsets ? desc->key_offsets : nullptr,
-                                desc->key_offsets ? desc->key_offsets + V + 1 : nullptr);
-        if (ix->key_post_off.empty()) ix->key_post_off.assign(1, 0);
-        ix->key_maxw = std::move(maxw);
-        // per-key weight scale: |w| * 2^Sw < 2^30 with max |w| * 2^Sw >= 2^29
-        ix->key_wshift.assign((size_t)V, 0);
-        for (int64_t k = 0; k < V; ++k) {
-            if (ix->key_maxw[k] > 0.0f) {
-                int e;
-                std::frexp((double)ix->key_maxw[k], &e);  // max|w| < 2^e
-                ix->key_wshift[k] = (int8_t)std::max(-120, std::min(120, 30 - e));
-            }
-        }
-        if (hipGetDevice(&ix->device) != hipSuccess) ix->device = 0;
-        ebr_index_info& s = ix->stats;
-        s.n_ads = ix->n_ads;
-        s.n_keys = V;
-        s.n_postings = n_post;
-        s.n_chunks = p.n_chunks;
-        s.n_tiles = ix->n_tiles;
-        s.dim = ix->dim;
-        s.tile_ads = kTileAds;
-        s.arena_bytes = p.total;
-        s.bytes_emb_f32 = p.bytes_emb_f32;
-        s.bytes_emb_bf16 = p.bytes_emb_bf16;
-        s.bytes_emb_fp8 = p.bytes_emb_fp8 + p.bytes_fp8_scale;
-        s.max_err_bf16 = q_err2[0];
-        s.max_err_fp8 = q_err2[1];
-        s.bytes_chunk_headers = (uint64_t)p.n_chunks * 16;
-        s.bytes_packed_ids = (uint64_t)p.n_words * 4;
-        s.bytes_weights = desc->post_w ? (uint64_t)n_post * 4 : 0;
-        s.bits_per_id = n_post ? (double)(s.bytes_chunk_headers + s.bytes_packed_ids) * 8.0 / (double)n_post : 0.0;
-        s.bytes_per_posting = n_post ? (double)(s.bytes_chunk_headers + s.bytes_packed_ids + s.bytes_weights) / (double)n_post : 0.0;
-        s.encode_ms = enc_ms;
-        s.upload_ms = up_ms;
+        ebr_index* ix = finish_index(desc->n_ads, desc->dim, desc->dtypes, V, n_post, desc->post_w != nullptr, p, base,
+                                     std::move(m.key_chunk_off), desc->key_offsets, std::move(maxw), q_err2, q_norm2,
+                                     e_norm2, enc_ms, up_ms);
         *out = ix;
+        return EBR_OK;
+    } catch (const std::bad_alloc&) {
+        set_error("host out of memory");
+        return EBR_ENOMEM;
+    }
+}
+
+
+ebr_status ebr_device_build_scratch_size(int64_t n_keys, int64_t n_postings, size_t* bytes) {
+    if (!bytes || n_keys < 0 || n_postings < 0) { set_error("bad argument"); return EBR_EINVAL; }
+    *bytes = build_scratch(n_keys, n_postings).total;
+    return EBR_OK;
+}
+
+ebr_status ebr_device_index_size(const ebr_build_desc* desc, void* scratch, size_t scratch_bytes, void* hip_stream,
+                                 size_t* arena_bytes) {
+    try {
+        if (!arena_bytes) { set_error("arena_bytes is NULL"); return EBR_EINVAL; }
+        BuildArgs a;
+        std::vector<int64_t> ko;
+        int64_t nc = 0, nw = 0;
+        ebr_status st = device_shapes(desc, (char*)scratch, scratch_bytes, (hipStream_t)hip_stream, &a, &ko, &nc, &nw);
+        if (st) return st;
+        *arena_bytes = arena_plan(desc->n_ads, desc->dim, desc->dtypes, ko.back(), nc, nw, desc->post_w != nullptr).total;
+        return EBR_OK;
+    } catch (const std::bad_alloc&) {
+        set_error("host out of memory");
+        return EBR_ENOMEM;
+    }
+}
+
+ebr_status ebr_build_index_device(const ebr_build_desc* desc, void* scratch, size_t scratch_bytes, void* dev_arena,
+                                  size_t arena_bytes, void* hip_stream, ebr_index** out) {
+    try {
+        if (!out) { set_error("out is NULL"); return EBR_EINVAL; }
+        *out = nullptr;
+        const auto t0 = std::chrono::steady_clock::now();
+        hipStream_t st = (hipStream_t)hip_stream;
+        BuildArgs a;
+        std::vector<int64_t> ko;
+        int64_t nc = 0, nw = 0;
+        ebr_status s = device_shapes(desc, (char*)scratch, scratch_bytes, st, &a, &ko, &nc, &nw);
+        if (s) return s;
+        const int64_t V = desc->n_keys, n_post = ko.back();
+        const ArenaPlan p = arena_plan(desc->n_ads, desc->dim, desc->dtypes, n_post, nc, nw, desc->post_w != nullptr);
+        if (!dev_arena || arena_bytes < p.total) { set_error("arena too small: need %zu bytes, got %zu", p.total, arena_bytes); return EBR_ENOMEM; }
+        if ((uintptr_t)dev_arena & 255) { set_error("arena must be 256-byte aligned"); return EBR_EINVAL; }
+        char* base = (char*)dev_arena;
+        a.hdr = (ChunkHdr*)(base + p.off_chunks);
+        a.words = (uint32_t*)(base + p.off_words);
+        a.emb_f32 = (float*)(base + p.off_emb_f32);
+        a.emb_bf16 = (desc->dtypes & (1u << EBR_BF16)) ? (uint16_t*)(base + p.off_emb_bf16) : nullptr;
+        a.emb_fp8 = (desc->dtypes & (1u << EBR_FP8E4M3)) ? (uint8_t*)(base + p.off_emb_fp8) : nullptr;
+        a.fp8_scale = a.emb_fp8 ? (float*)(base + p.off_fp8_scale) : nullptr;
+        // rows first: non-finite embeddings are refused before the copies are written
+        LAUNCH(launch_build_rows(a, st));
+        unsigned long long flags[2] = {0, 0}, stats[5] = {0, 0, 0, 0, 0};
+        HIP_TRY(hipMemcpyAsync(flags, a.flags, 16, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (flags[1] != ~0ull) { set_error("non-finite embedding in ad %llu", flags[1]); return EBR_EINVAL; }
+        LAUNCH(launch_build_pack(a, st));
+        LAUNCH(launch_fill_u32(a.words + nw, 0u, 2, st));  // the two pad words
+        LAUNCH(launch_build_layout(a, st));
+        if (desc->post_w && n_post > 0)
+            HIP_TRY(hipMemcpyAsync(base + p.off_weights, desc->post_w, 4 * (size_t)n_post, hipMemcpyDeviceToDevice, st));
+        std::vector<uint32_t> kco((size_t)V + 1, 0u);
+        std::vector<float> maxw((size_t)V, 0.0f);
+        HIP_TRY(hipMemcpyAsync(stats, a.stats, 40, hipMemcpyDeviceToHost, st));
+        if (V > 0) {
+            HIP_TRY(hipMemcpyAsync(kco.data(), a.key_chunk_off, 4 * (size_t)(V + 1), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(maxw.data(), a.key_maxw, 4 * (size_t)V, hipMemcpyDeviceToHost, st));
+        }
+        HIP_TRY(hipStreamSynchronize(st));
+        auto root = [&](int i) {
+            double v;
+            std::memcpy(&v, &stats[i], 8);
+            return std::sqrt(v);  // the largest row norm: the root of the largest squared norm
+        };
+        const double q_err2[2] = {root(1), root(3)}, q_norm2[2] = {root(2), root(4)};
+        *out = finish_index(desc->n_ads, desc->dim, desc->dtypes, V, n_post, desc->post_w != nullptr, p, base,
+                            std::move(kco), ko.data(), std::move(maxw), q_err2, q_norm2, root(0), ms_since(t0), 0.0);
         return EBR_OK;
     } catch (const std::bad_alloc&) {
         set_error("host out of memory");
@@ -506,6 +710,9 @@ struct Plan {
     int kcmax = 0;
     std::vector<double> aq;     // per query: sum_j |m_j| max|W[k_j,:]|
     bool packed = false;  // bucket entries carry users ranges: one query group, < 2^19 features
+    bool split = false;   // split buckets (several query groups, see kernels.h)
+    int n_sub = 1, n_hot = 0, cold_first = 0;
+    std::vector<uint32_t> hot_tab, hot_users, hot_users_off, cold_off, cold_users;
     int64_t nnz = 0;
     int kmax = 0;
     std::vector<uint32_t> uk_chunk_begin, uk_chunk_prefix, users_off, users;
@@ -525,7 +732,8 @@ struct Plan {
     size_t o_kc = 0, o_aq = 0, off_ctl = 0, off_cwide = 0, off_rid = 0, off_rwide = 0, off_rst = 0, off_eps = 0,
            off_unc = 0, off_fb_users = 0, off_fb_ids = 0, off_fb_scores = 0, fb_limit = 0;
     size_t o_ukb = 0, o_ukp = 0, o_ukw = 0, o_uoff = 0, o_users = 0, o_qi = 0, o_kq = 0, o_jq = 0,
-           o_oo = 0, o_st = 0, o_werr = 0;
+           o_oo = 0, o_st = 0, o_werr = 0, o_htab = 0, o_husers = 0, o_hoff = 0, o_coff = 0,
+           o_cusers = 0;
     int64_t n_super = 0;
     size_t off_stcnt = 0, off_stoff = 0, off_stfill = 0, off_stage = 0, off_cmap = 0;
     size_t off_big_deep = 0, off_big_wide = 0, off_big_keys = 0, off_big_tmp = 0, off_big_hist = 0,
@@ -578,6 +786,8 @@ static void layout(const Index& ix, bool topk, const BatchSizes& z, Plan* P) {
     const int nqg = std::max(1, (B + P->gq - 1) / P->gq);
     const size_t n_users_off = (size_t)nu * nqg + 1, n_users = 2 * (size_t)std::max<int64_t>(1, z.nnz);
     P->bucket_n = z.bucket_n;
+    const bool split = split_groups(nqg) && nu < (1 << 21);
+    P->n_sub = split ? nqg + 2 : 1;
     size_t off = 0;
     auto put = [&](size_t bytes) { size_t o = off; off = align256(off + std::max<size_t>(bytes, 16)); return o; };
     P->off_plan = off;
@@ -594,6 +804,13 @@ static void layout(const Index& ix, bool topk, const BatchSizes& z, Plan* P) {
     P->o_werr = put(4 * (size_t)B);
     P->o_oo = put(8 * (size_t)(B + 1));
     P->o_st = put(4 * (size_t)z.n_sample);
+    if (split) {
+        P->o_htab = put(4 * (size_t)nqg * (size_t)std::min(nu, kHotMax));
+        P->o_husers = put(4 * n_users);
+        P->o_hoff = put(4 * (size_t)(nqg + 1));
+        P->o_coff = put(4 * (size_t)(nu + 1));
+        P->o_cusers = put(4 * n_users);
+    }
     P->plan_bytes = off - P->off_plan;
     P->n_super = (ix.n_ads + kSuperAds - 1) / kSuperAds;
     P->off_stcnt = put(4 * (size_t)(P->n_super + 1));
@@ -603,7 +820,7 @@ static void layout(const Index& ix, bool topk, const BatchSizes& z, Plan* P) {
     P->off_stage = put(8 * (size_t)P->bucket_n);
     // chunks of the batch: sum over keys of ceil(L / 64) <= postings / 64 + keys
     P->off_cmap = put(8 * ((size_t)P->bucket_n / kChunk + (size_t)nu + 1));
-    P->off_toff = put(4 * (size_t)(ix.n_tiles + 1));
+    P->off_toff = put(4 * (size_t)(ix.n_tiles * P->n_sub + 1));
     P->off_bucket = put(8 * (size_t)P->bucket_n);
     if (topk) {
         P->off_skeys = put(4 * (size_t)B * (size_t)z.n_sample * kTileAds);
@@ -745,6 +962,68 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     if (nu >= (1 << (32 - kSuperShift))) { set_error("too many distinct keys in one batch"); return EBR_EINVAL; }
     P->nu = nu;
     P->packed = P->n_qg == 1 && nnz < (1LL << 19);
+    // split buckets (several query groups): hot keys first, then warm, then cold (kernels.h)
+    const int nqg = std::max(1, P->n_qg);
+    P->split = split_groups(nqg) && nu < (1 << 21);
+    P->n_sub = P->split ? nqg + 2 : 1;
+    P->n_hot = 0;
+    P->cold_first = nu;
+    std::vector<uint32_t> ucnt;  // split: users per slot (all groups)
+    if (P->split) {
+        std::vector<uint32_t> users_of(nu, 0u);
+        for (int64_t j = 0; j < nnz; ++j) users_of[slot[j]]++;
+        // cold: at most as many users as groups (placing a posting once per user costs less
+        // than every group visiting it); hot: of the others, the longest lists first (ties by
+        // slot), while each group's users of them fit its LDS records; warm: the rest
+        const uint32_t limit = (uint32_t)cold_user_limit(nqg);
+        std::vector<uint64_t> by_len;  // (~length << 32) | slot of the non-cold keys, ascending
+        std::vector<int32_t> cand(nu, -1);
+        for (int u = 0; u < nu; ++u)
+            if (users_of[u] > limit) {
+                cand[u] = (int32_t)by_len.size();
+                const uint64_t L = (uint64_t)(ix.key_post_off[uk[u] + 1] - ix.key_post_off[uk[u]]);
+                by_len.push_back(((~L & 0xffffffffull) << 32) | (uint64_t)u);
+            }
+        // per (non-cold key, group): users
+        std::vector<uint32_t> cnt(by_len.size() * (size_t)nqg, 0u);
+        for (int q = 0; q < B; ++q)
+            for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j)
+                if (cand[slot[j]] >= 0) cnt[(size_t)cand[slot[j]] * nqg + q / P->gq]++;
+        std::sort(by_len.begin(), by_len.end());
+        const uint32_t cap = (uint32_t)score_users_lds(ix.dim, P->w64);
+        std::vector<uint32_t> hu(nqg, 0u);
+        std::vector<int32_t> order;
+        order.reserve(nu);
+        for (uint64_t key : by_len) {
+            const int32_t u = (int32_t)(key & 0xffffffffu);
+            if ((int)order.size() == kHotMax) break;
+            const uint32_t* c = cnt.data() + (size_t)cand[u] * nqg;
+            bool fits = true;
+            for (int g = 0; g < nqg && fits; ++g) fits = hu[g] + c[g] <= cap;
+            if (!fits) continue;
+            for (int g = 0; g < nqg; ++g) hu[g] += c[g];
+            order.push_back(u);
+        }
+        std::vector<char> is_hot(nu, 0);
+        for (int32_t u : order) is_hot[u] = 1;
+        P->n_hot = (int)order.size();
+        for (int u = 0; u < nu; ++u)
+            if (!is_hot[u] && users_of[u] > limit) order.push_back(u);
+        P->cold_first = (int)order.size();
+        for (int u = 0; u < nu; ++u)
+            if (!is_hot[u] && users_of[u] <= limit) order.push_back(u);
+        // renumber the slots in that order
+        std::vector<int32_t> renum(nu);
+        std::vector<int32_t> uk2(nu);
+        ucnt.resize(nu);
+        for (int i = 0; i < nu; ++i) {
+            renum[order[i]] = i;
+            uk2[i] = uk[order[i]];
+            ucnt[i] = users_of[order[i]];
+        }
+        uk.swap(uk2);
+        for (int64_t j = 0; j < nnz; ++j) slot[j] = renum[slot[j]];
+    }
     P->uk_chunk_begin.resize(nu);
     P->uk_chunk_prefix.assign(nu + 1, 0);
     P->uk_wshift.resize(nu);
@@ -760,12 +1039,23 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     P->uk_chunk_prefix[nu] = (uint32_t)chunks;
     P->total_chunks = (uint32_t)chunks;
     P->bucket_n = posts;
-    // users of each (distinct key, query group), in query order
-    const int nqg = std::max(1, P->n_qg);
+    if (P->split) {
+        // a cold key's postings are placed once per user
+        for (int u = P->cold_first; u < nu; ++u)
+            P->bucket_n += (uint64_t)(ix.key_post_off[uk[u] + 1] - ix.key_post_off[uk[u]]) * (ucnt[u] - 1u);
+    }
+    // users of each (distinct key, query group), in query order; the groups' entries are
+    // disjoint, so groups are counted and filled in parallel
+    auto per_group = [&](const std::function<void(int)>& fn) {
+        parallel_for(nqg, [&](int64_t g0, int64_t g1) { for (int64_t g = g0; g < g1; ++g) fn((int)g); }, 1);
+    };
     P->users_off.assign((size_t)nu * nqg + 1, 0);
-    for (int q = 0; q < B; ++q)
-        for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j)
-            P->users_off[(size_t)slot[j] * nqg + q / P->gq + 1]++;
+    per_group([&](int g) {
+        const int q1 = std::min(B, (g + 1) * P->gq);
+        for (int q = g * P->gq; q < q1; ++q)
+            for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j)
+                P->users_off[(size_t)slot[j] * nqg + g + 1]++;
+    });
     for (size_t i = 1; i < P->users_off.size(); ++i) P->users_off[i] += P->users_off[i - 1];
     // per-query fixed-point scale of the cross term: the largest S with
     // sum_j |m_j| max|W[k_j,:]| 2^S (1 + 2^-23) + F_q + 1 below 2^31 (2^63 for 64-bit cells), so
@@ -801,18 +1091,63 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     P->users.assign((size_t)2 * std::max<int64_t>(1, nnz), 0u);
     {
         std::vector<uint32_t> fill(P->users_off.begin(), P->users_off.end() - 1);
-        for (int q = 0; q < B; ++q)
-            for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
-                const size_t s = (size_t)slot[j] * nqg + q / P->gq;
-                const uint32_t pos = fill[s]++;
-                const double m = bt->feat_mult ? (double)bt->feat_mult[j] : 1.0;
-                const int sw = ix.key_wshift[bt->feat_keys[j]];
-                const float mf = (float)std::ldexp(m, Sq[q] - sw);
-                uint32_t bits;
-                std::memcpy(&bits, &mf, 4);
-                P->users[2 * pos] = (uint32_t)(q % P->gq);
-                P->users[2 * pos + 1] = bits;
+        per_group([&](int g) {
+            const int q1 = std::min(B, (g + 1) * P->gq);
+            for (int q = g * P->gq; q < q1; ++q)
+                for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
+                    const uint32_t pos = fill[(size_t)slot[j] * nqg + g]++;
+                    const double m = bt->feat_mult ? (double)bt->feat_mult[j] : 1.0;
+                    const int sw = ix.key_wshift[bt->feat_keys[j]];
+                    const float mf = (float)std::ldexp(m, Sq[q] - sw);
+                    uint32_t bits;
+                    std::memcpy(&bits, &mf, 4);
+                    P->users[2 * pos] = (uint32_t)(q - g * P->gq);
+                    P->users[2 * pos + 1] = bits;
+                }
+        });
+    }
+    if (P->split) {
+        // per group: its users of the hot keys (the LDS records of its work-groups) and the
+        // table hot slot -> (first record << 9) | count
+        const int H = P->n_hot;
+        P->hot_tab.assign((size_t)nqg * std::max(1, H), 0u);
+        P->hot_users_off.assign(nqg + 1, 0u);
+        for (int g = 0; g < nqg; ++g) {
+            uint32_t n = 0;
+            for (int u = 0; u < H; ++u) n += P->users_off[(size_t)u * nqg + g + 1] - P->users_off[(size_t)u * nqg + g];
+            P->hot_users_off[g + 1] = P->hot_users_off[g] + n;
+        }
+        P->hot_users.assign(2 * (size_t)std::max(1u, P->hot_users_off[nqg]), 0u);
+        per_group([&](int g) {
+            uint32_t local = 0;
+            uint32_t* dst = P->hot_users.data() + 2 * (size_t)P->hot_users_off[g];
+            for (int u = 0; u < H; ++u) {
+                const uint32_t b = P->users_off[(size_t)u * nqg + g], e = P->users_off[(size_t)u * nqg + g + 1];
+                P->hot_tab[(size_t)g * H + u] = (local << 9) | (e - b);
+                std::memcpy(dst + 2 * (size_t)local, P->users.data() + 2 * (size_t)b, 8 * (size_t)(e - b));
+                local += e - b;
             }
+        });
+        // per cold key: its users of all groups as (query index in the batch, m'); a key's
+        // users of all groups are contiguous in users (slot-major offsets)
+        const int nc = nu - P->cold_first;
+        P->cold_off.assign((size_t)nc + 1, 0u);
+        for (int c = 0; c < nc; ++c) {
+            const size_t u = (size_t)(P->cold_first + c);
+            P->cold_off[c + 1] = P->cold_off[c] + (P->users_off[(u + 1) * nqg] - P->users_off[u * nqg]);
+        }
+        P->cold_users.assign(2 * (size_t)std::max(1u, P->cold_off[nc]), 0u);
+        parallel_for(nc, [&](int64_t c0, int64_t c1) {
+            for (int64_t c = c0; c < c1; ++c) {
+                const size_t u = (size_t)(P->cold_first + c);
+                uint32_t* dst = P->cold_users.data() + 2 * (size_t)P->cold_off[c];
+                for (int g = 0; g < nqg; ++g)
+                    for (uint32_t i = P->users_off[u * nqg + g]; i < P->users_off[u * nqg + g + 1]; ++i) {
+                        *dst++ = (uint32_t)g * (uint32_t)P->gq + P->users[2 * (size_t)i];
+                        *dst++ = P->users[2 * (size_t)i + 1];
+                    }
+            }
+        }, 8192);
     }
     // output offsets
     P->out_off.assign(B + 1, 0);
@@ -874,6 +1209,13 @@ static std::vector<char> pack_plan(const Plan& P) {
     cp(P.o_werr, P.werr.data(), 4 * P.werr.size());
     cp(P.o_oo, P.out_off.data(), 8 * P.out_off.size());
     cp(P.o_st, P.sample_tiles.data(), 4 * P.sample_tiles.size());
+    if (P.split) {
+        cp(P.o_htab, P.hot_tab.data(), 4 * (size_t)P.n_hot * (P.hot_users_off.size() - 1));
+        cp(P.o_husers, P.hot_users.data(), 4 * P.hot_users.size());
+        cp(P.o_hoff, P.hot_users_off.data(), 4 * P.hot_users_off.size());
+        cp(P.o_coff, P.cold_off.data(), 4 * P.cold_off.size());
+        cp(P.o_cusers, P.cold_users.data(), 4 * P.cold_users.size());
+    }
     return blob;
 }
 
@@ -893,14 +1235,6 @@ static int score_ctas() {
     return c;
 }
 
-#define LAUNCH(expr)                                                                       \
-    do {                                                                                   \
-        int rc_ = (expr);                                                                  \
-        if (rc_) {                                                                         \
-            set_error("%s failed: %s", #expr, hipGetErrorString((hipError_t)rc_));         \
-            return EBR_EDEVICE;                                                            \
-        }                                                                                  \
-    } while (0)
 
 // Upload the plan, decode the batch's lists into tile buckets. Shared by top-K and dense.
 // The plan bytes (pack_plan) are uploaded from src first unless src is null (already there).
@@ -933,6 +1267,12 @@ static ebr_status run_decode(const Index& ix, const Plan& P, char* ws, hipStream
     d.users_off = P.packed ? (const uint32_t*)(ws + P.o_uoff) : nullptr;
     d.tile_off = (uint32_t*)(ws + P.off_toff);
     d.bucket = (uint32_t*)(ws + P.off_bucket);
+    d.n_sub = P.n_sub;
+    d.n_hot = P.n_hot;
+    d.cold_first = P.split ? P.cold_first : P.nu;
+    d.gq_shift = P.gq == 256 ? 8 : 7;
+    d.cold_off = P.split ? (const uint32_t*)(ws + P.o_coff) : nullptr;
+    d.cold_users = P.split ? (const uint32_t*)(ws + P.o_cusers) : nullptr;
     LAUNCH(launch_chunk_map(d, st));
     LAUNCH(launch_decode(d, 0, st));
     LAUNCH(launch_excl_scan_u32(stcnt, stoff, P.n_super, (uint32_t*)(ws + P.off_stmp), st));
@@ -954,6 +1294,11 @@ static ScoreArgs score_args(const Index& ix, const Plan& P, const ebr_batch* bt,
     s.wide64 = P.w64 ? 1 : 0;
     s.tile_off = (const uint32_t*)(ws + P.off_toff);
     s.bucket = (const uint32_t*)(ws + P.off_bucket);
+    s.n_sub = P.n_sub;
+    s.n_hot = P.n_hot;
+    s.hot_tab = P.split ? (const uint32_t*)(ws + P.o_htab) : nullptr;
+    s.hot_users = P.split ? (const uint32_t*)(ws + P.o_husers) : nullptr;
+    s.hot_users_off = P.split ? (const uint32_t*)(ws + P.o_hoff) : nullptr;
     s.users_off = (const uint32_t*)(ws + P.o_uoff);
     s.users = (const uint32_t*)(ws + P.o_users);
     s.n_users = (uint32_t)P.nnz;

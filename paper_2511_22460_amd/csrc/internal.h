@@ -87,6 +87,11 @@ struct ArenaPlan {
     int64_t n_chunks = 0, n_words = 0;
 };
 
+// Arena sections of an index of these sizes (n_chunks 64-posting chunks, n_words packed gap
+// words; weights: whether a weight array is stored).
+ArenaPlan arena_plan(int64_t n_ads, int32_t dim, uint32_t dtypes, int64_t n_post, int64_t n_chunks,
+                     int64_t n_words, bool weights);
+
 // ---------------------------------------------------------------- error plumbing
 
 void set_error(const char* fmt, ...);

@@ -24,6 +24,28 @@ constexpr float kWideTau = 0x1p-18f;
 // predecessor left no query unresolved exits at once.
 constexpr int kMaxRounds = 4;
 
+// Query groups of the scoring kernel (shared by the host planner and the kernel): queries per
+// group, and the (query, multiplier) records one work-group keeps in LDS.
+constexpr int score_gq(int dim, bool w64) { return (dim <= 64 && !w64) ? 256 : 128; }
+constexpr int score_users_lds(int dim, bool w64) { return (dim > 64 && w64) ? 4096 : 8192; }
+
+// Split buckets of a batch of several query groups. Its distinct keys are numbered hot, then
+// warm, then cold:
+//   hot  - the keys with the longest lists, as many as fit every group's LDS (at most kHotMax
+//          keys; each group's users of them at most score_users_lds). Their postings are
+//          shared by all groups; a work-group finds a key's users in an LDS table.
+//   warm - other keys with more users than query groups: shared postings, users found through
+//          the global users_off table.
+//   cold - keys with at most as many users as query groups: one bucket entry per (posting,
+//          user), carrying the pair's rounded term round(fl(m' w')) (an FP32 integer value),
+//          in the bucket of the user's query group.
+// Per tile the bucket holds [hot | warm | cold of group 0 | ... | cold of group G - 1], so the
+// tile offsets have n_tiles * (G + 2) + 1 entries.
+constexpr int kHotMax = 2048;
+constexpr int kSplitMaxGroups = 62;
+inline bool split_groups(int n_qg) { return n_qg > 1 && n_qg <= kSplitMaxGroups; }
+inline int cold_user_limit(int n_qg) { return n_qg; }
+
 // Per-batch control block (device, in the workspace).
 struct Control {
     uint32_t error;                   // bit 0: non-finite user row; bit 1: not converged
@@ -51,8 +73,15 @@ struct DecodeArgs {
     uint32_t* stage;                  // place pass: pairs ((slot << 10) | ad & 1023, w' bits)
     uint2* chunk_map;                 // per batch chunk: (slot, chunk index in the index)
     const uint32_t* users_off;        // non-null: final entries carry their key's users range
-    uint32_t* tile_off;               // refine: n_tiles + 1 offsets into bucket
+    uint32_t* tile_off;               // refine: n_tiles * n_sub + 1 offsets into bucket
     uint32_t* bucket;                 // refine: pairs (users range or slot | ad & 31, w' bits)
+    // split buckets (n_sub = groups + 2; 1 otherwise)
+    int32_t n_sub;
+    int32_t n_hot;                    // slots [0, n_hot) are hot
+    int32_t cold_first;               // slots [cold_first, n_ukeys) are cold
+    int32_t gq_shift;                 // log2 of the queries per group
+    const uint32_t* cold_off;         // per cold slot: its users in cold_users (CSR)
+    const uint32_t* cold_users;       // pairs (query index in the batch, bits of m')
 };
 
 struct ScoreArgs {
@@ -65,8 +94,13 @@ struct ScoreArgs {
     int32_t n_qgroups;
     int32_t packed;                   // bucket entries carry users ranges (one query group)
     int32_t wide64;                   // 64-bit cross-term cells (FP32 scans; 128-query groups)
-    const uint32_t* tile_off;         // n_tiles + 1
+    const uint32_t* tile_off;         // n_tiles * n_sub + 1
     const uint32_t* bucket;           // pairs
+    int32_t n_sub;                    // sub-ranges per tile (split buckets: groups + 2)
+    int32_t n_hot;                    // split buckets: hot keys
+    const uint32_t* hot_tab;          // split: per (group, hot slot) (users index << 9) | count
+    const uint32_t* hot_users;        // split: per group, its users of the hot keys
+    const uint32_t* hot_users_off;    // split: groups + 1 offsets into hot_users
     const uint32_t* users_off;        // n_ukeys * n_qgroups + 1
     const uint32_t* users;            // pairs (query within group, bits of m')
     uint32_t n_users;                 // pairs in users
@@ -190,7 +224,7 @@ int launch_decode_key(const ChunkHdr* chunks, const uint32_t* words, const float
                       float* w, void* stream);
 bool score_dim_supported(int dim);
 // Queries per query group of the scoring kernel for this embedding width and cell width.
-int score_group_queries(int dim, bool wide64 = false);
+inline int score_group_queries(int dim, bool wide64 = false) { return score_gq(dim, wide64); }
 int score_ranges(int n_work, int n_qgroups, int ctas);
 int launch_score(const ScoreArgs& a, int dim, int mode, int ranges, void* stream);
 int launch_select(const SelectArgs& a, int n_queries, void* stream);

@@ -184,20 +184,40 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
             const uint64_t above = (lane == 63) ? 0ull : (heads & (~0ull << (lane + 1)));
             const int next = above ? (int)__builtin_ctzll(above) : count;
             const int run = next - lane;
+            // a cold key of split buckets: each posting is placed once per user of the key
+            const bool cold = (int)u >= a.cold_first;
+            uint32_t c0 = 0, nusers = 1;
+            if (cold) {
+                c0 = a.cold_off[u - (uint32_t)a.cold_first];
+                nusers = a.cold_off[u - (uint32_t)a.cold_first + 1] - c0;
+            }
             if (!place) {
-                if (head) atomicAdd(&a.st_cnt[st], (uint32_t)run);
+                if (head) atomicAdd(&a.st_cnt[st], (uint32_t)run * nusers);
                 continue;
             }
             uint32_t base = 0;
-            if (head) base = atomicAdd(&a.st_fill[st], (uint32_t)run);
+            if (head) base = atomicAdd(&a.st_fill[st], (uint32_t)run * nusers);
             const uint64_t upto = (lane == 63) ? heads : (heads & ((2ull << lane) - 1ull));
             const int my_head = upto ? 63 - (int)__builtin_clzll(upto) : 0;
             base = __shfl(base, my_head, 64);
             if (valid) {
-                const uint32_t pos = a.st_off[st] + base + (uint32_t)(lane - my_head);
+                const uint32_t pos = a.st_off[st] + base + (uint32_t)(lane - my_head) * nusers;
                 const float ws = ldexpf(wt[i], a.uk_wshift[u]);  // exact: a power-of-two scale
-                reinterpret_cast<uint2*>(a.stage)[pos] =
-                    make_uint2((u << kSuperShift) | (id & (kSuperAds - 1)), __float_as_uint(ws));
+                uint2* out = reinterpret_cast<uint2*>(a.stage) + pos;
+                if (!cold) {
+                    out[0] = make_uint2((u << kSuperShift) | (id & (kSuperAds - 1)), __float_as_uint(ws));
+                } else {
+                    // the pair's term round(fl(m' w')): an FP32 value that is an integer
+                    const uint2* cu = reinterpret_cast<const uint2*>(a.cold_users) + c0;
+                    const uint32_t gmask = (1u << a.gq_shift) - 1u;
+                    for (uint32_t j = 0; j < nusers; ++j) {
+                        const uint2 r = cu[j];
+                        const float v = rintf(__uint_as_float(r.y) * ws);
+                        out[j] = make_uint2(0x80000000u | ((r.x >> a.gq_shift) << 18) | ((r.x & gmask) << kSuperShift) |
+                                                (id & (kSuperAds - 1)),
+                                            __float_as_uint(v));
+                    }
+                }
             }
         }
     }
@@ -206,22 +226,34 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
 // Entries of one super-tile a k_refine work-group keeps in registers (per thread) when they
 // fit; larger super-tiles are read twice.
 constexpr int kRefineNT = 1024, kRefineRegs = 16;
+constexpr int kRefineBins = kTilesPerSuper * (kSplitMaxGroups + 2);
+static_assert(kRefineBins <= 2 * kRefineNT, "two bins per thread in the offset scan");
 
-// One work-group per super-tile: counting sort of its entries by 32-ad tile (LDS counters),
-// the tile offsets, and the final entry format read by k_score: x = (u0 << 13) |
-// ((cnt - 1) << 5) | ad & 31 when the batch is one query group (users[u0, u0 + cnt) are the
-// key's users), else (slot << 5) | ad & 31; y = the bits of w'.
+// One work-group per super-tile: counting sort of its entries by (32-ad tile, sub-range)
+// (LDS counters; one sub-range unless the buckets are split), the tile offsets, and the final
+// entry format read by k_score: x = (u0 << 13) | ((cnt - 1) << 5) | ad & 31 when the batch is
+// one query group (users[u0, u0 + cnt) are the key's users), (query row << 5) | ad & 31 for
+// a cold pair (y: its term), else (slot << 5) | ad & 31; y = the bits of w'.
 __global__ __launch_bounds__(kRefineNT) void k_refine(DecodeArgs a) {
-    __shared__ uint32_t s_cnt[kTilesPerSuper], s_off[kTilesPerSuper];
+    __shared__ uint32_t s_cnt[kRefineBins], s_off[kRefineBins];
+    __shared__ uint32_t s_scan[kRefineNT / 64 + 1];
     const uint32_t st = blockIdx.x;
     const uint32_t beg = a.st_off[st], end = a.st_off[st + 1];
     const int tid = (int)threadIdx.x;
-    if (tid < kTilesPerSuper) s_cnt[tid] = 0u;
+    const int S = a.n_sub, nb = kTilesPerSuper * S;
+    for (int b = tid; b < nb; b += kRefineNT) s_cnt[b] = 0u;
     __syncthreads();
     const uint2* in = reinterpret_cast<const uint2*>(a.stage);
     const bool regs = end - beg <= (uint32_t)(kRefineNT * kRefineRegs);
     uint2 e[kRefineRegs];
-    auto tile_of = [](uint2 v) { return (v.x >> kTileShift) & (kTilesPerSuper - 1); };
+    // bin: tile within the super-tile, then sub-range: hot, warm, cold pairs of group g
+    auto bin_of = [&](uint2 v) -> uint32_t {
+        const uint32_t t = (v.x >> kTileShift) & (kTilesPerSuper - 1);
+        if (S == 1) return t;
+        const uint32_t sub = (v.x >> 31) ? 2u + ((v.x >> 18) & 0x1fffu)
+                                          : ((v.x >> kSuperShift) < (uint32_t)a.n_hot ? 0u : 1u);
+        return t * (uint32_t)S + sub;
+    };
     if (regs) {
         #pragma unroll
         for (int r = 0; r < kRefineRegs; ++r) {
@@ -230,32 +262,35 @@ __global__ __launch_bounds__(kRefineNT) void k_refine(DecodeArgs a) {
         }
         #pragma unroll
         for (int r = 0; r < kRefineRegs; ++r)
-            if (beg + (uint32_t)tid + (uint32_t)(r * kRefineNT) < end) atomicAdd(&s_cnt[tile_of(e[r])], 1u);
+            if (beg + (uint32_t)tid + (uint32_t)(r * kRefineNT) < end) atomicAdd(&s_cnt[bin_of(e[r])], 1u);
     } else {
-        for (uint32_t i = beg + (uint32_t)tid; i < end; i += kRefineNT) atomicAdd(&s_cnt[tile_of(in[i])], 1u);
+        for (uint32_t i = beg + (uint32_t)tid; i < end; i += kRefineNT) atomicAdd(&s_cnt[bin_of(in[i])], 1u);
     }
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = beg;
-        for (int t = 0; t < kTilesPerSuper; ++t) {
-            s_off[t] = run;
-            run += s_cnt[t];
-            s_cnt[t] = 0u;
-        }
+    {
+        // exclusive scan of the bin counts, two bins per thread
+        const uint32_t c0 = 2 * tid < nb ? s_cnt[2 * tid] : 0u;
+        const uint32_t c1 = 2 * tid + 1 < nb ? s_cnt[2 * tid + 1] : 0u;
+        uint32_t tot;
+        const uint32_t x = block_excl_scan<kRefineNT>(c0 + c1, s_scan, &tot);
+        if (2 * tid < nb) { s_off[2 * tid] = beg + x; s_cnt[2 * tid] = 0u; }
+        if (2 * tid + 1 < nb) { s_off[2 * tid + 1] = beg + x + c0; s_cnt[2 * tid + 1] = 0u; }
     }
     __syncthreads();
-    if (tid < kTilesPerSuper) {
-        const uint64_t tile = (uint64_t)st * kTilesPerSuper + (uint64_t)tid;
-        if (tile < (uint64_t)a.n_tiles) a.tile_off[tile] = s_off[tid];
+    for (int b = tid; b < nb; b += kRefineNT) {
+        const uint64_t tile = (uint64_t)st * kTilesPerSuper + (uint64_t)(b / S);
+        if (tile < (uint64_t)a.n_tiles) a.tile_off[tile * (uint64_t)S + (uint64_t)(b % S)] = s_off[b];
     }
-    if (st == gridDim.x - 1 && tid == 0) a.tile_off[a.n_tiles] = end;
+    if (st == gridDim.x - 1 && tid == 0) a.tile_off[(uint64_t)a.n_tiles * (uint64_t)S] = end;
     uint2* out = reinterpret_cast<uint2*>(a.bucket);
     auto place = [&](uint2 v) {
-        const uint32_t t = tile_of(v);
-        const uint32_t pos = s_off[t] + atomicAdd(&s_cnt[t], 1u);
+        const uint32_t b = bin_of(v);
+        const uint32_t pos = s_off[b] + atomicAdd(&s_cnt[b], 1u);
         const uint32_t u = v.x >> kSuperShift, o = v.x & (kTileAds - 1);
         uint32_t x = (u << kTileShift) | o;
-        if (a.users_off) {
+        if (S > 1 && (v.x >> 31)) {
+            x = (((v.x >> kSuperShift) & 255u) << kTileShift) | o;  // cold pair: its query row
+        } else if (a.users_off) {
             const uint32_t u0 = a.users_off[u];
             x = (u0 << 13) | ((a.users_off[u + 1] - u0 - 1u) << kTileShift) | o;
         }
@@ -634,6 +669,7 @@ int launch_excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t*
 
 int launch_refine(const DecodeArgs& a, void* stream) {
     if (a.n_super <= 0) return 0;
+    if (a.n_sub < 1 || a.n_sub > kSplitMaxGroups + 2) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(k_refine, dim3((unsigned)a.n_super), dim3(kRefineNT), 0, (hipStream_t)stream, a);
     return last(hipSuccess);
 }
@@ -662,8 +698,6 @@ int launch_decode_key(const ChunkHdr* chunks, const uint32_t* words, const float
     return last(hipSuccess);
 }
 
-
-int score_group_queries(int dim, bool wide64) { return (dim <= 64 && !wide64) ? 256 : 128; }
 
 bool score_dim_supported(int dim) {
     switch (dim) {

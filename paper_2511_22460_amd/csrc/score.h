@@ -40,11 +40,12 @@ template <bool W64> using AccT = typename std::conditional<W64, unsigned long lo
 // Queries per group: 256 (8 consumer waves) up to d = 64 with 32-bit cells, else 128 (4
 // consumer waves), so that the U operand and the LDS buffers fit.
 template <int D, bool W64 = false> struct ScoreShape {
-    static constexpr int GQ = (D <= 64 && !W64) ? 256 : 128;
+    static constexpr int GQ = score_gq(D, W64);
     static constexpr int CW = GQ / 32;
     static constexpr int NT = 64 * (CW + kProducerWaves);
-    // (query, multiplier) pairs of a one-group batch copied to LDS when they fit
-    static constexpr int USERS_LDS = (D > 64 && W64) ? 4096 : 8192;
+    // (query, multiplier) records in LDS: a one-group batch's (when they fit), or a group's
+    // users of the hot keys of split buckets
+    static constexpr int USERS_LDS = score_users_lds(D, W64);
 };
 
 // FP32 -> int64, round to nearest even; |p| <= 2^62 (the planner's bound for 64-bit cells).
@@ -113,11 +114,17 @@ __device__ __attribute__((noinline)) void store_dense(float* deep_out, float* wi
 
 // Bucket entry: x = (u0 << 13) | ((cnt - 1) << 5) | ad offset when the batch is one query
 // group (the key's users are users[u0, u0 + cnt)), else (slot << 5) | ad offset; y = w' bits.
-// Cross-term wave xw owns entries beg + xw + kCrossWaves * (lane + 64 r) of each tile; round
-// r = 0 is prefetched one tile ahead.
+// With split buckets a tile's shared entries are [beg, mid) of hot keys (users in the LDS
+// table) and [mid, end) of warm keys (users through users_off); a group's cold pairs are
+// added by the stager wave. Cross-term wave xw owns entries beg + xw + kCrossWaves * (lane +
+// 64 r) of each tile; round r = 0 is prefetched one tile ahead.
+struct Bounds {
+    uint32_t beg, mid, end;
+};
+
 struct ProdTile {
-    uint32_t beg, end;  // the tile's bucket range
-    uint2 e0;           // this lane's round-0 entry (valid if beg + pw + 8 * lane < end)
+    Bounds b;
+    uint2 e0;  // this lane's round-0 entry
 };
 
 // Users one lane adds per item: an item is (bucket entry, up to kUserChunk of the users of the
@@ -128,6 +135,16 @@ struct ProdTile {
 // LDS bank each) at every j.
 constexpr int kUserChunk = 8;
 
+// The (query, multiplier) records and the hot-key table in LDS: LDS-typed pointers, so that
+// their loads are LDS reads (a generic pointer would make them flat loads).
+typedef __attribute__((address_space(3))) const unsigned long long lds_uint2;
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+
+// Where an entry's (query, multiplier) records are: 0 = users[] in global memory, 1 = the LDS
+// records, 2 = per entry (split buckets: hot keys in LDS, warm keys in global memory).
+constexpr int kSrcGlobal = 0, kSrcLds = 1, kSrcMixed = 2;
+constexpr uint32_t kCoLds = 1u << 14;  // EntryItems::co: this entry's records are in LDS
+
 // Up to 64 bucket entries of one tile (one per lane) cut into items and laid out 64 items per
 // step: an exclusive scan of the entries' item counts places each entry's items; each entry
 // writes (first item << 6 | lane) into the slot of its first item in this wave's LDS row
@@ -136,17 +153,24 @@ constexpr int kUserChunk = 8;
 struct EntryItems {
     uint32_t nch, pre, total;  // items of this lane's entry, items before it, items in all
     uint32_t u0;               // users index of the entry's first user
-    uint32_t co;               // (users count << 5) | ad offset
+    uint32_t co;               // (users count << 5) | ad offset, kCoLds if the users are in LDS
     uint32_t w;                // w' bits
 };
 
-__device__ __forceinline__ EntryItems entry_items(const ScoreArgs& a, int g, uint2 e, bool valid) {
+template <int SRC>
+__device__ __forceinline__ EntryItems entry_items(const ScoreArgs& a, int g, uint2 e, bool valid, bool hot,
+                                                  lds_u32* s_hot) {
     EntryItems t;
-    uint32_t cnt = 0, u0 = 0;
+    uint32_t cnt = 0, u0 = 0, lds = SRC == kSrcLds ? kCoLds : 0u;
     if (valid) {
         if (a.packed) {
             u0 = e.x >> 13;
             cnt = ((e.x >> kTileShift) & 255u) + 1u;
+        } else if (SRC == kSrcMixed && hot) {
+            const uint32_t h = s_hot[e.x >> kTileShift];
+            u0 = h >> 9;
+            cnt = h & 511u;
+            lds = kCoLds;
         } else {
             const uint32_t slot = (e.x >> kTileShift) * (uint32_t)a.n_qgroups + (uint32_t)g;
             u0 = a.users_off[slot];
@@ -158,7 +182,7 @@ __device__ __forceinline__ EntryItems entry_items(const ScoreArgs& a, int g, uin
     t.pre = incl - t.nch;
     t.total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     t.u0 = u0;
-    t.co = (cnt << kTileShift) | (e.x & (kTileAds - 1));
+    t.co = (cnt << kTileShift) | (e.x & (kTileAds - 1)) | lds;
     t.w = e.y;
     return t;
 }
@@ -201,14 +225,10 @@ struct ItemLoad {
     uint32_t valid;
 };
 
-// The (query, multiplier) pairs of a one-group batch copied to LDS: an LDS-typed pointer, so
-// that its loads are LDS reads (a generic pointer would make them flat loads).
-typedef __attribute__((address_space(3))) const unsigned long long lds_uint2;
-
-// users[i] from the LDS copy (LU) or from global memory
-template <bool LU>
-__device__ __forceinline__ uint2 user_at(const ScoreArgs& a, lds_uint2* lds_users, uint32_t i) {
-    if constexpr (LU) {
+// users[i] from the LDS records or from global memory
+template <int SRC>
+__device__ __forceinline__ uint2 user_at(const ScoreArgs& a, lds_uint2* lds_users, uint32_t i, uint32_t fl) {
+    if (SRC == kSrcLds || (SRC == kSrcMixed && (fl & kCoLds))) {
         const unsigned long long v = lds_users[i];
         return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
     } else {
@@ -216,7 +236,7 @@ __device__ __forceinline__ uint2 user_at(const ScoreArgs& a, lds_uint2* lds_user
     }
 }
 
-template <bool LU>
+template <int SRC>
 __device__ __forceinline__ ItemLoad item_load(const ScoreArgs& a, const EntryItems& t, uint32_t s, int m,
                                               lds_uint2* lds_users) {
     ItemLoad it;
@@ -228,26 +248,28 @@ __device__ __forceinline__ ItemLoad item_load(const ScoreArgs& a, const EntryIte
     it.w = __shfl((int)t.w, ml, 64);
     it.o = (int)(co & (kTileAds - 1));
     const uint32_t c = k - ((uint32_t)m >> 6);  // item (chunk) index within its entry
-    const uint32_t cnt = co >> kTileShift;
+    const uint32_t cnt = (co >> kTileShift) & 511u;
     const uint32_t nch = (cnt + (kUserChunk - 1)) / kUserChunk;
     const bool on = k < t.total && m >= 0;
+    const uint32_t fl = co & kCoLds;
     it.valid = 0u;
     #pragma unroll
     for (int j = 0; j < kUserChunk; ++j) {
         const uint32_t uj = c + (uint32_t)j * nch;
         const bool ok = on && uj < cnt;
         it.valid |= ok ? (1u << j) : 0u;
-        it.ue[j] = ok ? user_at<LU>(a, lds_users, u0 + uj) : make_uint2(0u, 0u);
+        it.ue[j] = ok ? user_at<SRC>(a, lds_users, u0 + uj, fl) : make_uint2(0u, 0u);
     }
     return it;
 }
 
 // Every entry of the wave has at most kUserChunk users (one item each): the item of lane l is
 // lane l's own entry, with no search.
-template <bool LU>
+template <int SRC>
 __device__ __forceinline__ ItemLoad own_item_load(const ScoreArgs& a, const EntryItems& t, lds_uint2* lds_users) {
     ItemLoad it;
-    const uint32_t cnt = t.co >> kTileShift;
+    const uint32_t cnt = (t.co >> kTileShift) & 511u;
+    const uint32_t fl = t.co & kCoLds;
     it.o = (int)(t.co & (kTileAds - 1));
     it.w = (int)t.w;
     it.valid = 0u;
@@ -255,13 +277,14 @@ __device__ __forceinline__ ItemLoad own_item_load(const ScoreArgs& a, const Entr
     for (int j = 0; j < kUserChunk; ++j) {
         const bool ok = (uint32_t)j < cnt;
         it.valid |= ok ? (1u << j) : 0u;
-        it.ue[j] = ok ? user_at<LU>(a, lds_users, t.u0 + (uint32_t)j) : make_uint2(0u, 0u);
+        it.ue[j] = ok ? user_at<SRC>(a, lds_users, t.u0 + (uint32_t)j, fl) : make_uint2(0u, 0u);
     }
     return it;
 }
 
 // One (query, posting) pair: round(fl(m' * w')) into the query's cell (users hold m' bits,
-// bucket entries w' bits).
+// bucket entries w' bits). A cold pair of split buckets arrives as m' = 1 and w' = its
+// rounded term, which this reproduces exactly.
 template <bool W64>
 __device__ __forceinline__ void pair_add(AccT<W64>* acc, uint2 ue, int o, int w) {
     const float p = __uint_as_float(ue.y) * __uint_as_float((uint32_t)w);
@@ -279,17 +302,17 @@ __device__ __forceinline__ void item_add(AccT<W64>* acc, const ItemLoad& it) {
 }
 
 // Items of steps [s_begin, end) of a set of entries.
-template <bool LU, bool W64>
+template <int SRC, bool W64>
 __device__ __forceinline__ void item_steps(const ScoreArgs& a, const EntryItems& t, uint32_t s_begin,
                                            int* mark, AccT<W64>* acc, lds_uint2* lds_users) {
     if (s_begin == 0 && __ballot(t.nch > 1u) == 0ull) {
-        item_add<W64>(acc, own_item_load<LU>(a, t, lds_users));
+        item_add<W64>(acc, own_item_load<SRC>(a, t, lds_users));
         return;
     }
     int carry = carry_before(t, s_begin);
     for (uint32_t s = s_begin; 64u * s < t.total; ++s) {
         const int m = step_owner(t, s, mark, carry);
-        item_add<W64>(acc, item_load<LU>(a, t, s, m, lds_users));
+        item_add<W64>(acc, item_load<SRC>(a, t, s, m, lds_users));
     }
 }
 
@@ -300,63 +323,76 @@ struct ItemsAhead {
     uint32_t total;
 };
 
-template <bool LU>
-__device__ __forceinline__ ItemsAhead items_ahead(const ScoreArgs& a, int g, uint2 e, bool valid,
-                                                  int* mark, lds_uint2* lds_users) {
-    const EntryItems t = entry_items(a, g, e, valid);
+template <int SRC>
+__device__ __forceinline__ ItemsAhead items_ahead(const ScoreArgs& a, int g, uint2 e, bool valid, bool hot,
+                                                  int* mark, lds_uint2* lds_users, lds_u32* s_hot) {
+    const EntryItems t = entry_items<SRC>(a, g, e, valid, hot, s_hot);
     ItemsAhead ia;
     ia.total = t.total;
     if (__ballot(t.nch > 1u) == 0ull) {
-        ia.it = own_item_load<LU>(a, t, lds_users);
+        ia.it = own_item_load<SRC>(a, t, lds_users);
         return ia;
     }
     int carry = -1;
     const int m = t.total > 0u ? step_owner(t, 0, mark, carry) : -1;
-    ia.it = item_load<LU>(a, t, 0, m, lds_users);
+    ia.it = item_load<SRC>(a, t, 0, m, lds_users);
     return ia;
 }
 
-__device__ __forceinline__ uint2 prod_bounds(const ScoreArgs& a, uint32_t tile) {
-    return make_uint2(a.tile_off[tile], a.tile_off[tile + 1]);
+// The tile's shared bucket range: split buckets [hot | warm) sub-ranges 0 and 1 of the tile,
+// else the tile's whole range (mid = beg: no hot entries).
+__device__ __forceinline__ Bounds prod_bounds(const ScoreArgs& a, uint32_t tile) {
+    Bounds b;
+    if (a.n_sub > 1) {
+        const uint32_t* p = a.tile_off + (size_t)tile * (uint32_t)a.n_sub;
+        b.beg = p[0];
+        b.mid = p[1];
+        b.end = p[2];
+    } else {
+        b.beg = b.mid = a.tile_off[tile];
+        b.end = a.tile_off[tile + 1];
+    }
+    return b;
 }
 
-__device__ __forceinline__ ProdTile prod_entries(const ScoreArgs& a, uint2 b, int pw) {
+__device__ __forceinline__ ProdTile prod_entries(const ScoreArgs& a, const Bounds& b, int pw) {
     ProdTile t;
-    t.beg = b.x;
-    t.end = b.y;
-    const uint32_t ei = t.beg + (uint32_t)pw + kCrossWaves * (uint32_t)lane_id();
-    t.e0 = ei < t.end ? reinterpret_cast<const uint2*>(a.bucket)[ei] : make_uint2(0u, 0u);
+    t.b = b;
+    const uint32_t ei = b.beg + (uint32_t)pw + kCrossWaves * (uint32_t)lane_id();
+    t.e0 = ei < b.end ? reinterpret_cast<const uint2*>(a.bucket)[ei] : make_uint2(0u, 0u);
     return t;
 }
 
 // Cross term of one tile (this wave's share): the prefetched first step of round 0, the rest
 // of round 0, then later rounds of entries.
-template <bool LU, bool W64>
+template <int SRC, bool W64>
 __device__ __forceinline__ void prod_tile(const ScoreArgs& a, int g, int pw, const ProdTile& t,
                                           const ItemsAhead& ia, int* mark, AccT<W64>* acc,
-                                          lds_uint2* lds_users) {
+                                          lds_uint2* lds_users, lds_u32* s_hot) {
     const int lane = lane_id();
     const uint2* bucket = reinterpret_cast<const uint2*>(a.bucket);
     constexpr uint32_t kRound = kCrossWaves * 64u;
-    const uint32_t first = t.beg + (uint32_t)pw;
-    if (first >= t.end) return;
+    const uint32_t first = t.b.beg + (uint32_t)pw;
+    if (first >= t.b.end) return;
     item_add<W64>(acc, ia.it);
-    if (ia.total > 64u)
-        item_steps<LU, W64>(a, entry_items(a, g, t.e0, first + kCrossWaves * (uint32_t)lane < t.end), 1u,
-                       mark, acc, lds_users);
-    for (uint32_t base = first + kRound; base < t.end; base += kRound) {
+    if (ia.total > 64u) {
+        const uint32_t e0 = first + kCrossWaves * (uint32_t)lane;
+        item_steps<SRC, W64>(a, entry_items<SRC>(a, g, t.e0, e0 < t.b.end, e0 < t.b.mid, s_hot), 1u, mark, acc,
+                             lds_users);
+    }
+    for (uint32_t base = first + kRound; base < t.b.end; base += kRound) {
         const uint32_t ei = base + kCrossWaves * (uint32_t)lane;
-        const bool ok = ei < t.end;
+        const bool ok = ei < t.b.end;
         const uint2 e = ok ? bucket[ei] : make_uint2(0u, 0u);
-        item_steps<LU, W64>(a, entry_items(a, g, e, ok), 0u, mark, acc, lds_users);
+        item_steps<SRC, W64>(a, entry_items<SRC>(a, g, e, ok, ei < t.b.mid, s_hot), 0u, mark, acc, lds_users);
     }
 }
 
-template <bool LU>
+template <int SRC>
 __device__ __forceinline__ ItemsAhead prod_ahead(const ScoreArgs& a, int g, int pw, const ProdTile& t,
-                                                 int* mark, lds_uint2* lds_users) {
-    const uint32_t first = t.beg + (uint32_t)pw;
-    return items_ahead<LU>(a, g, t.e0, first + kCrossWaves * (uint32_t)lane_id() < t.end, mark, lds_users);
+                                                 int* mark, lds_uint2* lds_users, lds_u32* s_hot) {
+    const uint32_t e0 = t.b.beg + (uint32_t)pw + kCrossWaves * (uint32_t)lane_id();
+    return items_ahead<SRC>(a, g, t.e0, e0 < t.b.end, e0 < t.b.mid, mark, lds_users, s_hot);
 }
 
 
@@ -418,6 +454,7 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
     __shared__ uint32_t s_live[GQ];
     __shared__ int s_mark[kCrossWaves][64];
     __shared__ uint2 s_users[kUsersLds];
+    __shared__ uint32_t s_hot[kHotMax];
 
     const int tid = (int)threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const bool producer = wave >= CW;
@@ -442,12 +479,21 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
     if (n_it <= 0) return;
 
     for (int i = tid; i < 2 * GQ * kTileAds; i += NT) (&s_acc[0][0])[i] = 0;
-    // one query group: its (query, multiplier) users fit in LDS when few enough
+    // one query group: its (query, multiplier) users fit in LDS when few enough; split
+    // buckets: this group's users of the hot keys (they fit by construction) and the hot-key
+    // table
+    const bool split = a.n_sub > 1;
     const bool users_in_lds = a.packed && a.n_users <= (uint32_t)kUsersLds;
     lds_uint2* lu = (lds_uint2*)s_users;
+    lds_u32* lh = (lds_u32*)s_hot;
     if (users_in_lds) {
         for (uint32_t i = (uint32_t)tid; i < a.n_users; i += (uint32_t)NT)
             s_users[i] = reinterpret_cast<const uint2*>(a.users)[i];
+    } else if (split) {
+        const uint32_t h0 = a.hot_users_off[g], h1 = a.hot_users_off[g + 1];
+        for (uint32_t i = (uint32_t)tid; i < h1 - h0; i += (uint32_t)NT)
+            s_users[i] = reinterpret_cast<const uint2*>(a.hot_users)[h0 + i];
+        for (int i = tid; i < a.n_hot; i += NT) s_hot[i] = a.hot_tab[(size_t)g * (uint32_t)a.n_hot + (uint32_t)i];
     }
     for (int i = tid; i < GQ; i += NT) {
         const int q = qbase + i;
@@ -476,8 +522,9 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
         if (pw < kStageWaves) {
             // Stager wave: the embedding block (and FP8 row scales) of tile u is loaded into
             // registers two iterations before the consumers read it and written to LDS one
-            // iteration before; two register sets, for odd and even u. This wave issues no
-            // other global loads, so each wait covers exactly the block it needs.
+            // iteration before; two register sets, for odd and even u. Its other loads are the
+            // cold pairs of split buckets, issued in the same order as the blocks, so each wait
+            // covers what the step needs and leaves the later tiles' loads in flight.
             const int sl = pw * 64 + lane;
             struct Raw {
                 f32x4 u[SPER];   // FP32 / BF16 units
@@ -504,14 +551,59 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
                 }
                 if (DT == 2 && sl < kTileAds) s_escale[buf][sl] = r.scale;
             };
+            // Split buckets: this group's cold pairs of tile u (their terms precomputed) are
+            // added to the accumulators of tile u in the interval in which the cross-term waves
+            // fill them; a tile's cold range is loaded two tiles ahead, its first 64 entries one
+            // tile ahead (the rest, if any, when they are added).
+            const uint2* bucket = reinterpret_cast<const uint2*>(a.bucket);
+            struct Cold {
+                uint2 b;  // the tile's cold range
+                uint2 e;  // this lane's entry b.x + lane of it
+            };
+            auto cold_bounds = [&](int u) -> uint2 {
+                const uint32_t* p = a.tile_off + (size_t)tile_at(u) * (uint32_t)a.n_sub + 2u + (uint32_t)g;
+                return make_uint2(p[0], p[1]);
+            };
+            auto cold_entry = [&](uint2 b) -> uint2 {
+                const uint32_t i = b.x + (uint32_t)lane;
+                return i < b.y ? bucket[i] : make_uint2(0u, 0u);
+            };
+            auto cold_pair = [&](Acc* acc, uint2 e) {  // (row << 5 | ad offset, term): m' = 1
+                pair_add<W64>(acc, make_uint2(e.x >> kTileShift, 0x3f800000u), (int)(e.x & (kTileAds - 1)), (int)e.y);
+            };
+            auto cold_add = [&](int buf, const Cold& c) {
+                Acc* acc = s_acc[buf];
+                if (c.b.x + (uint32_t)lane < c.b.y) cold_pair(acc, c.e);
+                for (uint32_t i = c.b.x + 64u + (uint32_t)lane; i < c.b.y; i += 64u) cold_pair(acc, bucket[i]);
+            };
+            Cold cc{};
+            uint2 cnb{};
             Raw ro, re;
             emb_load(tile_at(0), ro);
+            if (split) {
+                cc.b = cold_bounds(0);
+                cc.e = cold_entry(cc.b);
+                cold_add(0, cc);
+                if (1 < n_it) {
+                    cc.b = cold_bounds(1);
+                    cc.e = cold_entry(cc.b);
+                }
+                if (2 < n_it) cnb = cold_bounds(2);
+            }
             emb_store(0, ro);
             if (1 < n_it) emb_load(tile_at(1), ro);
             if (2 < n_it) emb_load(tile_at(2), re);
             __syncthreads();
             auto step = [&](int u, Raw& r) {
                 emb_store(u & 1, r);
+                if (split) {
+                    cold_add(u & 1, cc);
+                    if (u + 1 < n_it) {
+                        cc.b = cnb;
+                        cc.e = cold_entry(cc.b);
+                    }
+                    if (u + 2 < n_it) cnb = cold_bounds(u + 2);
+                }
                 if (u + 2 < n_it) emb_load(tile_at(u + 2), r);
                 __syncthreads();
             };
@@ -522,46 +614,75 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
             __syncthreads();  // the consumers' last iteration
             return;
         }
-        // Cross-term waves (instantiated for users in LDS and in global memory, a uniform
-        // choice): bucket bounds four tiles ahead, entries two tiles ahead, the first step of
-        // items (mapped, users loaded) one tile ahead.
+        // Cross-term waves (instantiated per users source: LDS, global memory, or per entry
+        // for split buckets): bucket bounds 64 tiles ahead, entries four tiles ahead, the
+        // first step of items (mapped, users loaded) two tiles ahead.
         const int xw = pw - kStageWaves;
-        auto cross = [&](auto lds_tag) {
-            constexpr bool LU = decltype(lds_tag)::value;
+        auto cross = [&](auto src_tag) {
+            constexpr int SRC = decltype(src_tag)::value;
             int* mark = s_mark[xw];
+            // Bucket bounds of 64 consecutive tiles are held one tile per lane and read with
+            // readlane; the next 64 tiles' are loaded when the current ones start being used,
+            // so no per-tile chain of dependent loads waits on memory.
+            struct BoundsBatch {
+                uint32_t beg, mid, end;
+            };
+            auto bounds_batch = [&](int c) {  // lane i: tile slot 64 c + i
+                BoundsBatch r{0u, 0u, 0u};
+                const int u = 64 * c + lane;
+                if (u < n_it) {
+                    const Bounds b = prod_bounds(a, tile_at(u));
+                    r = BoundsBatch{b.beg, b.mid, b.end};
+                }
+                return r;
+            };
+            BoundsBatch bcur = bounds_batch(0), bnxt = bounds_batch(1);
+            int bc = 0;
+            auto bounds_of = [&](int u) {  // u wave-uniform, never below the current batch
+                if ((u >> 6) > bc) {
+                    bcur = bnxt;
+                    ++bc;
+                    bnxt = bounds_batch(bc + 1);
+                }
+                const int i = u & 63;
+                Bounds b;
+                b.beg = (uint32_t)__builtin_amdgcn_readlane((int)bcur.beg, i);
+                b.mid = (uint32_t)__builtin_amdgcn_readlane((int)bcur.mid, i);
+                b.end = (uint32_t)__builtin_amdgcn_readlane((int)bcur.end, i);
+                return b;
+            };
+            auto entries_of = [&](int u) { return prod_entries(a, bounds_of(u), xw); };
             {
-                const ProdTile p0 = prod_entries(a, prod_bounds(a, tile_at(0)), xw);
-                prod_tile<LU, W64>(a, g, xw, p0, prod_ahead<LU>(a, g, xw, p0, mark, lu), mark, s_acc[0], lu);
+                const ProdTile p0 = entries_of(0);
+                prod_tile<SRC, W64>(a, g, xw, p0, prod_ahead<SRC>(a, g, xw, p0, mark, lu, lh), mark, s_acc[0], lu, lh);
             }
             // Tiles u = 1 .. n_it - 1 are filled in iteration u - 1, with the state kept in two
             // sets (odd and even u). Before the step for tile u its set holds: the first items
-            // of u (mapped, loaded), the entries of u and of u + 2, the bounds of u + 4.
+            // of u (mapped, loaded) and the entries of u, u + 2 and u + 4.
             struct Set {
                 ItemsAhead pa;
-                ProdTile pc, pn;
-                uint2 bn;
+                ProdTile pc, pn, pnn;
             };
             Set so{}, se{};
-            auto entries_of = [&](int u) { return prod_entries(a, prod_bounds(a, tile_at(u)), xw); };
             auto fill = [&](Set& st, int u) {  // prologue: the state before the step for tile u
                 if (u >= n_it) return;
                 st.pc = entries_of(u);
-                st.pa = prod_ahead<LU>(a, g, xw, st.pc, mark, lu);
+                st.pa = prod_ahead<SRC>(a, g, xw, st.pc, mark, lu, lh);
                 if (u + 2 < n_it) st.pn = entries_of(u + 2);
-                if (u + 4 < n_it) st.bn = prod_bounds(a, tile_at(u + 4));
+                if (u + 4 < n_it) st.pnn = entries_of(u + 4);
             };
             fill(so, 1);
             fill(se, 2);
             __syncthreads();
             auto step = [&](int u, Set& st) {
                 const int nb = u & 1;  // buffer of tile u (the consumers read it in iteration u)
-                prod_tile<LU, W64>(a, g, xw, st.pc, st.pa, mark, s_acc[nb], lu);
+                prod_tile<SRC, W64>(a, g, xw, st.pc, st.pa, mark, s_acc[nb], lu, lh);
                 if (u + 2 < n_it) {
-                    st.pa = prod_ahead<LU>(a, g, xw, st.pn, mark, lu);
+                    st.pa = prod_ahead<SRC>(a, g, xw, st.pn, mark, lu, lh);
                     st.pc = st.pn;
                 }
-                if (u + 4 < n_it) st.pn = prod_entries(a, st.bn, xw);
-                if (u + 6 < n_it) st.bn = prod_bounds(a, tile_at(u + 6));
+                if (u + 4 < n_it) st.pn = st.pnn;
+                if (u + 6 < n_it) st.pnn = entries_of(u + 6);
                 __syncthreads();
             };
             for (int u = 1; u < n_it; u += 2) {
@@ -570,8 +691,9 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
             }
             __syncthreads();  // the consumers' last iteration
         };
-        if (users_in_lds) cross(std::true_type{});
-        else cross(std::false_type{});
+        if (split) cross(std::integral_constant<int, kSrcMixed>{});
+        else if (users_in_lds) cross(std::integral_constant<int, kSrcLds>{});
+        else cross(std::integral_constant<int, kSrcGlobal>{});
         return;
     }
 

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "kernels.h"
 
 namespace ebr {
 namespace {
@@ -39,6 +40,7 @@ constexpr int kStagedK = 2048;
 
 struct Ticket {
     uint64_t id = 0;
+    const Index* ix = nullptr;  // the index the query runs on (the server's at submission)
     std::vector<float> user;
     std::vector<int32_t> keys;
     std::vector<float> mult;  // empty: all ones
@@ -74,7 +76,10 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 using namespace ebr;
 
 struct ebr_server {
-    const Index* ix = nullptr;
+    const Index* ix = nullptr;  // the current index: new queries run on it (guarded by mu)
+    // per index: queries submitted to it and not yet completed (plus submissions in progress);
+    // a swap waits until the previous index has none
+    std::unordered_map<const Index*, int64_t> pending;
     int device = 0;
     ebr_server_opts opt{};
     int factor = 1;
@@ -98,15 +103,15 @@ struct ebr_server {
     double busy_ms = 0.0;
     Clock::time_point t_stats;
 
-    int kcount(int k) const {
+    int kcount(const Index& x, int k) const {
         if (k == 0) return 0;
-        return (int)std::min<int64_t>(ix->n_ads, (int64_t)factor * k);
+        return (int)std::min<int64_t>(x.n_ads, (int64_t)factor * k);
     }
 
-    // Slot bytes a batch of these sizes needs: user rows, both outputs, workspace.
-    size_t need(const BatchSizes& z) const {
-        return a256((size_t)z.B * ix->dim * 4) + 2 * a256(4 * (size_t)std::max<int64_t>(1, z.n_out)) +
-               topk_workspace_bytes(*ix, (int)opt.scan_dtype, z);
+    // Slot bytes a batch of these sizes needs on index x: user rows, both outputs, workspace.
+    size_t need(const Index& x, const BatchSizes& z) const {
+        return a256((size_t)z.B * x.dim * 4) + 2 * a256(4 * (size_t)std::max<int64_t>(1, z.n_out)) +
+               topk_workspace_bytes(x, (int)opt.scan_dtype, z);
     }
 
     BatchSizes single(const Ticket& t) const {
@@ -115,7 +120,7 @@ struct ebr_server {
         z.nnz = (int64_t)t.keys.size();
         z.nu = (int)t.keys.size();
         z.bucket_n = t.postings;
-        z.kcmax = kcount(t.k);
+        z.kcmax = kcount(*t.ix, t.k);
         z.n_out = t.k;
         return z;
     }
@@ -144,14 +149,24 @@ void ebr_server::worker(int si) {
                 cv_work.wait_until(lk, deadline);
             }
             if (queue.empty()) continue;
-            const size_t n = std::min<size_t>(queue.size(), (size_t)opt.max_batch);
+            // a batch runs on one index: the head's, up to the first query of a later one
+            size_t n = std::min<size_t>(queue.size(), (size_t)opt.max_batch);
+            for (size_t i = 1; i < n; ++i)
+                if (queue[i]->ix != queue.front()->ix) { n = i; break; }
             take.assign(queue.begin(), queue.begin() + n);
             queue.erase(queue.begin(), queue.begin() + n);
         }
         // admission: first-in first-out while the batch fits the slot
         size_t keep = 0;
         try {
-            std::unordered_set<int32_t> seen;
+            // users per key of the batch so far; a batch of several query groups places the
+            // postings of a key with u users min(u, limit) times at most (split buckets)
+            std::unordered_map<int32_t, uint32_t> users;
+            const Index& bx = *take[0]->ix;
+            const int gq = score_group_queries(bx.dim);
+            uint64_t distinct = 0, expanded = 0;
+            int limit = 1;
+            auto len = [&](int32_t k) { return (uint64_t)(bx.key_post_off[k + 1] - bx.key_post_off[k]); };
             BatchSizes z;
             for (; keep < take.size(); ++keep) {
                 const Ticket& t = *take[keep];
@@ -159,15 +174,30 @@ void ebr_server::worker(int si) {
                 z2.B += 1;
                 z2.nnz += (int64_t)t.keys.size();
                 z2.n_out += t.k;
-                z2.kcmax = std::max(z2.kcmax, kcount(t.k));
-                for (int32_t k : t.keys)
-                    if (!seen.count(k)) {
+                z2.kcmax = std::max(z2.kcmax, kcount(bx, t.k));
+                const int nqg = (z2.B + gq - 1) / gq;
+                const int limit2 = split_groups(nqg) ? cold_user_limit(nqg) : 1;
+                uint64_t distinct2 = distinct, expanded2 = expanded;
+                if (limit2 != limit) {
+                    expanded2 = 0;
+                    for (const auto& kv : users) expanded2 += len(kv.first) * std::min<uint32_t>(kv.second, (uint32_t)limit2);
+                }
+                for (int32_t k : t.keys) {
+                    const auto it = users.find(k);
+                    const uint32_t c = it == users.end() ? 0u : it->second;
+                    if (c == 0) {
                         z2.nu += 1;
-                        z2.bucket_n += (uint64_t)(ix->key_post_off[k + 1] - ix->key_post_off[k]);
+                        distinct2 += len(k);
                     }
+                    if (c < (uint32_t)limit2) expanded2 += len(k);
+                }
+                z2.bucket_n = limit2 > 1 ? expanded2 : distinct2;
                 // the first query always fits (checked at submission)
-                if (keep > 0 && (z2.n_out > out_cap || need(z2) > sl.bytes)) break;
-                for (int32_t k : t.keys) seen.insert(k);
+                if (keep > 0 && (z2.n_out > out_cap || need(bx, z2) > sl.bytes)) break;
+                for (int32_t k : t.keys) users[k] += 1;
+                distinct = distinct2;
+                expanded = expanded2;
+                limit = limit2;
                 z = z2;
             }
         } catch (const std::bad_alloc&) {
@@ -186,7 +216,8 @@ void ebr_server::worker(int si) {
 void ebr_server::run_batch(Slot& sl, std::vector<Ticket*>& take) {
     const auto t0 = Clock::now();
     const int B = (int)take.size();
-    const int d = ix->dim;
+    const Index& bx = *take[0]->ix;  // every query of a batch runs on the same index
+    const int d = bx.dim;
     ebr_status st = EBR_OK;
     std::string err;
     try {
@@ -235,7 +266,7 @@ void ebr_server::run_batch(Slot& sl, std::vector<Ticket*>& take) {
             bt.scan_dtype = f32 ? EBR_F32 : opt.scan_dtype;
             bt.rescore_factor = f32 ? 0 : factor;
             ebr_timings tm{};
-            st = run_topk(*ix, &bt, p, ws_bytes, d_ids, d_scores, sl.stream, &tm, sl.graph);
+            st = run_topk(bx, &bt, p, ws_bytes, d_ids, d_scores, sl.stream, &tm, sl.graph);
         }
         bool inject = false;
         {
@@ -279,6 +310,7 @@ void ebr_server::run_batch(Slot& sl, std::vector<Ticket*>& take) {
         std::lock_guard<std::mutex> lk(mu);
         for (Ticket* t : take) {
             t->done = true;
+            --pending[t->ix];
             t->status = st;
             if (st) {
                 t->err = err;
@@ -331,8 +363,8 @@ ebr_status ebr_server_create(const ebr_index* index, void* scratch, size_t scrat
         z1.B = 1;
         z1.kcmax = 1;
         z1.n_out = 1;
-        if (S->need(z1) > per) {
-            set_error("scratch of %zu bytes per slot cannot hold a one-query batch (%zu bytes)", per, S->need(z1));
+        if (S->need(ix, z1) > per) {
+            set_error("scratch of %zu bytes per slot cannot hold a one-query batch (%zu bytes)", per, S->need(ix, z1));
             delete S;
             return EBR_ENOMEM;
         }
@@ -394,10 +426,34 @@ ebr_status ebr_server_create(const ebr_index* index, void* scratch, size_t scrat
     return EBR_OK;
 }
 
+static ebr_status submit_on(ebr_server* S, const Index& ix, const ebr_query* q, uint32_t* ids_out,
+                            float* scores_out, uint64_t* ticket);
+
 ebr_status ebr_submit(ebr_server* S, const ebr_query* q, uint32_t* ids_out, float* scores_out,
                       uint64_t* ticket) {
     if (!S || !q || !ticket) { set_error("NULL argument"); return EBR_EINVAL; }
-    const Index& ix = *S->ix;
+    // the index of this submission stays alive until it is released below or the query has
+    // completed (a swap waits for both)
+    const Index* cur = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        cur = S->ix;
+        ++S->pending[cur];
+    }
+    auto release = [&](ebr_status s) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            --S->pending[cur];
+        }
+        S->cv_done.notify_all();
+        return s;
+    };
+    const ebr_status r = submit_on(S, *cur, q, ids_out, scores_out, ticket);
+    return r == EBR_OK ? r : release(r);
+}
+
+static ebr_status submit_on(ebr_server* S, const Index& ix, const ebr_query* q, uint32_t* ids_out,
+                            float* scores_out, uint64_t* ticket) {
     if (!q->user_emb) { set_error("user_emb is NULL"); return EBR_EINVAL; }
     if (q->n_feats < 0 || (q->n_feats > 0 && !q->feat_keys)) { set_error("bad feature list"); return EBR_EINVAL; }
     const int64_t kcap = std::min<int64_t>(ix.n_ads, kMaxK / S->factor);
@@ -409,6 +465,7 @@ ebr_status ebr_submit(ebr_server* S, const ebr_query* q, uint32_t* ids_out, floa
         t->keys.assign(q->feat_keys, q->feat_keys + q->n_feats);
         if (q->feat_mult) t->mult.assign(q->feat_mult, q->feat_mult + q->n_feats);
         t->k = q->k;
+        t->ix = &ix;
         t->ids_out = ids_out;
         t->scores_out = scores_out;
         auto reject = [&](ebr_status s) { delete t; return s; };
@@ -421,7 +478,7 @@ ebr_status ebr_submit(ebr_server* S, const ebr_query* q, uint32_t* ids_out, floa
         if (!sk.empty() && (sk.front() < 0 || sk.back() >= ix.n_keys)) { set_error("key out of range [0, %lld)", (long long)ix.n_keys); return reject(EBR_EINVAL); }
         if (std::adjacent_find(sk.begin(), sk.end()) != sk.end()) { set_error("query repeats a key"); return reject(EBR_EINVAL); }
         for (int32_t k : sk) t->postings += (uint64_t)(ix.key_post_off[k + 1] - ix.key_post_off[k]);
-        const size_t need = S->need(S->single(*t));
+        const size_t need = S->need(ix, S->single(*t));
         if (need > S->slots[0].bytes) {
             set_error("query needs %zu bytes of scratch, a slot holds %zu", need, S->slots[0].bytes);
             return reject(EBR_ENOMEM);
@@ -447,6 +504,30 @@ ebr_status ebr_submit(ebr_server* S, const ebr_query* q, uint32_t* ids_out, floa
         set_error("host out of memory");
         return EBR_ENOMEM;
     }
+}
+
+ebr_status ebr_server_swap_index(ebr_server* S, const ebr_index* next) {
+    if (!S || !next) { set_error("NULL argument"); return EBR_EINVAL; }
+    const Index* old = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        old = S->ix;
+    }
+    if (next->dim != old->dim || next->n_ads != old->n_ads) {
+        set_error("the new index must have the same ads and width (%lld x %d), not %lld x %d",
+                  (long long)old->n_ads, old->dim, (long long)next->n_ads, next->dim);
+        return EBR_EINVAL;
+    }
+    if ((S->opt.scan_dtype == EBR_BF16 && !next->emb_bf16) || (S->opt.scan_dtype == EBR_FP8E4M3 && !next->emb_fp8)) {
+        set_error("the new index lacks the server's scan copy");
+        return EBR_EUNSUPPORTED;
+    }
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (S->ix != old) { set_error("another swap is in progress"); return EBR_EAGAIN; }
+    S->ix = next;
+    S->cv_done.wait(lk, [&] { return S->pending[old] == 0; });
+    if (next != old) S->pending.erase(old);
+    return EBR_OK;
 }
 
 ebr_status ebr_poll(ebr_server* S, uint64_t ticket, int32_t timeout_us) {
