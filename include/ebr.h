@@ -104,7 +104,9 @@ typedef struct {
     double upload_ms;        /* host-to-device copy time of the last build */
 } ebr_index_info;
 
-/* Exact arena size (bytes) ebr_build_index needs for desc. Host only; no GPU use. */
+/* Exact arena size (bytes) ebr_build_index needs for desc: the storage of Section 3.4
+ * ("Storage Layout", redesigned as in ebr_build_index) plus the embedding copies. Host only;
+ * no GPU use. */
 ebr_status ebr_index_size(const ebr_build_desc* desc, size_t* arena_bytes);
 
 /*
@@ -147,7 +149,8 @@ ebr_status ebr_build_index_device(const ebr_build_desc* desc, void* scratch, siz
                                   ebr_index** out);
 
 /*
- * Test hook: decode key's list on the GPU from the compressed arena into the
+ * Test hook: decode key's list on the GPU from the compressed arena (the inverse of the
+ * encoding of Section 3.4, "Block Compression", as redesigned here) into the
  * device arrays ids / w of capacity cap; *len (host) receives the list length.
  * Blocking. EBR_ENOMEM if cap < length (nothing written).
  */
@@ -211,7 +214,8 @@ typedef struct {
     int32_t wide64;
 } ebr_batch;
 
-/* Workspace bytes ebr_score_topk / ebr_score_dense need for this batch. Host only. */
+/* Workspace bytes ebr_score_topk / ebr_score_dense need for this batch (its queries are the
+ * inputs of Algorithm 2, Section 3.4). Host only. */
 ebr_status ebr_workspace_size(const ebr_index* index, const ebr_batch* batch, size_t* bytes);
 
 /*
@@ -302,7 +306,8 @@ typedef struct {
 } ebr_tune_report;
 
 /*
- * Autotuner. Runs `batch` (as ebr_score_topk, same workspace and outputs) under the
+ * Autotuner (launch tuning is this library's, not the paper's; the batch is the query input of
+ * Algorithm 2, Section 3.4). Runs `batch` (as ebr_score_topk, same workspace and outputs) under the
  * default shape and then under candidate shapes, one field at a time (score ranges
  * at 1, 2 and 4 work-groups per compute unit; then sample ranges; then 4, 8, 16 and
  * 32 decode chunks per wavefront), `reps` timed runs each (<= 0: 3) after one
@@ -488,7 +493,8 @@ ebr_status ebr_server_create(const ebr_index* index, void* scratch, size_t scrat
                              const ebr_server_opts* opts, ebr_server** out);
 
 /*
- * Queue one query. ids_out (uint32) and scores_out (FP32) are host arrays of
+ * Queue one query: its feature values {(k, w_hat)} (the input of Algorithm 2, Section 3.4),
+ * its user vector and K (top-k retrieval, Section 2). ids_out (uint32) and scores_out (FP32) are host arrays of
  * q->k entries that must stay valid until ebr_poll reports the ticket done;
  * they are written in (score descending, id ascending) order. *ticket
  * identifies the query for ebr_poll. Thread-safe.
@@ -500,7 +506,8 @@ ebr_status ebr_submit(ebr_server* server, const ebr_query* q, uint32_t* ids_out,
                       float* scores_out, uint64_t* ticket);
 
 /*
- * Wait up to timeout_us (< 0: without limit, 0: just look) for a ticket.
+ * Wait up to timeout_us (< 0: without limit, 0: just look) for a ticket (its top-K, as
+ * ebr_score_topk returns it; Section 3.1 and equation "hitmatch", Section 3.3).
  * EBR_OK: results written, the ticket is retired. EBR_EAGAIN: not done yet.
  * A failed batch reports its error (the ticket is retired).
  * EBR_ENOTFOUND: unknown or already retired ticket. Thread-safe.
@@ -531,7 +538,8 @@ ebr_status ebr_server_destroy(ebr_server* server);
 /* ------------------------------------------------------------------------ codec */
 
 /*
- * Host codec of one posting list in the index's chunk format, for tests and
+ * Host codec of one posting list in the index's chunk format (the lossless list compression
+ * of Section 3.4, "Block Compression", redesigned for 64-wide wavefronts), for tests and
  * tools that have no GPU. ids: n strictly increasing uint32. The encoding is
  * ceil(n / 64) 16-byte chunk headers followed by the packed gap words.
  * ebr_codec_size: bytes ebr_codec_encode writes.
@@ -545,7 +553,9 @@ ebr_status ebr_codec_decode(const void* in, size_t bytes, int64_t n, uint32_t* i
 /* ------------------------------------------------------------------------ quantisers */
 
 /*
- * Host reference of the index's reduced-precision encodings, for tests. BF16: round to
+ * Host reference of the index's reduced-precision encodings, for tests (the paper studies no
+ * reduced precision; the copies serve the approximate scan before the exact FP32 rescore of
+ * the K' best, see ebr_batch.scan_dtype). BF16: round to
  * nearest even. FP8: OCP e4m3fn of in[i] / scale, round to nearest even, saturating at
  * +-448; ebr_dequantize_fp8 decodes codes to FP32 (without the scale).
  */
