@@ -35,6 +35,10 @@ constexpr int kStageWaves = 1;
 constexpr int kCrossWaves = kProducerWaves - kStageWaves;
 constexpr int kStageThreads = 64 * kStageWaves;
 
+// Candidate ring: entries per consumer wave and ring half (the mean is below one per tile at
+// the top-K sizes served; a full slice falls back to a direct append).
+constexpr int kRingSlice = 8;
+
 template <bool W64> using AccT = typename std::conditional<W64, unsigned long long, uint32_t>::type;
 
 // Queries per group: 256 (8 consumer waves) up to d = 64 with 32-bit cells, else 128 (4
@@ -90,14 +94,21 @@ __device__ __forceinline__ int acc_idx(int q, int o) {
     return (((q >> 2) * kTileAds + (o ^ ((q >> 2) & 31))) << 2) | (q & 3);
 }
 
-// Rare path of the selection epilogue: append one survivor to its query's candidate buffer.
-// Kept out of line so that the per-row buffer addresses are not hoisted into registers.
-// The candidate's cross-term value is kept beside it when the scan is approximate, for the
-// exact rescore.
-__device__ __attribute__((noinline)) void append_candidate(unsigned long long* cand,
-                                                           uint32_t* cand_cnt, float* cand_wide,
-                                                           int cap, int q, uint32_t key,
-                                                           uint32_t idk, float wide) {
+// (key, id) at or above the threshold (hi, lo), in the order of the selection keys. Evaluated
+// without short-circuit branches: with them, a value selected after the branches (the id of a
+// candidate whose key ties the threshold) was found cleared in the compiled code.
+__device__ __forceinline__ bool key_passes(uint32_t key, uint32_t idk, uint32_t hi, uint32_t lo) {
+    return (key > hi) | ((key == hi) & (idk >= lo));
+}
+
+// Append one survivor to its query's candidate buffer (rare path of the selection epilogue).
+// The empty asm statement hides q's value from the optimizer, so that the per-row buffer
+// addresses of an unrolled row loop are computed here and not hoisted into registers (a call
+// would do the same, but makes the caller save its registers). The candidate's cross-term
+// value is kept beside it when the scan is approximate, for the exact rescore.
+__device__ __forceinline__ void append_candidate(unsigned long long* cand, uint32_t* cand_cnt, float* cand_wide,
+                                                 int cap, int q, uint32_t key, uint32_t idk, float wide) {
+    __asm__ volatile("" : "+v"(q));
     const uint32_t pos = atomicAdd(&cand_cnt[q], 1u);
     if (pos < (uint32_t)cap) {
         cand[(int64_t)q * cap + pos] = ((unsigned long long)key << 32) | (unsigned long long)idk;
@@ -162,19 +173,25 @@ __device__ __forceinline__ EntryItems entry_items(const ScoreArgs& a, int g, uin
                                                   lds_u32* s_hot) {
     EntryItems t;
     uint32_t cnt = 0, u0 = 0, lds = SRC == kSrcLds ? kCoLds : 0u;
-    if (valid) {
-        if (a.packed) {
-            u0 = e.x >> 13;
-            cnt = ((e.x >> kTileShift) & 255u) + 1u;
-        } else if (SRC == kSrcMixed && hot) {
-            const uint32_t h = s_hot[e.x >> kTileShift];
-            u0 = h >> 9;
-            cnt = h & 511u;
-            lds = kCoLds;
+    if (a.packed) {  // wave-uniform; no loads
+        u0 = valid ? e.x >> 13 : 0u;
+        cnt = valid ? ((e.x >> kTileShift) & 255u) + 1u : 0u;
+    } else {
+        // Loads are issued by every lane (lanes without a record read index 0) and their
+        // values selected, so that no load sits in a branch: the compiler then knows how many
+        // loads are in flight at each wait and leaves the prefetched ones outstanding.
+        const bool hl = SRC == kSrcMixed && valid && hot;
+        const bool gl = valid && !hl;
+        const uint32_t slot = gl ? (e.x >> kTileShift) * (uint32_t)a.n_qgroups + (uint32_t)g : 0u;
+        const uint32_t o0 = a.users_off[slot], o1 = a.users_off[slot + 1];
+        if (SRC == kSrcMixed) {
+            const uint32_t h = s_hot[hl ? e.x >> kTileShift : 0u];
+            u0 = hl ? h >> 9 : (gl ? o0 : 0u);
+            cnt = hl ? h & 511u : (gl ? o1 - o0 : 0u);
+            lds = hl ? kCoLds : 0u;
         } else {
-            const uint32_t slot = (e.x >> kTileShift) * (uint32_t)a.n_qgroups + (uint32_t)g;
-            u0 = a.users_off[slot];
-            cnt = a.users_off[slot + 1] - u0;
+            u0 = gl ? o0 : 0u;
+            cnt = gl ? o1 - o0 : 0u;
         }
     }
     t.nch = (cnt + (kUserChunk - 1)) / kUserChunk;
@@ -225,14 +242,32 @@ struct ItemLoad {
     uint32_t valid;
 };
 
-// users[i] from the LDS records or from global memory
+// The item's users[idx[j]] (bit j of valid) from the LDS records or from global memory;
+// users outside valid read index 0 (never added). The reads are unconditional and not
+// selected after the load (see entry_items), so a prefetched item's loads stay in flight. With
+// split buckets a lane's users are in LDS (hot key) or in global memory (warm key); the global
+// reads are issued only when some lane of the wave has a warm item, and then selected at once.
 template <int SRC>
-__device__ __forceinline__ uint2 user_at(const ScoreArgs& a, lds_uint2* lds_users, uint32_t i, uint32_t fl) {
-    if (SRC == kSrcLds || (SRC == kSrcMixed && (fl & kCoLds))) {
-        const unsigned long long v = lds_users[i];
-        return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
-    } else {
-        return reinterpret_cast<const uint2*>(a.users)[i];
+__device__ __forceinline__ void users_load(const ScoreArgs& a, lds_uint2* lds_users, const uint32_t* idx,
+                                           uint32_t valid, uint32_t fl, uint2* ue) {
+    const uint2* gu = reinterpret_cast<const uint2*>(a.users);
+    if (SRC == kSrcGlobal) {
+        #pragma unroll
+        for (int j = 0; j < kUserChunk; ++j) ue[j] = gu[((valid >> j) & 1u) ? idx[j] : 0u];
+        return;
+    }
+    const bool l = SRC == kSrcLds || (fl & kCoLds) != 0u;
+    #pragma unroll
+    for (int j = 0; j < kUserChunk; ++j) {
+        const unsigned long long v = lds_users[((valid >> j) & 1u) && l ? idx[j] : 0u];
+        ue[j] = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+    }
+    if (SRC == kSrcMixed && __ballot(valid != 0u && !l) != 0ull) {
+        uint2 gv[kUserChunk];
+        #pragma unroll
+        for (int j = 0; j < kUserChunk; ++j) gv[j] = gu[((valid >> j) & 1u) && !l ? idx[j] : 0u];
+        #pragma unroll
+        for (int j = 0; j < kUserChunk; ++j) ue[j] = l ? ue[j] : gv[j];
     }
 }
 
@@ -253,13 +288,14 @@ __device__ __forceinline__ ItemLoad item_load(const ScoreArgs& a, const EntryIte
     const bool on = k < t.total && m >= 0;
     const uint32_t fl = co & kCoLds;
     it.valid = 0u;
+    uint32_t idx[kUserChunk];
     #pragma unroll
     for (int j = 0; j < kUserChunk; ++j) {
         const uint32_t uj = c + (uint32_t)j * nch;
-        const bool ok = on && uj < cnt;
-        it.valid |= ok ? (1u << j) : 0u;
-        it.ue[j] = ok ? user_at<SRC>(a, lds_users, u0 + uj, fl) : make_uint2(0u, 0u);
+        it.valid |= on && uj < cnt ? (1u << j) : 0u;
+        idx[j] = u0 + uj;
     }
+    users_load<SRC>(a, lds_users, idx, it.valid, fl, it.ue);
     return it;
 }
 
@@ -273,12 +309,13 @@ __device__ __forceinline__ ItemLoad own_item_load(const ScoreArgs& a, const Entr
     it.o = (int)(t.co & (kTileAds - 1));
     it.w = (int)t.w;
     it.valid = 0u;
+    uint32_t idx[kUserChunk];
     #pragma unroll
     for (int j = 0; j < kUserChunk; ++j) {
-        const bool ok = (uint32_t)j < cnt;
-        it.valid |= ok ? (1u << j) : 0u;
-        it.ue[j] = ok ? user_at<SRC>(a, lds_users, t.u0 + (uint32_t)j, fl) : make_uint2(0u, 0u);
+        it.valid |= (uint32_t)j < cnt ? (1u << j) : 0u;
+        idx[j] = t.u0 + (uint32_t)j;
     }
+    users_load<SRC>(a, lds_users, idx, it.valid, fl, it.ue);
     return it;
 }
 
@@ -343,23 +380,22 @@ __device__ __forceinline__ ItemsAhead items_ahead(const ScoreArgs& a, int g, uin
 // else the tile's whole range (mid = beg: no hot entries).
 __device__ __forceinline__ Bounds prod_bounds(const ScoreArgs& a, uint32_t tile) {
     Bounds b;
-    if (a.n_sub > 1) {
-        const uint32_t* p = a.tile_off + (size_t)tile * (uint32_t)a.n_sub;
-        b.beg = p[0];
-        b.mid = p[1];
-        b.end = p[2];
-    } else {
-        b.beg = b.mid = a.tile_off[tile];
-        b.end = a.tile_off[tile + 1];
-    }
+    const bool split = a.n_sub > 1;
+    const uint32_t* p = a.tile_off + (size_t)tile * (uint32_t)a.n_sub;
+    const uint32_t x0 = p[0], x1 = p[1], x2 = p[split ? 2 : 1];
+    b.beg = x0;
+    b.mid = split ? x1 : x0;
+    b.end = split ? x2 : x1;
     return b;
 }
 
 __device__ __forceinline__ ProdTile prod_entries(const ScoreArgs& a, const Bounds& b, int pw) {
     ProdTile t;
     t.b = b;
+    // every lane loads (lanes past the tile's entries read entry 0): a prefetch in a branch,
+    // or selected right after its load, would make the compiler wait for it at once
     const uint32_t ei = b.beg + (uint32_t)pw + kCrossWaves * (uint32_t)lane_id();
-    t.e0 = ei < b.end ? reinterpret_cast<const uint2*>(a.bucket)[ei] : make_uint2(0u, 0u);
+    t.e0 = reinterpret_cast<const uint2*>(a.bucket)[ei < b.end ? ei : 0u];
     return t;
 }
 
@@ -383,7 +419,8 @@ __device__ __forceinline__ void prod_tile(const ScoreArgs& a, int g, int pw, con
     for (uint32_t base = first + kRound; base < t.b.end; base += kRound) {
         const uint32_t ei = base + kCrossWaves * (uint32_t)lane;
         const bool ok = ei < t.b.end;
-        const uint2 e = ok ? bucket[ei] : make_uint2(0u, 0u);
+        const uint2 v = bucket[ok ? ei : 0u];
+        const uint2 e = ok ? v : make_uint2(0u, 0u);
         item_steps<SRC, W64>(a, entry_items<SRC>(a, g, e, ok, ei < t.b.mid, s_hot), 0u, mark, acc, lds_users);
     }
 }
@@ -451,7 +488,13 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
     __shared__ __attribute__((aligned(16))) float s_thr[GQ];
     __shared__ uint32_t s_thr_hi[GQ];
     __shared__ uint32_t s_thr_lo[GQ];
-    __shared__ uint32_t s_live[GQ];
+    // Candidate ring (collect pass): consumer wave w pushes the cells of iteration it that
+    // reach their row's FP32 threshold, as (row << 5 | ad offset, score bits, cross-term cell
+    // bits), into its slice of half it & 1 and stores their count. In iteration it + 1 the same
+    // wave makes the exact (key, id) comparison and issues the global appends' atomics first,
+    // and writes the candidates at the end, so their latency hides behind the tile's work.
+    __shared__ uint32_t s_ring[2][CW][kRingSlice][3];
+    __shared__ uint32_t s_ring_n[2][CW];
     __shared__ int s_mark[kCrossWaves][64];
     __shared__ uint2 s_users[kUsersLds];
     __shared__ uint32_t s_hot[kHotMax];
@@ -479,6 +522,7 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
     if (n_it <= 0) return;
 
     for (int i = tid; i < 2 * GQ * kTileAds; i += NT) (&s_acc[0][0])[i] = 0;
+    if (tid < 2 * CW) (&s_ring_n[0][0])[tid] = 0u;
     // one query group: its (query, multiplier) users fit in LDS when few enough; split
     // buckets: this group's users of the hot keys (they fit by construction) and the hot-key
     // table
@@ -506,9 +550,6 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
             const bool live = in && a.active[q];
             // key 0 lies below every finite score's key: no threshold, every ad is a candidate
             s_thr[i] = live ? (hi == 0u ? -__builtin_inff() : key_score(hi)) : __builtin_nanf("");
-            s_live[i] = live ? 1u : 0u;
-        } else {
-            s_live[i] = in ? 1u : 0u;
         }
     }
     auto tile_at = [&](int i) -> uint32_t {
@@ -540,7 +581,7 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
                         else r.u[k] = reinterpret_cast<const f32x4*>(a.emb)[(int64_t)t * UNITS + j];
                     }
                 }
-                if (DT == 2 && sl < kTileAds) r.scale = a.fp8_scale[(int64_t)t * kTileAds + sl];
+                if (DT == 2) r.scale = a.fp8_scale[(int64_t)t * kTileAds + (sl & (kTileAds - 1))];
             };
             auto emb_store = [&](int buf, const Raw& r) {
                 #pragma unroll
@@ -566,7 +607,8 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
             };
             auto cold_entry = [&](uint2 b) -> uint2 {
                 const uint32_t i = b.x + (uint32_t)lane;
-                return i < b.y ? bucket[i] : make_uint2(0u, 0u);
+                const uint2 v = bucket[i < b.y ? i : 0u];
+                return i < b.y ? v : make_uint2(0u, 0u);
             };
             auto cold_pair = [&](Acc* acc, uint2 e) {  // (row << 5 | ad offset, term): m' = 1
                 pair_add<W64>(acc, make_uint2(e.x >> kTileShift, 0x3f800000u), (int)(e.x & (kTileAds - 1)), (int)e.y);
@@ -584,33 +626,34 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
                 cc.b = cold_bounds(0);
                 cc.e = cold_entry(cc.b);
                 cold_add(0, cc);
-                if (1 < n_it) {
-                    cc.b = cold_bounds(1);
-                    cc.e = cold_entry(cc.b);
-                }
-                if (2 < n_it) cnb = cold_bounds(2);
+                cc.b = cold_bounds(min(1, n_it - 1));
+                cc.e = cold_entry(cc.b);
+                cnb = cold_bounds(min(2, n_it - 1));
             }
             emb_store(0, ro);
-            if (1 < n_it) emb_load(tile_at(1), ro);
-            if (2 < n_it) emb_load(tile_at(2), re);
+            emb_load(tile_at(min(1, n_it - 1)), ro);
+            emb_load(tile_at(min(2, n_it - 1)), re);
             __syncthreads();
+            // The steady state has one path: past the range the loads repeat the last tile
+            // (never used), and an odd last step is peeled off the loop, so that the compiler
+            // counts the loads in flight exactly and waits only for the set being stored.
             auto step = [&](int u, Raw& r) {
                 emb_store(u & 1, r);
                 if (split) {
                     cold_add(u & 1, cc);
-                    if (u + 1 < n_it) {
-                        cc.b = cnb;
-                        cc.e = cold_entry(cc.b);
-                    }
-                    if (u + 2 < n_it) cnb = cold_bounds(u + 2);
+                    cc.b = cnb;
+                    cc.e = cold_entry(cc.b);
+                    cnb = cold_bounds(min(u + 2, n_it - 1));
                 }
-                if (u + 2 < n_it) emb_load(tile_at(u + 2), r);
+                emb_load(tile_at(min(u + 2, n_it - 1)), r);
                 __syncthreads();
             };
-            for (int u = 1; u < n_it; u += 2) {
+            int u = 1;
+            for (; u + 1 < n_it; u += 2) {
                 step(u, ro);
-                if (u + 1 < n_it) step(u + 1, re);
+                step(u + 1, re);
             }
+            if (u < n_it) step(u, ro);
             __syncthreads();  // the consumers' last iteration
             return;
         }
@@ -627,14 +670,10 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
             struct BoundsBatch {
                 uint32_t beg, mid, end;
             };
-            auto bounds_batch = [&](int c) {  // lane i: tile slot 64 c + i
-                BoundsBatch r{0u, 0u, 0u};
-                const int u = 64 * c + lane;
-                if (u < n_it) {
-                    const Bounds b = prod_bounds(a, tile_at(u));
-                    r = BoundsBatch{b.beg, b.mid, b.end};
-                }
-                return r;
+            auto bounds_batch = [&](int c) {  // lane i: tile slot 64 c + i (lanes past the range:
+                                               // the last tile, never read)
+                const Bounds b = prod_bounds(a, tile_at(min(64 * c + lane, n_it - 1)));
+                return BoundsBatch{b.beg, b.mid, b.end};
             };
             BoundsBatch bcur = bounds_batch(0), bnxt = bounds_batch(1);
             int bc = 0;
@@ -664,12 +703,14 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
                 ProdTile pc, pn, pnn;
             };
             Set so{}, se{};
+            // Past the range every stage works on the last tile again (never added), so the
+            // steady state has one path and the compiler counts the loads in flight exactly.
+            auto cl = [&](int u) { return min(u, n_it - 1); };
             auto fill = [&](Set& st, int u) {  // prologue: the state before the step for tile u
-                if (u >= n_it) return;
-                st.pc = entries_of(u);
+                st.pc = entries_of(cl(u));
                 st.pa = prod_ahead<SRC>(a, g, xw, st.pc, mark, lu, lh);
-                if (u + 2 < n_it) st.pn = entries_of(u + 2);
-                if (u + 4 < n_it) st.pnn = entries_of(u + 4);
+                st.pn = entries_of(cl(u + 2));
+                st.pnn = entries_of(cl(u + 4));
             };
             fill(so, 1);
             fill(se, 2);
@@ -677,18 +718,18 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
             auto step = [&](int u, Set& st) {
                 const int nb = u & 1;  // buffer of tile u (the consumers read it in iteration u)
                 prod_tile<SRC, W64>(a, g, xw, st.pc, st.pa, mark, s_acc[nb], lu, lh);
-                if (u + 2 < n_it) {
-                    st.pa = prod_ahead<SRC>(a, g, xw, st.pn, mark, lu, lh);
-                    st.pc = st.pn;
-                }
-                if (u + 4 < n_it) st.pn = st.pnn;
-                if (u + 6 < n_it) st.pnn = entries_of(u + 6);
+                st.pa = prod_ahead<SRC>(a, g, xw, st.pn, mark, lu, lh);
+                st.pc = st.pn;
+                st.pn = st.pnn;
+                st.pnn = entries_of(cl(u + 6));
                 __syncthreads();
             };
-            for (int u = 1; u < n_it; u += 2) {
+            int u = 1;
+            for (; u + 1 < n_it; u += 2) {
                 step(u, so);
-                if (u + 1 < n_it) step(u + 1, se);
+                step(u + 1, se);
             }
+            if (u < n_it) step(u, so);
             __syncthreads();  // the consumers' last iteration
         };
         if (split) cross(std::integral_constant<int, kSrcMixed>{});
@@ -745,7 +786,7 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
                     if (__ballot(pass) != 0ull && pass) {
                         const uint32_t idk = 0xffffffffu - (uint32_t)ad;
                         const uint32_t key = score_key(sc);
-                        if (key > s_thr_hi[row] || (key == s_thr_hi[row] && idk >= s_thr_lo[row]))
+                        if (key_passes(key, idk, s_thr_hi[row], s_thr_lo[row]))
                             append_candidate(a.cand, a.cand_cnt, a.cand_wide, a.cap, q, key, idk,
                                              wv * sq);
                     }
@@ -787,14 +828,51 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
             }
         }
     }
-    bool wave_live = false;
-    if (q0 < B) {
-        uint32_t any = 0;
-        for (int i = 0; i < 32; ++i) any |= s_live[wave * 32 + i];
-        wave_live = any != 0;
+    bool wave_live = false;  // some query of this wave's 32 rows takes part in this pass
+    {
+        const int q = q0 + (lane & 31);
+        wave_live = __ballot(q < B && (MODE != 0 || a.active[q] != 0u)) != 0ull;
     }
     __syncthreads();
 
+    // Appends of this wave's ring slice of iteration it (entry `lane`): exact comparison with
+    // the row's (key, id) threshold, then the atomic that reserves the slot; the candidate is
+    // written by drain_finish, once the slot has returned.
+    struct Pending {
+        int q;
+        uint32_t key, idk, pos;
+        float wide;
+        bool ok;
+    };
+    auto drain_issue = [&](int it) {
+        Pending p{};
+        const int h = it & 1;
+        int l = lane;
+        __asm__ volatile("" : "+v"(l));  // the slot address is computed here, not kept live
+        const int wv = __builtin_amdgcn_readfirstlane(wave);  // wave-uniform: scalar address math
+        if ((uint32_t)l < s_ring_n[h][wv]) {
+            const uint32_t* e = s_ring[h][wv][l];
+            const uint32_t x = e[0];
+            const int ql = (int)(x >> kTileShift);
+            const uint32_t key = score_key(__uint_as_float(e[1]));
+            const uint32_t idk = 0xffffffffu - (uint32_t)((int64_t)tile_at(it) * kTileAds + (x & (kTileAds - 1)));
+            if (key_passes(key, idk, s_thr_hi[ql], s_thr_lo[ql])) {
+                p.q = qbase + ql;
+                p.key = key;
+                p.idk = idk;
+                p.wide = __uint_as_float(e[2]) * s_qscale[ql];
+                p.pos = atomicAdd(&a.cand_cnt[p.q], 1u);
+                p.ok = true;
+            }
+        }
+        return p;
+    };
+    auto drain_finish = [&](const Pending& p) {
+        if (p.ok && p.pos < (uint32_t)a.cap) {
+            a.cand[(int64_t)p.q * a.cap + p.pos] = ((unsigned long long)p.key << 32) | (unsigned long long)p.idk;
+            if (a.cand_wide) a.cand_wide[(int64_t)p.q * a.cap + p.pos] = p.wide;
+        }
+    };
     // this lane's rows: group g4 (0..3) holds rows rg(g4) .. rg(g4) + 3 of the group's 256
     auto rg = [&](int g4) { return wave * 32 + 8 * g4 + 4 * (lane >> 5); };
     const int o = lane & 31;
@@ -812,6 +890,9 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
             __syncthreads();
             return;
         }
+        // the survivors of iteration it - 1: their appends' atomics are issued now
+        Pending pd{};
+        if (MODE == 0 && it > 0) pd = drain_issue(it - 1);
         // products first: the tile's B operands are read from LDS up to eight quads ahead of
         // the products that use them, so one LDS latency is exposed per tile
         const uint32_t tile = tile_at(it);
@@ -854,7 +935,7 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
         const int64_t ad = (int64_t)tile * kTileAds + o;
         const bool ad_ok = ad < a.n_ads;
         float sc[16];
-        uint64_t pass = 0;  // lanes with a cell at or above its row's threshold
+        uint32_t pm = 0;  // bit r: this lane's cell r is at or above its row's FP32 threshold
         // sample pass: row base of this wave's block plus a 32-bit offset per row
         uint32_t* skeys = MODE == 1 ? a.sample_keys + (int64_t)q0 * a.sample_ld : nullptr;
         const uint32_t scol = (uint32_t)(first + it) * kTileAds + (uint32_t)o;
@@ -879,29 +960,48 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
                         skeys[(uint32_t)rl * (uint32_t)a.sample_ld + scol] = ad_ok ? score_key(fmaf(wd[4 * g4 + k], sq[k], deep)) : 0u;
                 } else {
                     sc[4 * g4 + k] = fmaf(wd[4 * g4 + k], sq[k], deep);
-                    pass |= __ballot(sc[4 * g4 + k] >= th[k]);  // NaN threshold: never
+                    pm |= sc[4 * g4 + k] >= th[k] ? 1u << (4 * g4 + k) : 0u;  // NaN threshold: never
                 }
             }
         }
-        if (MODE == 0 && (pass & __ballot(ad_ok)) != 0ull) {
-            // rare: exact (key, id) comparison against the threshold, then append
-            if (ad_ok) {
-                const uint32_t idk = 0xffffffffu - (uint32_t)ad;
+        if (MODE == 0) {
+            // rare: push this wave's cells at or above the FP32 threshold into its ring slice
+            // (the stager makes the exact comparison); a full slice appends directly
+            if (!ad_ok) pm = 0u;
+            uint32_t n = 0;  // wave-uniform
+            if (__ballot(pm != 0u) != 0ull) {
                 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int ql = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    if (sc[r] >= s_thr[ql]) {
-                        const uint32_t key = score_key(sc[r]);
-                        if (key > s_thr_hi[ql] || (key == s_thr_hi[ql] && idk >= s_thr_lo[ql]))
-                            append_candidate(a.cand, a.cand_cnt, a.cand_wide, a.cap, qbase + ql, key, idk,
-                                             wd[r] * s_qscale[ql]);
+                    const uint64_t bl = __ballot((pm >> r) & 1u);
+                    if (bl == 0ull) continue;
+                    if ((pm >> r) & 1u) {
+                        int ql = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                        __asm__ volatile("" : "+v"(ql));  // per-row addresses computed here, not hoisted
+                        const uint32_t slot = n + (uint32_t)__builtin_amdgcn_mbcnt_hi(
+                                                          (uint32_t)(bl >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bl, 0u));
+                        if (slot < (uint32_t)kRingSlice) {
+                            uint32_t* e = s_ring[cur][wave][slot];
+                            e[0] = ((uint32_t)ql << kTileShift) | (uint32_t)o;
+                            e[1] = __float_as_uint(sc[r]);
+                            e[2] = __float_as_uint(wd[r]);
+                        } else {
+                            const uint32_t key = score_key(sc[r]);
+                            const uint32_t idk = 0xffffffffu - (uint32_t)ad;
+                            if (key_passes(key, idk, s_thr_hi[ql], s_thr_lo[ql]))
+                                append_candidate(a.cand, a.cand_cnt, a.cand_wide, a.cap, qbase + ql, key, idk,
+                                                 wd[r] * s_qscale[ql]);
+                        }
                     }
+                    n += (uint32_t)__builtin_popcountll(bl);
                 }
             }
+            if (lane == 0) s_ring_n[cur][wave] = min(n, (uint32_t)kRingSlice);
+            drain_finish(pd);
         }
         __syncthreads();
     };
     for (int it = 0; it < n_it; ++it) iter(it);
+    if (MODE == 0 && wave_live) drain_finish(drain_issue(n_it - 1));
 }
 
 // Exact FP32 rescore of the Kc approximate-best candidates of query q (one work-group): each
