@@ -160,6 +160,8 @@ def main():
                     help="timed batches of the 4096-query uneven batch (0: skip)")
     ap.add_argument("--refresh-runs", type=int, default=2,
                     help="device builds of the benchmark index (online refresh) to time (0: skip)")
+    ap.add_argument("--wide-steps", type=int, default=3,
+                    help="timed batches of the d = 128 point (widened towers; 0 skips it)")
     ap.add_argument("--binary-steps", type=int, default=5,
                     help="timed batches of the same queries on an ids-only copy of the index "
                          "(the paper's binary L, multipliers w x per feature; 0: skip)")
@@ -381,6 +383,50 @@ def main():
         log(f"[bench] binary L: {qb:.0f} queries/s, decode {binary['phases_ms']['decode_ms']:.3f} ms "
             f"(weighted {phase['decode_ms']:.3f}), k_score {binary['phases_ms']['score_ms']:.3f} ms")
 
+    # widened towers (Section 3.2, the IPNN concatenation): the same lists and queries with
+    # d = 128 ad and user rows, FP32 scan and BF16 scan + FP32 rescore, each checked against
+    # the oracle on a few queries
+    wide = None
+    if args.wide_steps > 0:
+        t1 = time.time()
+        ww = W.widened(wl, 128)
+        ixw = E.Index.from_workload(ww, device=dev, dtypes=1 | (1 << E.BF16))
+        log(f"[bench] d = 128 index built in {time.time() - t1:.1f}s")
+        Uw = torch.from_numpy(np.ascontiguousarray(ww.user_emb)).to(dev)
+        wide = {"workload": "the same lists and 256 queries with 128-d towers (N(0,1), normalised)",
+                "n_ads": N, "dim": 128}
+        wout = {}
+        for name, dt in (("f32", E.F32), ("bf16", E.BF16)):
+            for i in range(2):
+                ixw.score_topk(Uw, ww.feat_offsets, ww.feat_keys, ww.k, ww.feat_mult, scan_dtype=dt,
+                               rescore_factor=4, out=out)
+            torch.cuda.synchronize()
+            tt = []
+            t1 = time.perf_counter()
+            for i in range(args.wide_steps):
+                ixw.score_topk(Uw, ww.feat_offsets, ww.feat_keys, ww.k, ww.feat_mult, scan_dtype=dt,
+                               rescore_factor=4, out=out)
+                tt.append(E.last_timings())
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t1
+            wout[name] = (out[0].cpu().numpy().view(np.uint32).copy(), out[1].cpu().numpy().copy())
+            first_ms = float(np.mean([t.get("score_first_ms", 0.0) for t in tt]))
+            wide[name] = {"queries_per_s": B * args.wide_steps / el,
+                          "ms_per_batch": 1000 * el / args.wide_steps,
+                          # the collect pass's products: 2 B N d flops
+                          "score_tflops": 2.0 * B * N * 128 / (first_ms * 1e-3) / 1e12 if first_ms > 0 else None,
+                          "phases_ms": {k: float(np.mean([t[k] for t in tt]))
+                                        for k in ("decode_ms", "sample_ms", "score_ms", "finalize_ms", "rescore_ms")}}
+            log(f"[bench] d = 128 {name}: {wide[name]['queries_per_s']:.0f} queries/s "
+                f"({wide[name]['ms_per_batch']:.2f} ms/batch)")
+        if args.cpu_seconds > 0:
+            wleg = oracle_leg(ww, 1e9, max_queries=8)
+            wide["parity"] = {name: check_outputs(ww, wleg, o[0], o[1], out_offs, f"d128 {name}")
+                              for name, o in wout.items()}
+            del wleg
+        ixw.close()
+        del ww, Uw
+
     # online refresh: the same index rebuilt on the GPU from lists and embeddings already in
     # device memory (ebr_build_index_device), against the host build's encode + upload
     refresh = None
@@ -488,6 +534,9 @@ def main():
         parity = {name: check_outputs(wl, leg, o[0], o[1], out_offs, name) for name, o in outputs.items()}
         if binary is not None and "parity" in binary:
             parity["binary_L"] = binary["parity"]
+        if wide is not None and "parity" in wide:
+            for name, v in wide["parity"].items():
+                parity["d128_" + name] = v
         parity["ok"] = all(v["failures"] == 0 for v in parity.values() if isinstance(v, dict))
         log(f"[bench] parity of the timed outputs vs the oracle: {parity}")
         del leg
@@ -526,6 +575,7 @@ def main():
         "precision": precision,
         "batching": batching,
         "binary_L": binary,
+        "wide_d128": wide,
         "refresh": refresh,
         "serving": serving,
     }

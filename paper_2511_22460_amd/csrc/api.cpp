@@ -7,11 +7,13 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -85,10 +87,82 @@ struct PhaseClock {
 
 // ------------------------------------------------------------------ host threading
 
+// Host threads for the planner and the index encoder: the machine's, at most 16 (the CPU
+// share of one GPU on the hosts served).
 static int host_threads() {
     unsigned n = std::thread::hardware_concurrency();
     if (n == 0) n = 4;
-    return (int)std::min(n, 32u);
+    return (int)std::min(n, 16u);
+}
+
+// Persistent workers for the planner's parallel loops (a thread per slice would cost tens of
+// microseconds to start, several times per batch). One loop runs on the pool at a time; a
+// loop started while the pool is busy (another batch being planned on another thread) runs
+// its slices with threads of its own.
+class HostPool {
+  public:
+    explicit HostPool(int n) {
+        for (int i = 0; i < n; ++i) workers_.emplace_back([this] { work(); });
+    }
+    ~HostPool() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : workers_) t.join();
+    }
+    int size() const { return (int)workers_.size(); }
+    // fn(t) for t in [0, n): the caller runs slice 0, the workers the rest; false if busy
+    bool run(int n, const std::function<void(int)>& fn) {
+        std::unique_lock<std::mutex> busy(run_mu_, std::try_to_lock);
+        if (!busy.owns_lock()) return false;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            fn_ = &fn;
+            n_ = n;
+            next_ = 1;
+            left_ = n - 1;
+            ++gen_;
+        }
+        cv_.notify_all();
+        fn(0);
+        std::unique_lock<std::mutex> lk(mu_);
+        done_.wait(lk, [this] { return left_ == 0; });
+        fn_ = nullptr;
+        return true;
+    }
+
+  private:
+    void work() {
+        uint64_t seen = 0;
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            cv_.wait(lk, [&] { return stop_ || (gen_ != seen && next_ < n_); });
+            if (stop_) return;
+            seen = gen_;
+            while (next_ < n_) {
+                const int t = next_++;
+                const std::function<void(int)>* f = fn_;
+                lk.unlock();
+                (*f)(t);
+                lk.lock();
+                if (--left_ == 0) done_.notify_all();
+            }
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::mutex mu_, run_mu_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)>* fn_ = nullptr;
+    int n_ = 0, next_ = 0, left_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+
+static HostPool& host_pool() {
+    static HostPool pool(host_threads() - 1);
+    return pool;
 }
 
 // Calls fn(begin, end) on nt contiguous slices of [0, n).
@@ -97,13 +171,16 @@ static void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>&
     int nt = host_threads();
     if (n < min_per_thread * 2) nt = 1;
     if (nt <= 1) { fn(0, n); return; }
+    const int64_t per = (n + nt - 1) / nt;
+    const int ns = (int)((n + per - 1) / per);
+    auto slice = [&](int t) {
+        const int64_t b = t * per, e = std::min(n, b + per);
+        if (b < e) fn(b, e);
+    };
+    if (host_pool().run(ns, slice)) return;
     std::vector<std::thread> th;
-    int64_t per = (n + nt - 1) / nt;
-    for (int t = 0; t < nt; ++t) {
-        int64_t b = t * per, e = std::min(n, b + per);
-        if (b >= e) break;
-        th.emplace_back(fn, b, e);
-    }
+    for (int t = 1; t < ns; ++t) th.emplace_back(slice, t);
+    slice(0);
     for (auto& x : th) x.join();
 }
 
@@ -743,29 +820,15 @@ struct Plan {
     size_t total = 0;
 };
 
-// Per-thread planner scratch sized to the key space: a stamp per key (duplicate check within a
-// query, one generation per query) and a slot per key (distinct keys of a batch; all -1
-// between calls).
+// Per-thread planner scratch sized to the key space: a slot per key (distinct keys of a batch;
+// all -1 between calls).
 struct PlanScratch {
-    std::vector<uint32_t> stamp;
     std::vector<int32_t> slot_of;
-    uint32_t gen = 0;
-    uint32_t next_gen() {
-        if (++gen == 0) {
-            std::fill(stamp.begin(), stamp.end(), 0u);
-            gen = 1;
-        }
-        return gen;
-    }
 };
 
 static PlanScratch& plan_scratch(int64_t n_keys) {
     static thread_local PlanScratch ps;
-    if ((int64_t)ps.stamp.size() < n_keys) {
-        ps.stamp.assign((size_t)n_keys, 0u);
-        ps.slot_of.assign((size_t)n_keys, -1);
-        ps.gen = 0;
-    }
+    if ((int64_t)ps.slot_of.size() < n_keys) ps.slot_of.assign((size_t)n_keys, -1);
     return ps;
 }
 
@@ -906,21 +969,40 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     if (nnz > 0 && !bt->feat_keys) { set_error("feat_keys is NULL"); return EBR_EINVAL; }
     P->nnz = nnz;
     if (nnz >= (1LL << 31)) { set_error("more than 2^31 features in one batch"); return EBR_EINVAL; }
-    // keys in range, distinct within a query (a per-key stamp of the query being checked);
-    // multipliers finite
+    // keys in range, distinct within a query, multipliers finite; and the distinct keys of
+    // the batch, in order of first use, with each feature's key slot (one pass: a key's slot,
+    // then the last query that used the slot)
     PlanScratch& ps = plan_scratch(ix.n_keys);
-    for (int q = 0; q < B; ++q) {
-        const int64_t f0 = bt->feat_offsets[q], f1 = bt->feat_offsets[q + 1];
-        const uint32_t gen = ps.next_gen();
-        for (int64_t j = f0; j < f1; ++j) {
-            const int32_t k = bt->feat_keys[j];
-            if (k < 0 || k >= ix.n_keys) { set_error("query %d: key %d out of range [0, %lld)", q, k, (long long)ix.n_keys); return EBR_EINVAL; }
-            if (ps.stamp[k] == gen) { set_error("query %d repeats a key", q); return EBR_EINVAL; }
-            ps.stamp[k] = gen;
+    std::vector<int32_t> uk;
+    std::vector<int32_t> slot(nnz);
+    {
+        std::vector<int32_t> last_q;
+        auto undo = [&]() { for (int32_t k : uk) ps.slot_of[k] = -1; };
+        for (int q = 0; q < B; ++q) {
+            const int64_t f0 = bt->feat_offsets[q], f1 = bt->feat_offsets[q + 1];
+            for (int64_t j = f0; j < f1; ++j) {
+                const int32_t k = bt->feat_keys[j];
+                if (k < 0 || k >= ix.n_keys) {
+                    undo();
+                    set_error("query %d: key %d out of range [0, %lld)", q, k, (long long)ix.n_keys);
+                    return EBR_EINVAL;
+                }
+                int32_t sl = ps.slot_of[k];
+                if (sl < 0) {
+                    sl = (int32_t)uk.size();
+                    ps.slot_of[k] = sl;
+                    uk.push_back(k);
+                    last_q.push_back(-1);
+                }
+                if (last_q[sl] == q) { undo(); set_error("query %d repeats a key", q); return EBR_EINVAL; }
+                last_q[sl] = q;
+                slot[j] = sl;
+            }
+            if (bt->feat_mult)
+                for (int64_t j = f0; j < f1; ++j)
+                    if (!std::isfinite(bt->feat_mult[j])) { undo(); set_error("query %d: non-finite multiplier", q); return EBR_EINVAL; }
         }
-        if (bt->feat_mult)
-            for (int64_t j = f0; j < f1; ++j)
-                if (!std::isfinite(bt->feat_mult[j])) { set_error("query %d: non-finite multiplier", q); return EBR_EINVAL; }
+        undo();
     }
     P->kq.assign(B, 0);
     P->kmax = 0;
@@ -944,20 +1026,6 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         P->kcnt[q] = (int32_t)kc;
         P->kcmax = std::max(P->kcmax, (int)kc);
     }
-    // distinct keys of the batch, in order of first use, and each feature's key slot
-    std::vector<int32_t> uk;
-    std::vector<int32_t> slot(nnz);
-    for (int64_t j = 0; j < nnz; ++j) {
-        const int32_t k = bt->feat_keys[j];
-        int32_t sl = ps.slot_of[k];
-        if (sl < 0) {
-            sl = (int32_t)uk.size();
-            ps.slot_of[k] = sl;
-            uk.push_back(k);
-        }
-        slot[j] = sl;
-    }
-    for (int32_t k : uk) ps.slot_of[k] = -1;
     const int nu = (int)uk.size();
     if (nu >= (1 << (32 - kSuperShift))) { set_error("too many distinct keys in one batch"); return EBR_EINVAL; }
     P->nu = nu;
@@ -986,9 +1054,14 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
             }
         // per (non-cold key, group): users
         std::vector<uint32_t> cnt(by_len.size() * (size_t)nqg, 0u);
-        for (int q = 0; q < B; ++q)
-            for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j)
-                if (cand[slot[j]] >= 0) cnt[(size_t)cand[slot[j]] * nqg + q / P->gq]++;
+        parallel_for(nqg, [&](int64_t g0, int64_t g1) {  // a group's queries touch its column only
+            for (int64_t g = g0; g < g1; ++g) {
+                const int q1 = std::min(B, (int)(g + 1) * P->gq);
+                for (int q = (int)g * P->gq; q < q1; ++q)
+                    for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j)
+                        if (cand[slot[j]] >= 0) cnt[(size_t)cand[slot[j]] * nqg + g]++;
+            }
+        }, 1);
         std::sort(by_len.begin(), by_len.end());
         const uint32_t cap = (uint32_t)score_users_lds(ix.dim, P->w64);
         std::vector<uint32_t> hu(nqg, 0u);
@@ -1056,7 +1129,28 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
             for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j)
                 P->users_off[(size_t)slot[j] * nqg + g + 1]++;
     });
-    for (size_t i = 1; i < P->users_off.size(); ++i) P->users_off[i] += P->users_off[i - 1];
+    {
+        // inclusive prefix of users_off in place: per-slice sums, their prefix, then each slice
+        std::vector<uint32_t>& uo = P->users_off;
+        const int64_t n = (int64_t)uo.size();
+        const int ns = 16;
+        const int64_t per = (n + ns - 1) / ns;
+        std::vector<uint32_t> part(ns + 1, 0u);
+        parallel_for(ns, [&](int64_t t0, int64_t t1) {
+            for (int64_t t = t0; t < t1; ++t) {
+                uint32_t acc = 0;
+                for (int64_t i = t * per, e = std::min(n, (t + 1) * per); i < e; ++i) acc += uo[(size_t)i];
+                part[(size_t)t + 1] = acc;
+            }
+        }, 1);
+        for (int t = 0; t < ns; ++t) part[(size_t)t + 1] += part[(size_t)t];
+        parallel_for(ns, [&](int64_t t0, int64_t t1) {
+            for (int64_t t = t0; t < t1; ++t) {
+                uint32_t acc = part[(size_t)t];
+                for (int64_t i = t * per, e = std::min(n, (t + 1) * per); i < e; ++i) uo[(size_t)i] = acc += uo[(size_t)i];
+            }
+        }, 1);
+    }
     // per-query fixed-point scale of the cross term: the largest S with
     // sum_j |m_j| max|W[k_j,:]| 2^S (1 + 2^-23) + F_q + 1 below 2^31 (2^63 for 64-bit cells), so
     // that every (query, ad) sum of rounded terms fits the cell; a sum's rounding error is at
@@ -1066,7 +1160,7 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     P->aq.assign(B, 0.0);
     P->werr.assign(B, 0.0f);
     const int cell_bits = P->w64 ? 63 : 31;
-    for (int q = 0; q < B; ++q) {
+    parallel_for(B, [&](int64_t q0, int64_t q1) { for (int64_t q = q0; q < q1; ++q) {
         double A = 0.0;
         const int64_t F = bt->feat_offsets[q + 1] - bt->feat_offsets[q];
         for (int64_t j = bt->feat_offsets[q]; j < bt->feat_offsets[q + 1]; ++j) {
@@ -1085,7 +1179,7 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         Sq[q] = S;
         P->qinv[q] = std::ldexp(1.0, -S);
         P->werr[q] = (float)std::ldexp((double)F, -S - 1);
-    }
+    } }, 64);
     // users: (query within its group, bits of m' = m * 2^(S_q - Sw_k) in FP32), in query order;
     // |m'| <= 2^(e(max|W_k|) - e(A_q) + 1) |m| max|W_k| / max|W_k| stays far from overflow
     P->users.assign((size_t)2 * std::max<int64_t>(1, nnz), 0u);

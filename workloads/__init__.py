@@ -258,6 +258,19 @@ def binary(wl: Workload, seed_tag: int = 7) -> Workload:
                     recipe)
 
 
+def widened(wl: Workload, dim: int, seed_tag: int = 11) -> Workload:
+    """The same lists and queries with towers of width `dim` (Section 3.2: the IPNN
+    concatenation lengthens both vectors): new seeded ad and user rows, N(0, 1) per element
+    and L2-normalised, from seed + seed_tag."""
+    seed = int(wl.recipe.get("seed", BASE_SEED)) + seed_tag
+    A = normal_rows(seed, 1, wl.n_ads, dim)
+    U = normal_rows(seed, 2, wl.n_queries, dim)
+    recipe = dict(wl.recipe)
+    recipe.update({"dim": dim, "tower_seed": seed})
+    return Workload(wl.name + f"+d{dim}", wl.n_ads, dim, wl.n_keys, A, wl.key_offsets, wl.post_ids,
+                    wl.post_w, U, wl.feat_offsets, wl.feat_keys, wl.feat_mult, wl.k, recipe)
+
+
 def make(name: str = "c1", **over) -> Workload:
     """Build a workload from a named recipe, with optional overrides of any recipe field.
 
