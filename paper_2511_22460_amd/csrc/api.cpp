@@ -1714,6 +1714,7 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
         if (approx) HIP_TRY(hipMemcpyAsync(&nunc, unc, 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (hc.error & 1u) { set_error("non-finite user embedding in the batch"); return EBR_EINVAL; }
+        if (hc.error & 4u) { set_error("internal error: a rescore candidate id lies outside the inventory"); return EBR_EDEVICE; }
         int rounds_run = 1;
         for (int r = 0; r + 1 < kMaxRounds; ++r) rounds_run += hc.unres[r] > 0 ? 1 : 0;
         // rare: still unresolved after the enqueued rounds; continue round by round

@@ -48,7 +48,8 @@ inline int cold_user_limit(int n_qg) { return n_qg; }
 
 // Per-batch control block (device, in the workspace).
 struct Control {
-    uint32_t error;                   // bit 0: non-finite user row; bit 1: not converged
+    uint32_t error;                   // bit 0: non-finite user row; bit 1: not converged;
+                                      // bit 2: a rescore candidate id out of range
     uint32_t unres[kMaxRounds];       // queries left unresolved by round r
     uint32_t uncertified;             // reduced-precision scans: failed certificates
     uint32_t imprecise;               // queries whose 32-bit cross term missed kWideTau
@@ -184,7 +185,7 @@ struct RescoreArgs {
     const float* eps;                 // per query: bound on |approximate - exact| score
     const float* werr;                // per query: cross-term rounding bound, or null
     uint32_t* imprecise;
-    const Control* ctl;
+    Control* ctl;                     // bit 2 of error: a candidate id outside the inventory
     const uint32_t* skip;             // non-null and nonzero: selection unfinished, do nothing
     int32_t r_ld;
     const int64_t* out_off;

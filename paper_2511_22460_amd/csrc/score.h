@@ -1032,7 +1032,11 @@ __global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
     // bits; the cross term is the scan's exact value.
     const f32x4* emb = reinterpret_cast<const f32x4*>(a.emb);
     for (int r = tid; r < Kc; r += 1024) {
-        const uint32_t id = a.r_id[(int64_t)q * a.r_ld + r];
+        uint32_t id = a.r_id[(int64_t)q * a.r_ld + r];
+        if ((int64_t)id >= a.n_ads) {  // never from a correct scan: report, read a valid row
+            if (a.ctl) atomicOr(&a.ctl->error, 4u);
+            id = 0u;
+        }
         const int64_t b = id >> kTileShift;
         const int o = (int)(id & (kTileAds - 1));
         f32x4 e0[NQ], e1[NQ];
