@@ -1133,7 +1133,7 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         // inclusive prefix of users_off in place: per-slice sums, their prefix, then each slice
         std::vector<uint32_t>& uo = P->users_off;
         const int64_t n = (int64_t)uo.size();
-        const int ns = 16;
+        const int ns = n > (1 << 18) ? 16 : 1;
         const int64_t per = (n + ns - 1) / ns;
         std::vector<uint32_t> part(ns + 1, 0u);
         parallel_for(ns, [&](int64_t t0, int64_t t1) {
@@ -1179,7 +1179,7 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
         Sq[q] = S;
         P->qinv[q] = std::ldexp(1.0, -S);
         P->werr[q] = (float)std::ldexp((double)F, -S - 1);
-    } }, 64);
+    } }, nnz > (1 << 16) ? 64 : std::max(B, 1));  // small batches: one thread (waking the pool costs more)
     // users: (query within its group, bits of m' = m * 2^(S_q - Sw_k) in FP32), in query order;
     // |m'| <= 2^(e(max|W_k|) - e(A_q) + 1) |m| max|W_k| / max|W_k| stays far from overflow
     P->users.assign((size_t)2 * std::max<int64_t>(1, nnz), 0u);
@@ -1242,6 +1242,18 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
                     }
             }
         }, 8192);
+    }
+    // the kernel reads each user's row as its cell code (acc_row_code); the cold records
+    // above keep the query index
+    {
+        const uint32_t n = P->users_off.back();
+        parallel_for(n, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) P->users[2 * i] = acc_row_code(P->users[2 * i], P->w64);
+        }, 1 << 16);
+        const uint32_t nh = P->split ? P->hot_users_off[nqg] : 0u;
+        parallel_for(nh, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) P->hot_users[2 * i] = acc_row_code(P->hot_users[2 * i], P->w64);
+        }, 1 << 16);
     }
     // output offsets
     P->out_off.assign(B + 1, 0);

@@ -46,6 +46,17 @@ constexpr int kSplitMaxGroups = 62;
 inline bool split_groups(int n_qg) { return n_qg > 1 && n_qg <= kSplitMaxGroups; }
 inline int cold_user_limit(int n_qg) { return n_qg; }
 
+// The cross-term cell of query row q (within its group) and ad offset o sits at byte
+// B(q) + ((o << s) ^ X(q)) of the LDS accumulator tile, s = 4 for 32-bit and 5 for 64-bit cells
+// (rows grouped by four, the column XOR-swizzled by the row group; the layout is acc_idx in
+// score.h): B(q) = (q >> 2) 128 c + (q & 3) c and X(q) = ((q >> 2) & 31) << s with c the cell
+// bytes. A user record carries code = B | X << 16 instead of its row, so that a pair's cell
+// address is three instructions.
+inline constexpr uint32_t acc_row_code(uint32_t q, bool w64) {
+    return w64 ? (((q >> 2) * 1024u + (q & 3u) * 8u) | ((((q >> 2) & 31u) << 5) << 16))
+               : (((q >> 2) * 512u + (q & 3u) * 4u) | ((((q >> 2) & 31u) << 4) << 16));
+}
+
 // Per-batch control block (device, in the workspace).
 struct Control {
     uint32_t error;                   // bit 0: non-finite user row; bit 1: not converged;

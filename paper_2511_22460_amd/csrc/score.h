@@ -90,9 +90,22 @@ __device__ __forceinline__ void clear4(unsigned long long* p) {
 // consecutive rows one lane of the 32x32 matrix-core tile owns are adjacent (two 16-byte
 // LDS reads); the ad column is XOR-swizzled by the row group so that the users of one posting
 // (same ad, many rows) spread over the banks.
-__device__ __forceinline__ int acc_idx(int q, int o) {
+__host__ __device__ constexpr int acc_idx(int q, int o) {
     return (((q >> 2) * kTileAds + (o ^ ((q >> 2) & 31))) << 2) | (q & 3);
 }
+
+// the user records' cell codes (acc_row_code) address the same cells as acc_idx
+constexpr bool acc_codes_match() {
+    for (int w = 0; w < 2; ++w)
+        for (int q = 0; q < 256; ++q)
+            for (int o = 0; o < kTileAds; ++o) {
+                const uint32_t c = acc_row_code((uint32_t)q, w == 1);
+                const uint32_t byte = (c & 0xffffu) + (((uint32_t)o << (w ? 5 : 4)) ^ (c >> 16));
+                if (byte != (uint32_t)acc_idx(q, o) * (w ? 8u : 4u)) return false;
+            }
+    return true;
+}
+static_assert(acc_codes_match(), "cell codes and acc_idx disagree");
 
 // (key, id) at or above the threshold (hi, lo), in the order of the selection keys. Evaluated
 // without short-circuit branches: with them, a value selected after the branches (the id of a
@@ -319,16 +332,18 @@ __device__ __forceinline__ ItemLoad own_item_load(const ScoreArgs& a, const Entr
     return it;
 }
 
-// One (query, posting) pair: round(fl(m' * w')) into the query's cell (users hold m' bits,
-// bucket entries w' bits). A cold pair of split buckets arrives as m' = 1 and w' = its
-// rounded term, which this reproduces exactly.
+// One (query, posting) pair: round(fl(m' * w')) into the query's cell (users hold the row's
+// cell code (acc_row_code) and m' bits, bucket entries w' bits). A cold pair of split buckets
+// arrives as m' = 1 and w' = its rounded term, which this reproduces exactly.
 template <bool W64>
 __device__ __forceinline__ void pair_add(AccT<W64>* acc, uint2 ue, int o, int w) {
     const float p = __uint_as_float(ue.y) * __uint_as_float((uint32_t)w);
+    const uint32_t byte = (ue.x & 0xffffu) + (((uint32_t)o << (W64 ? 5 : 4)) ^ (ue.x >> 16));
+    AccT<W64>* cell = reinterpret_cast<AccT<W64>*>(reinterpret_cast<char*>(acc) + byte);
     if constexpr (W64)
-        atomicAdd(&acc[acc_idx((int)ue.x, o)], (unsigned long long)f32_to_i64_rn(p));
+        atomicAdd(cell, (unsigned long long)f32_to_i64_rn(p));
     else
-        atomicAdd(&acc[acc_idx((int)ue.x, o)], (uint32_t)__float2int_rn(p));
+        atomicAdd(cell, (uint32_t)__float2int_rn(p));
 }
 
 template <bool W64>
@@ -611,7 +626,8 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
                 return i < b.y ? v : make_uint2(0u, 0u);
             };
             auto cold_pair = [&](Acc* acc, uint2 e) {  // (row << 5 | ad offset, term): m' = 1
-                pair_add<W64>(acc, make_uint2(e.x >> kTileShift, 0x3f800000u), (int)(e.x & (kTileAds - 1)), (int)e.y);
+                pair_add<W64>(acc, make_uint2(acc_row_code(e.x >> kTileShift, W64), 0x3f800000u),
+                              (int)(e.x & (kTileAds - 1)), (int)e.y);
             };
             auto cold_add = [&](int buf, const Cold& c) {
                 Acc* acc = s_acc[buf];
