@@ -450,25 +450,17 @@ __device__ __forceinline__ ItemsAhead prod_ahead(const ScoreArgs& a, int g, int 
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// One e4m3fn code -> the BF16 bits of the same value (exact: every e4m3 value is a BF16 value).
-__device__ __forceinline__ uint32_t fp8_to_bf16_bits(uint32_t c) {
-    const uint32_t sgn = (c & 0x80u) << 8, e = (c >> 3) & 15u, m = c & 7u;
-    if (e != 0u) return sgn | ((e + 120u) << 7) | (m << 4);
-    if (m == 0u) return sgn;
-    const uint32_t p = 31u - __builtin_clz(m);  // m = 2^p (1 + f), value m 2^-9
-    return sgn | ((p + 118u) << 7) | ((m - (1u << p)) << (7u - p));
-}
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-// Eight e4m3fn codes (little-endian in v) -> eight BF16 values packed as one 16-byte operand.
+// Eight e4m3fn codes (little-endian in v) -> eight BF16 values packed as one 16-byte operand,
+// two codes per conversion instruction (scale 1: exact, every e4m3 value is a BF16 value).
 __device__ __forceinline__ f32x4 fp8x8_to_bf16x8(uint2 v) {
-    uint32_t w[4];
-    #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t src = i < 2 ? v.x : v.y;
-        const int sh = (i & 1) * 16;
-        w[i] = fp8_to_bf16_bits((src >> sh) & 0xffu) | (fp8_to_bf16_bits((src >> (sh + 8)) & 0xffu) << 16);
-    }
-    return f32x4{__uint_as_float(w[0]), __uint_as_float(w[1]), __uint_as_float(w[2]), __uint_as_float(w[3])};
+    const bf16x2 p0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.x, 1.0f, false);
+    const bf16x2 p1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.x, 1.0f, true);
+    const bf16x2 p2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.y, 1.0f, false);
+    const bf16x2 p3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v.y, 1.0f, true);
+    return f32x4{__builtin_bit_cast(float, p0), __builtin_bit_cast(float, p1), __builtin_bit_cast(float, p2),
+                 __builtin_bit_cast(float, p3)};
 }
 
 // Embedding copies the scan can stream (DT): 0 = FP32 (32x32x2 layout), 1 = BF16 and
