@@ -812,6 +812,7 @@ struct Plan {
            o_oo = 0, o_st = 0, o_werr = 0, o_htab = 0, o_husers = 0, o_hoff = 0, o_coff = 0,
            o_cusers = 0;
     int64_t n_super = 0;
+    int sshift = kSuperShift;  // log2 of the ads per decode super-tile
     size_t off_stcnt = 0, off_stoff = 0, off_stfill = 0, off_stage = 0, off_cmap = 0;
     size_t off_big_deep = 0, off_big_wide = 0, off_big_keys = 0, off_big_tmp = 0, off_big_hist = 0,
            off_big_stmp = 0;
@@ -875,11 +876,18 @@ static void layout(const Index& ix, bool topk, const BatchSizes& z, Plan* P) {
         P->o_cusers = put(4 * n_users);
     }
     P->plan_bytes = off - P->off_plan;
-    P->n_super = (ix.n_ads + kSuperAds - 1) / kSuperAds;
-    P->off_stcnt = put(4 * (size_t)(P->n_super + 1));
-    P->off_stoff = put(4 * (size_t)(P->n_super + 1));
-    P->off_stfill = put(4 * (size_t)(P->n_super + 1));
-    P->off_stmp = put(4 * (size_t)scan_tmp_words(P->n_super + 1));
+    // super-tiles of the list decode: 2048 ads without split buckets (longer runs of a list's
+    // postings per super-tile, so fewer atomics and longer writes; measured best of 1024..8192
+    // ads on 256-query batches) when the slots fit the entry's bits, else 1024; the counters
+    // are sized for 1024-ad super-tiles either way, so that a rerun subset of the batch, which
+    // may take the other size, fits the layout
+    const int64_t n_super_max = (ix.n_ads + kSuperAds - 1) / kSuperAds;
+    P->sshift = (!split && z.nu < (1 << (32 - kMaxSuperShift))) ? kMaxSuperShift : kSuperShift;
+    P->n_super = (ix.n_ads + (1LL << P->sshift) - 1) >> P->sshift;
+    P->off_stcnt = put(4 * (size_t)(n_super_max + 1));
+    P->off_stoff = put(4 * (size_t)(n_super_max + 1));
+    P->off_stfill = put(4 * (size_t)(n_super_max + 1));
+    P->off_stmp = put(4 * (size_t)scan_tmp_words(n_super_max + 1));
     P->off_stage = put(8 * (size_t)P->bucket_n);
     // chunks of the batch: sum over keys of ceil(L / 64) <= postings / 64 + keys
     P->off_cmap = put(8 * ((size_t)P->bucket_n / kChunk + (size_t)nu + 1));
@@ -1364,6 +1372,7 @@ static ebr_status run_decode(const Index& ix, const Plan& P, char* ws, hipStream
     d.chunks_per_wave = (uint32_t)chunks_per_wave;
     d.n_tiles = ix.n_tiles;
     d.n_super = P.n_super;
+    d.sshift = P.sshift;
     d.st_cnt = stcnt;
     d.st_off = stoff;
     d.st_fill = stfill;

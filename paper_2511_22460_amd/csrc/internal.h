@@ -23,6 +23,8 @@ constexpr int kTileShift = 5;
 constexpr int kSuperAds = 1024;
 constexpr int kSuperShift = 10;
 constexpr int kTilesPerSuper = kSuperAds / kTileAds;
+// Super-tiles of a batch without split buckets: 2048 ads (fewer, longer runs per list).
+constexpr int kMaxSuperShift = 11;
 // Postings per compressed chunk: one per lane of a 64-wide wavefront.
 constexpr int kChunk = 64;
 // Candidate slots per query in the selection buffer (sorted in LDS at the end).

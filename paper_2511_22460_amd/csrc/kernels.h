@@ -78,7 +78,9 @@ struct DecodeArgs {
     uint32_t total_chunks;
     uint32_t chunks_per_wave;         // consecutive chunks one decode wavefront takes (1..64)
     int64_t n_tiles;
-    int64_t n_super;                  // 1024-ad super-tiles
+    int64_t n_super;                  // super-tiles of 2^sshift ads
+    int32_t sshift;                   // 10 (1024 ads; always with split buckets) or
+                                      // kMaxSuperShift (2048 ads)
     uint32_t* st_cnt;                 // count pass: postings per super-tile
     const uint32_t* st_off;           // n_super + 1 exclusive prefix
     uint32_t* st_fill;                // place pass: running fill per super-tile

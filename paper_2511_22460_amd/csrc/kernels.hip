@@ -4,7 +4,8 @@
 //   0. k_chunk_map       - per chunk of the batch's distinct keys, its key slot and index
 //                          chunk.
 //   1. k_decode (count)  - every chunk is decoded by one wavefront (eight chunks' loads in
-//                          flight together); postings are counted per 1024-ad super-tile.
+//                          flight together); postings are counted per super-tile (2048
+//                          ads; 1024 with split buckets).
 //   2. scan              - exclusive scan of the super-tile counts.
 //   3. k_decode (place)  - decode again and place each posting (key slot, ad, weight) into
 //                          its super-tile's staging range.
@@ -123,9 +124,10 @@ __global__ __launch_bounds__(256) void k_chunk_map(DecodeArgs a) {
 constexpr int kDecGroup = 8;
 
 // One wavefront decodes a.chunks_per_wave consecutive chunks of the batch's distinct keys and
-// counts (place == 0) or places (place == 1) their postings into 1024-ad super-tile buckets.
-// Runs of postings in the same super-tile are aggregated into one atomic per run. A placed
-// entry is ((slot << 10) | ad & 1023, w' bits); k_refine orders each super-tile by 32-ad tile.
+// counts (place == 0) or places (place == 1) their postings into super-tile buckets of
+// 2^sshift ads. Runs of postings in the same super-tile are aggregated into one atomic per run.
+// A placed entry is ((slot << sshift) | ad mod 2^sshift, w' bits); k_refine orders each
+// super-tile by 32-ad tile.
 __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
     const int lane = lane_id();
     const uint32_t gw = blockIdx.x * 4u + (threadIdx.x >> 6);
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
             const uint32_t delta = (lane >= 1 && lane < count) ? gap + 1u : 0u;
             const uint32_t id = first + wave_incl_scan(delta);
             const bool valid = lane < count;
-            const uint32_t st = id >> kSuperShift;
+            const uint32_t st = id >> a.sshift;
             const uint32_t prev = __shfl_up(st, 1, 64);
             const bool head = valid && (lane == 0 || st != prev);
             const uint64_t heads = __ballot(head);
@@ -205,9 +207,10 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
                 const float ws = ldexpf(wt[i], a.uk_wshift[u]);  // exact: a power-of-two scale
                 uint2* out = reinterpret_cast<uint2*>(a.stage) + pos;
                 if (!cold) {
-                    out[0] = make_uint2((u << kSuperShift) | (id & (kSuperAds - 1)), __float_as_uint(ws));
+                    out[0] = make_uint2((u << a.sshift) | (id & ((1u << a.sshift) - 1u)), __float_as_uint(ws));
                 } else {
-                    // the pair's term round(fl(m' w')): an FP32 value that is an integer
+                    // the pair's term round(fl(m' w')): an FP32 value that is an integer (split
+                    // buckets: 1024-ad super-tiles)
                     const uint2* cu = reinterpret_cast<const uint2*>(a.cold_users) + c0;
                     const uint32_t gmask = (1u << a.gq_shift) - 1u;
                     for (uint32_t j = 0; j < nusers; ++j) {
@@ -226,7 +229,7 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a, int place) {
 // Entries of one super-tile a k_refine work-group keeps in registers (per thread) when they
 // fit; larger super-tiles are read twice.
 constexpr int kRefineNT = 1024, kRefineRegs = 16;
-constexpr int kRefineBins = kTilesPerSuper * (kSplitMaxGroups + 2);
+constexpr int kRefineBins = std::max(kTilesPerSuper * (kSplitMaxGroups + 2), 1 << (kMaxSuperShift - kTileShift));
 static_assert(kRefineBins <= 2 * kRefineNT, "two bins per thread in the offset scan");
 
 // One work-group per super-tile: counting sort of its entries by (32-ad tile, sub-range)
@@ -240,7 +243,8 @@ __global__ __launch_bounds__(kRefineNT) void k_refine(DecodeArgs a) {
     const uint32_t st = blockIdx.x;
     const uint32_t beg = a.st_off[st], end = a.st_off[st + 1];
     const int tid = (int)threadIdx.x;
-    const int S = a.n_sub, nb = kTilesPerSuper * S;
+    const int tps = 1 << (a.sshift - kTileShift);  // tiles per super-tile
+    const int S = a.n_sub, nb = tps * S;
     for (int b = tid; b < nb; b += kRefineNT) s_cnt[b] = 0u;
     __syncthreads();
     const uint2* in = reinterpret_cast<const uint2*>(a.stage);
@@ -248,10 +252,10 @@ __global__ __launch_bounds__(kRefineNT) void k_refine(DecodeArgs a) {
     uint2 e[kRefineRegs];
     // bin: tile within the super-tile, then sub-range: hot, warm, cold pairs of group g
     auto bin_of = [&](uint2 v) -> uint32_t {
-        const uint32_t t = (v.x >> kTileShift) & (kTilesPerSuper - 1);
+        const uint32_t t = (v.x >> kTileShift) & (uint32_t)(tps - 1);
         if (S == 1) return t;
         const uint32_t sub = (v.x >> 31) ? 2u + ((v.x >> 18) & 0x1fffu)
-                                          : ((v.x >> kSuperShift) < (uint32_t)a.n_hot ? 0u : 1u);
+                                          : ((v.x >> a.sshift) < (uint32_t)a.n_hot ? 0u : 1u);
         return t * (uint32_t)S + sub;
     };
     if (regs) {
@@ -278,7 +282,7 @@ __global__ __launch_bounds__(kRefineNT) void k_refine(DecodeArgs a) {
     }
     __syncthreads();
     for (int b = tid; b < nb; b += kRefineNT) {
-        const uint64_t tile = (uint64_t)st * kTilesPerSuper + (uint64_t)(b / S);
+        const uint64_t tile = (uint64_t)st * (uint64_t)tps + (uint64_t)(b / S);
         if (tile < (uint64_t)a.n_tiles) a.tile_off[tile * (uint64_t)S + (uint64_t)(b % S)] = s_off[b];
     }
     if (st == gridDim.x - 1 && tid == 0) a.tile_off[(uint64_t)a.n_tiles * (uint64_t)S] = end;
@@ -286,7 +290,7 @@ __global__ __launch_bounds__(kRefineNT) void k_refine(DecodeArgs a) {
     auto place = [&](uint2 v) {
         const uint32_t b = bin_of(v);
         const uint32_t pos = s_off[b] + atomicAdd(&s_cnt[b], 1u);
-        const uint32_t u = v.x >> kSuperShift, o = v.x & (kTileAds - 1);
+        const uint32_t u = v.x >> a.sshift, o = v.x & (kTileAds - 1);
         uint32_t x = (u << kTileShift) | o;
         if (S > 1 && (v.x >> 31)) {
             x = (((v.x >> kSuperShift) & 255u) << kTileShift) | o;  // cold pair: its query row
@@ -669,6 +673,8 @@ int launch_excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t*
 
 int launch_refine(const DecodeArgs& a, void* stream) {
     if (a.n_super <= 0) return 0;
+    if (a.sshift < kSuperShift || a.sshift > kMaxSuperShift || (a.n_sub > 1 && a.sshift != kSuperShift))
+        return (int)hipErrorInvalidValue;
     if (a.n_sub < 1 || a.n_sub > kSplitMaxGroups + 2) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(k_refine, dim3((unsigned)a.n_super), dim3(kRefineNT), 0, (hipStream_t)stream, a);
     return last(hipSuccess);
