@@ -414,8 +414,57 @@ __global__ __launch_bounds__(1024) void k_select(SelectArgs a) {
 //                  prep mode: the first Kc go, in rank order, to the rescore scratch (id and
 //                  the cross-term value carried with the candidate), with the Kc-th
 //                  approximate score for the recall certificate.
+// The kth largest (k >= 1) of the n distinct keys s[0, n): an MSB-first radix select, one
+// byte per pass (LDS histogram of the keys that share the bytes fixed so far).
+__device__ __forceinline__ unsigned long long kth_largest(const unsigned long long* s, int n, int kth, uint32_t* hist,
+                                          unsigned long long* pref, int* rank_out) {
+    const int tid = (int)threadIdx.x;
+    unsigned long long prefix = 0ull, mask = 0ull;
+    int rank = kth;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int b = tid; b < 256; b += 1024) hist[b] = 0u;
+        __syncthreads();
+        for (int i = tid; i < n; i += 1024) {
+            const unsigned long long key = s[i];
+            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            // lane l: bins 255 - 4 l .. 252 - 4 l, counted from the top
+            uint32_t v[4], sum = 0u;
+            #pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                v[t] = hist[255 - (4 * tid + t)];
+                sum += v[t];
+            }
+            const uint32_t incl = wave_incl_sum(sum);
+            uint32_t acc = incl - sum;
+            if (acc < (uint32_t)rank && (uint32_t)rank <= incl) {
+                #pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (acc < (uint32_t)rank && (uint32_t)rank <= acc + v[t]) {
+                        *pref = prefix | ((unsigned long long)(255 - (4 * tid + t)) << shift);
+                        *rank_out = rank - (int)acc;
+                    }
+                    acc += v[t];
+                }
+            }
+        }
+        __syncthreads();
+        prefix = *pref;
+        rank = *rank_out;
+        mask |= 255ull << shift;
+        __syncthreads();
+    }
+    return prefix;
+}
+
 __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
     __shared__ unsigned long long s[kCandCap];
+    __shared__ uint32_t s_hist[256];
+    __shared__ unsigned long long s_pref;
+    __shared__ int s_rank;
+    __shared__ uint32_t s_slot;
     const int q = (int)blockIdx.x;
     const int tid = (int)threadIdx.x;
     if (a.gate && *a.gate == 0u) return;
@@ -428,36 +477,54 @@ __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
         return;
     }
     const int n = (int)min(c, (uint32_t)a.cap);
-    int P = 64;
-    while (P < n) P <<= 1;
     const unsigned long long* src = a.cand + (int64_t)q * a.cap;
-    for (int i = tid; i < P; i += 1024) s[i] = (i < n) ? src[i] : 0ull;
-    __syncthreads();
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < P; i += 1024) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const unsigned long long x = s[i], y = s[ixj];
-                    const bool desc = (i & k) == 0;
-                    if (desc ? (x < y) : (x > y)) { s[i] = y; s[ixj] = x; }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    if (c > (uint32_t)a.cap) {
-        if (tid == 0) {
-            const unsigned long long t = s[Kc - 1];
-            a.thresh[2 * q] = (uint32_t)(t >> 32);
-            a.thresh[2 * q + 1] = (uint32_t)t;
-            a.status[q] = kStatusOverflow;
-            atomicAdd(a.unresolved, 1u);
-        }
-        return;
-    }
     int done = kStatusDone;
-    if (!a.prep) {
+    if (a.prep || c > (uint32_t)a.cap) {
+        // only the Kc-th best key is needed (a threshold; the prep pass's candidates in any
+        // order): a radix select instead of a sort
+        for (int i = tid; i < n; i += 1024) s[i] = src[i];
+        if (tid == 0) s_slot = 0u;
+        __syncthreads();
+        const unsigned long long T = kth_largest(s, n, Kc, s_hist, &s_pref, &s_rank);
+        if (c > (uint32_t)a.cap) {
+            if (tid == 0) {
+                a.thresh[2 * q] = (uint32_t)(T >> 32);
+                a.thresh[2 * q + 1] = (uint32_t)T;
+                a.status[q] = kStatusOverflow;
+                atomicAdd(a.unresolved, 1u);
+            }
+            return;
+        }
+        // the Kc best by approximate key (the keys are distinct: exactly Kc of them reach T),
+        // with their carried cross terms; the rescore sorts their exact scores
+        const float* cw = a.cand_wide + (int64_t)q * a.cap;
+        for (int p = tid; p < n; p += 1024) {
+            const unsigned long long key = s[p];
+            if (key >= T) {
+                const uint32_t slot = atomicAdd(&s_slot, 1u);
+                a.r_id[(int64_t)q * a.r_ld + slot] = 0xffffffffu - (uint32_t)key;
+                a.r_wide[(int64_t)q * a.r_ld + slot] = cw[p];
+            }
+        }
+        if (tid == 0) a.r_stilde[q] = key_score((uint32_t)(T >> 32));
+    } else {
+        int P = 64;
+        while (P < n) P <<= 1;
+        for (int i = tid; i < P; i += 1024) s[i] = (i < n) ? src[i] : 0ull;
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = tid; i < P; i += 1024) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const unsigned long long x = s[i], y = s[ixj];
+                        const bool desc = (i & k) == 0;
+                        if (desc ? (x < y) : (x > y)) { s[i] = y; s[ixj] = x; }
+                    }
+                }
+                __syncthreads();
+            }
+        }
         const int K = a.kq[q];
         const int64_t o = a.out_off[q];
         for (int i = tid; i < K; i += 1024) {
@@ -468,23 +535,6 @@ __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
         if (a.werr && !wide_precise(a.werr[q], key_score((uint32_t)(s[0] >> 32)),
                                     key_score((uint32_t)(s[K - 1] >> 32))))
             done = kStatusImprecise;
-    } else {
-        // the Kc best by approximate key, in rank order, with their carried cross terms
-        const unsigned long long T = s[Kc - 1];
-        const float* cw = a.cand_wide + (int64_t)q * a.cap;
-        for (int p = tid; p < n; p += 1024) {
-            const unsigned long long key = src[p];
-            if (key >= T) {
-                int lo = 0, hi = Kc - 1;  // s[0..Kc) descending and distinct: find key
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s[mid] > key) lo = mid + 1; else hi = mid;
-                }
-                a.r_id[(int64_t)q * a.r_ld + lo] = 0xffffffffu - (uint32_t)key;
-                a.r_wide[(int64_t)q * a.r_ld + lo] = cw[p];
-            }
-        }
-        if (tid == 0) a.r_stilde[q] = key_score((uint32_t)(T >> 32));
     }
     if (tid == 0) {
         a.status[q] = done;
