@@ -414,51 +414,6 @@ __global__ __launch_bounds__(1024) void k_select(SelectArgs a) {
 //                  prep mode: the first Kc go, in rank order, to the rescore scratch (id and
 //                  the cross-term value carried with the candidate), with the Kc-th
 //                  approximate score for the recall certificate.
-// The kth largest (k >= 1) of the n distinct keys s[0, n): an MSB-first radix select, one
-// byte per pass (LDS histogram of the keys that share the bytes fixed so far).
-__device__ __forceinline__ unsigned long long kth_largest(const unsigned long long* s, int n, int kth, uint32_t* hist,
-                                          unsigned long long* pref, int* rank_out) {
-    const int tid = (int)threadIdx.x;
-    unsigned long long prefix = 0ull, mask = 0ull;
-    int rank = kth;
-    for (int shift = 56; shift >= 0; shift -= 8) {
-        for (int b = tid; b < 256; b += 1024) hist[b] = 0u;
-        __syncthreads();
-        for (int i = tid; i < n; i += 1024) {
-            const unsigned long long key = s[i];
-            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
-        }
-        __syncthreads();
-        if (tid < 64) {
-            // lane l: bins 255 - 4 l .. 252 - 4 l, counted from the top
-            uint32_t v[4], sum = 0u;
-            #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                v[t] = hist[255 - (4 * tid + t)];
-                sum += v[t];
-            }
-            const uint32_t incl = wave_incl_sum(sum);
-            uint32_t acc = incl - sum;
-            if (acc < (uint32_t)rank && (uint32_t)rank <= incl) {
-                #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    if (acc < (uint32_t)rank && (uint32_t)rank <= acc + v[t]) {
-                        *pref = prefix | ((unsigned long long)(255 - (4 * tid + t)) << shift);
-                        *rank_out = rank - (int)acc;
-                    }
-                    acc += v[t];
-                }
-            }
-        }
-        __syncthreads();
-        prefix = *pref;
-        rank = *rank_out;
-        mask |= 255ull << shift;
-        __syncthreads();
-    }
-    return prefix;
-}
-
 __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
     __shared__ unsigned long long s[kCandCap];
     __shared__ uint32_t s_hist[256];

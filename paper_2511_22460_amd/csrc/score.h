@@ -1025,6 +1025,10 @@ __global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
     constexpr int NQ = D / 8;
     __shared__ unsigned long long s[kMaxK];
     __shared__ float s_u[D];
+    __shared__ uint32_t s_hist[256];
+    __shared__ unsigned long long s_pref;
+    __shared__ int s_rank;
+    __shared__ uint32_t s_slot;
     const int q = (int)blockIdx.x;
     const int tid = (int)threadIdx.x;
     const int K = a.kq[q];
@@ -1065,9 +1069,27 @@ __global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
         const float sc = deep + a.r_wide[(int64_t)q * a.r_ld + r];
         s[r] = ((unsigned long long)score_key(sc) << 32) | (unsigned long long)(0xffffffffu - id);
     }
+    // the K best exact keys, sorted: the K-th best by radix select, the keys at or above it
+    // (exactly K: they are distinct) moved to the front, then a sort of those alone
+    if (tid == 0) s_slot = 0u;
+    __syncthreads();
+    const unsigned long long T = kth_largest(s, Kc, K, s_hist, &s_pref, &s_rank);
+    {
+        constexpr int R = kMaxK / 1024;
+        unsigned long long v[R];
+        #pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = tid + 1024 * i;
+            v[i] = r < Kc ? s[r] : 0ull;
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (tid + 1024 * i < Kc && v[i] >= T) s[atomicAdd(&s_slot, 1u)] = v[i];
+    }
     int P = 64;
-    while (P < Kc) P <<= 1;
-    for (int i = Kc + tid; i < P; i += 1024) s[i] = 0ull;
+    while (P < K) P <<= 1;
+    for (int i = K + tid; i < P; i += 1024) s[i] = 0ull;
     __syncthreads();
     for (int k = 2; k <= P; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
