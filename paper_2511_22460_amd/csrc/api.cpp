@@ -302,20 +302,19 @@ ArenaPlan arena_plan(int64_t n_ads, int32_t dim, uint32_t dtypes, int64_t n_post
     return p;
 }
 
-// FP32 copy in the matrix-core layout (see k_score in score.h).
+// FP32 copy: the rows, row-major, padded with zero rows to a multiple of 32 (k_score stages
+// a tile's 32 rows into the matrix-core operand order in LDS; a rescored ad's row is
+// contiguous).
 static void swizzle_f32(const float* E, int64_t n_ads, int32_t d, float* out) {
     const int64_t n_blk = (n_ads + kTileAds - 1) / kTileAds;
-    const int NQ = d / 8;
     parallel_for(n_blk, [&](int64_t b0, int64_t b1) {
         for (int64_t b = b0; b < b1; ++b) {
             float* dst = out + b * (int64_t)kTileAds * d;
-            for (int i = 0; i < NQ; ++i)
-                for (int l = 0; l < 64; ++l)
-                    for (int j = 0; j < 4; ++j) {
-                        const int64_t row = b * kTileAds + (l & 31);
-                        const int col = 8 * i + 2 * j + (l >> 5);
-                        dst[((int64_t)i * 64 + l) * 4 + j] = row < n_ads ? E[row * d + col] : 0.0f;
-                    }
+            for (int l = 0; l < kTileAds; ++l) {
+                const int64_t row = b * kTileAds + l;
+                if (row < n_ads) std::memcpy(dst + (int64_t)l * d, E + row * d, sizeof(float) * (size_t)d);
+                else std::memset(dst + (int64_t)l * d, 0, sizeof(float) * (size_t)d);
+            }
         }
     }, 64);
 }

@@ -10,7 +10,8 @@
 //   scan         - word offsets per chunk
 //   k_bld_pack   - per chunk: header and packed gap words
 //   k_bld_rows   - per ad row: finite check, row norms and quantisation errors (FP64), FP8 scale
-//   k_bld_layout - the FP32 copy in the 32x32x2 operand layout, BF16 / FP8 in the 32x32x16 one
+//   k_bld_layout - the FP32 copy (row-major, padded to whole tiles), BF16 / FP8 in the 32x32x16
+//                  operand layout
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -228,11 +229,9 @@ __global__ __launch_bounds__(256) void k_bld_layout(BuildArgs a, int64_t n_elem)
     const int64_t blk = idx / (32 * d);
     const int r = (int)(idx % (32 * d));
     {
-        // FP32: quad i of lane l holds e[32 blk + (l & 31)][8 i + 2 j + (l >> 5)], j = 0..3
-        const int i = r / 256, l = (r / 4) % 64, j = r % 4;
-        const int64_t row = 32 * blk + (l & 31);
-        const int col = 8 * i + 2 * j + (l >> 5);
-        a.emb_f32[idx] = row < a.n_ads ? a.emb[row * d + col] : 0.0f;
+        // FP32: the rows, row-major, zero rows past the inventory
+        const int64_t row = 32 * blk + r / d;
+        a.emb_f32[idx] = row < a.n_ads ? a.emb[idx] : 0.0f;
     }
     if (a.emb_bf16 || a.emb_fp8) {
         // 16-dim step s, lane l, value j holds e[32 blk + (l & 31)][16 s + 8 (l >> 5) + j]

@@ -58,7 +58,7 @@ struct Index {
     int64_t n_tiles = 0;      // ceil(n_ads / 32)
     uint32_t dtypes = 0;
     // device pointers into the caller's arena
-    const void* emb_f32 = nullptr;   // swizzled, see k_score in score.h
+    const void* emb_f32 = nullptr;   // row-major, padded to whole tiles (see k_score in score.h)
     const void* emb_bf16 = nullptr;  // 32x32x16 BF16 operand layout (optional)
     const void* emb_fp8 = nullptr;   // same element order, e4m3fn codes (optional)
     const float* fp8_scale = nullptr;  // per ad row (optional)

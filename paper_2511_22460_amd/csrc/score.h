@@ -19,10 +19,13 @@ namespace ebr {
 //                             and accumulate its cross term into the other LDS buffer.
 // One barrier per tile hands the double-buffered accumulators and embedding stage over.
 //
-// Embedding layout (FP32 copy): per 32-ad block, D/8 quads x 64 lanes x 4 floats, where
-// quad i of lane l holds e[32b + (l & 31)][8i + 2j + (l >> 5)] for j = 0..3. Step s = 4i + j
-// of the K loop then finds the B operand of v_mfma_f32_32x32x2_f32 (B[k][n] with
-// k = l >> 5, n = l & 31) in component j of quad i.
+// Embedding layout (FP32 copy): row-major, the rows padded to a multiple of 32 (so that an
+// ad's row is 2 x 128-byte lines when it is gathered on its own). The stager writes a tile's
+// 16-byte chunk c (dimensions 4c .. 4c + 3) of ad o to LDS quad i = c >> 1, lane
+// ((c & 1) << 5 | o) XOR 2i (the XOR spreads the stager's writes over the banks), so that step
+// s = 4i + j of the K loop finds the B operand of v_mfma_f32_32x32x2_f32 (B[k][n] with
+// k = l >> 5, n = l & 31) in component j of that quad: dimension 8i + 4k + j. The user rows
+// (A operand) take the same dimension order.
 //
 // Accumulator layout of v_mfma_f32_32x32x2_f32: register r of lane l holds row
 // 8 * (r >> 2) + 4 * (l >> 5) + (r & 3), column l & 31.
@@ -463,6 +466,14 @@ __device__ __forceinline__ f32x4 fp8x8_to_bf16x8(uint2 v) {
                  __builtin_bit_cast(float, p3)};
 }
 
+// LDS quad of the FP32 copy's 16-byte unit j of a tile (row-major: ad j / (D / 4), chunk
+// c = j mod (D / 4)): quad c >> 1, lane ((c & 1) << 5 | ad) XOR 2 (c >> 1).
+template <int D>
+__device__ __forceinline__ int f32_slot_d(int j) {
+    const int o = j / (D / 4), c = j % (D / 4), i = c >> 1;
+    return i * 64 + ((((c & 1) << 5) | o) ^ (2 * i));
+}
+
 // Embedding copies the scan can stream (DT): 0 = FP32 (32x32x2 layout), 1 = BF16 and
 // 2 = FP8 (both in the 32x32x16 BF16 operand layout; FP8 is expanded to BF16 in LDS and its
 // per-ad scale applied to the finished dot product).
@@ -594,8 +605,10 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
                 #pragma unroll
                 for (int k = 0; k < SPER; ++k) {
                     const int j = sl + k * kStageThreads;
-                    if (UNITS % kStageThreads == 0 || j < UNITS)
-                        s_emb[buf][j] = DT == 2 ? fp8x8_to_bf16x8(r.c[k]) : r.u[k];
+                    if (UNITS % kStageThreads == 0 || j < UNITS) {
+                        if (DT == 0) s_emb[buf][f32_slot_d<D>(j)] = r.u[k];
+                        else s_emb[buf][j] = DT == 2 ? fp8x8_to_bf16x8(r.c[k]) : r.u[k];
+                    }
                 }
                 if (DT == 2 && sl < kTileAds) s_escale[buf][sl] = r.scale;
             };
@@ -748,8 +761,8 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
 
     // consumer, groups of at most 2 CW queries (FP32, d <= 64): lane (wave w, half h) owns the
     // cell of row 2 w + h and ad column lane mod 32 and computes its dot product as a chain of
-    // FMAs in the order and rounding of the 32x32x2 matrix product (per step the even
-    // dimension, then the odd one, each rounded), so its scores are bit-identical to the
+    // FMAs in the order and rounding of the 32x32x2 matrix product (per step the k = 0
+    // dimension, then the k = 1 one, each rounded), so its scores are bit-identical to the
     // matrix-core path's, while the work is spread over all consumer waves instead of a
     // 32-row product on one SIMD for a handful of rows.
     if (DT == 0 && MODE != 2 && D <= 64 && B - qbase <= 2 * CW) {
@@ -770,12 +783,12 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
                 float deep = 0.0f;
 #pragma unroll
                 for (int i = 0; i < NQ; ++i) {
-                    const f32x4 e0 = eb[i * 64 + o];       // dimensions 8 i + 2 j
-                    const f32x4 e1 = eb[i * 64 + 32 + o];  // dimensions 8 i + 2 j + 1
+                    const f32x4 e0 = eb[i * 64 + (o ^ (2 * i))];         // dimensions 8 i + j
+                    const f32x4 e1 = eb[i * 64 + ((32 + o) ^ (2 * i))];  // dimensions 8 i + 4 + j
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        deep = fmaf(us[8 * i + 2 * j], e0[j], deep);
-                        deep = fmaf(us[8 * i + 2 * j + 1], e1[j], deep);
+                        deep = fmaf(us[8 * i + j], e0[j], deep);
+                        deep = fmaf(us[8 * i + 4 + j], e1[j], deep);
                     }
                 }
                 const int cell = acc_idx(row, o);
@@ -816,10 +829,11 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
     {
         const int q = q0 + (lane & 31);
         if (DT == 0) {
+            // step s = 4 i + j, k = lane >> 5: dimension 8 i + 4 k + j (the FP32 layout's order)
             const int kofs = lane >> 5;
             #pragma unroll
             for (int s = 0; s < NUR; ++s)
-                ureg[s] = (q < B) ? a.user[(int64_t)q * D + 2 * s + kofs] : 0.0f;
+                ureg[s] = (q < B) ? a.user[(int64_t)q * D + 8 * (s >> 2) + 4 * kofs + (s & 3)] : 0.0f;
         } else {
             const int kofs = 8 * (lane >> 5);
             #pragma unroll
@@ -910,11 +924,11 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
             constexpr int W = NQ < 8 ? NQ : 8;
             f32x4 ev[W];
             #pragma unroll
-            for (int i = 0; i < W; ++i) ev[i] = eb[i * 64 + lane];
+            for (int i = 0; i < W; ++i) ev[i] = eb[i * 64 + (lane ^ (2 * i))];
             #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 const f32x4 e4 = ev[i % W];
-                if (i + W < NQ) ev[i % W] = eb[(i + W) * 64 + lane];
+                if (i + W < NQ) ev[i % W] = eb[(i + W) * 64 + (lane ^ (2 * (i + W)))];
                 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     c = __builtin_amdgcn_mfma_f32_32x32x2f32(ureg[4 * i + j], e4[j], c, 0, 0, 0);
@@ -1038,10 +1052,10 @@ __global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
     const int Kc = a.kcnt[q];
     for (int i = tid; i < D; i += 1024) s_u[i] = a.user[(int64_t)q * D + i];
     __syncthreads();
-    // one thread per candidate: the dot product is one FMA chain over the dimensions in
-    // order, which is what the FP32 scan's 32x32x2 products compute (the k = 0 dimension of
-    // each step, then the k = 1 one, each rounded), so a rescored score has the FP32 scan's
-    // bits; the cross term is the scan's exact value.
+    // one thread per candidate: the dot product is one FMA chain over the dimensions in the
+    // order the FP32 scan's 32x32x2 products take them (per step s = 4 i + j dimension 8 i + j,
+    // then 8 i + 4 + j, each rounded), so a rescored score has the FP32 scan's bits; the cross
+    // term is the scan's exact value.
     const f32x4* emb = reinterpret_cast<const f32x4*>(a.emb);
     for (int r = tid; r < Kc; r += 1024) {
         uint32_t id = a.r_id[(int64_t)q * a.r_ld + r];
@@ -1049,21 +1063,20 @@ __global__ __launch_bounds__(1024) void k_rescore(RescoreArgs a) {
             if (a.ctl) atomicOr(&a.ctl->error, 4u);
             id = 0u;
         }
-        const int64_t b = id >> kTileShift;
-        const int o = (int)(id & (kTileAds - 1));
+        const f32x4* row = emb + (int64_t)id * (D / 4);  // the ad's row: 2 x 128-byte lines (d = 64)
         f32x4 e0[NQ], e1[NQ];
         #pragma unroll
         for (int i = 0; i < NQ; ++i) {
-            e0[i] = emb[(b * NQ + i) * 64 + o];       // dimensions 8 i + 2 j
-            e1[i] = emb[(b * NQ + i) * 64 + 32 + o];  // dimensions 8 i + 2 j + 1
+            e0[i] = row[2 * i];      // dimensions 8 i + j
+            e1[i] = row[2 * i + 1];  // dimensions 8 i + 4 + j
         }
         float deep = 0.0f;
         #pragma unroll
         for (int i = 0; i < NQ; ++i) {
             #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                deep = fmaf(s_u[8 * i + 2 * j], e0[i][j], deep);
-                deep = fmaf(s_u[8 * i + 2 * j + 1], e1[i][j], deep);
+                deep = fmaf(s_u[8 * i + j], e0[i][j], deep);
+                deep = fmaf(s_u[8 * i + 4 + j], e1[i][j], deep);
             }
         }
         const float sc = deep + a.r_wide[(int64_t)q * a.r_ld + r];
