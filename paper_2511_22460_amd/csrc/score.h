@@ -349,11 +349,26 @@ __device__ __forceinline__ void pair_add(AccT<W64>* acc, uint2 ue, int o, int w)
         atomicAdd(cell, (uint32_t)__float2int_rn(p));
 }
 
+// The item's pairs, without a branch: a pair outside the item adds 0 to a cell of its own
+// lane. With a branch per pair the compiler waited for all LDS operations in each branch, so
+// every add waited for the one before it; a wave-uniform exit after the last used slot brings
+// those waits back as well.
 template <bool W64>
 __device__ __forceinline__ void item_add(AccT<W64>* acc, const ItemLoad& it) {
+    const uint32_t spare = (uint32_t)lane_id() * (uint32_t)sizeof(AccT<W64>);
+    const uint32_t os = (uint32_t)it.o << (W64 ? 5 : 4);
     #pragma unroll
-    for (int j = 0; j < kUserChunk; ++j)
-        if ((it.valid >> j) & 1u) pair_add<W64>(acc, it.ue[j], it.o, it.w);
+    for (int j = 0; j < kUserChunk; ++j) {
+        const bool v = (it.valid >> j) & 1u;
+        const uint2 ue = it.ue[j];
+        const float p = __uint_as_float(ue.y) * __uint_as_float((uint32_t)it.w);
+        const uint32_t byte = v ? (ue.x & 0xffffu) + (os ^ (ue.x >> 16)) : spare;
+        AccT<W64>* cell = reinterpret_cast<AccT<W64>*>(reinterpret_cast<char*>(acc) + byte);
+        if constexpr (W64)
+            atomicAdd(cell, v ? (unsigned long long)f32_to_i64_rn(p) : 0ull);
+        else
+            atomicAdd(cell, v ? (uint32_t)__float2int_rn(p) : 0u);
+    }
 }
 
 // Items of steps [s_begin, end) of a set of entries.
