@@ -972,7 +972,10 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
         const int64_t ad = (int64_t)tile * kTileAds + o;
         const bool ad_ok = ad < a.n_ads;
         float sc[16];
-        uint32_t pm = 0;  // bit r: this lane's cell r is at or above its row's FP32 threshold
+        // some cell of the wave is at or above its row's FP32 threshold: each comparison's
+        // lane mask (one vector compare into scalar registers), or-ed on the scalar unit
+        const uint64_t okm = __ballot(ad_ok);
+        uint64_t any = 0;
         // sample pass: row base of this wave's block plus a 32-bit offset per row
         uint32_t* skeys = MODE == 1 ? a.sample_keys + (int64_t)q0 * a.sample_ld : nullptr;
         const uint32_t scol = (uint32_t)(first + it) * kTileAds + (uint32_t)o;
@@ -997,21 +1000,24 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
                         skeys[(uint32_t)rl * (uint32_t)a.sample_ld + scol] = ad_ok ? score_key(fmaf(wd[4 * g4 + k], sq[k], deep)) : 0u;
                 } else {
                     sc[4 * g4 + k] = fmaf(wd[4 * g4 + k], sq[k], deep);
-                    pm |= sc[4 * g4 + k] >= th[k] ? 1u << (4 * g4 + k) : 0u;  // NaN threshold: never
+                    any |= __ballot(sc[4 * g4 + k] >= th[k]);  // NaN threshold: never
                 }
             }
         }
         if (MODE == 0) {
             // rare: push this wave's cells at or above the FP32 threshold into its ring slice
             // (the stager makes the exact comparison); a full slice appends directly
-            if (!ad_ok) pm = 0u;
             uint32_t n = 0;  // wave-uniform
-            if (__ballot(pm != 0u) != 0ull) {
+            if ((any & okm) != 0ull) {
+                f32x4 thv[4];  // the rows' thresholds again, read together
+                #pragma unroll
+                for (int g4 = 0; g4 < 4; ++g4) thv[g4] = *reinterpret_cast<const f32x4*>(s_thr + rg(g4));
                 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const uint64_t bl = __ballot((pm >> r) & 1u);
+                    const bool mine = ad_ok && sc[r] >= thv[r >> 2][r & 3];
+                    const uint64_t bl = __ballot(mine);
                     if (bl == 0ull) continue;
-                    if ((pm >> r) & 1u) {
+                    if (mine) {
                         int ql = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                         __asm__ volatile("" : "+v"(ql));  // per-row addresses computed here, not hoisted
                         const uint32_t slot = n + (uint32_t)__builtin_amdgcn_mbcnt_hi(
