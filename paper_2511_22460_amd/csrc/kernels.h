@@ -178,14 +178,14 @@ struct FinalArgs {
     const float* werr;                // output mode: per-query bound on the cross term's
                                       // fixed-point rounding, or null (no check)
     uint32_t* imprecise;              // count of queries that missed kWideTau
-    uint32_t* r_id;                   // prep: B x r_ld ids in approximate rank order
+    uint32_t* r_id;                   // prep: B x r_ld ids of the Kc best, in no particular order
     float* r_wide;                    // prep: their cross-term values
     float* r_stilde;                  // prep: the K'-th approximate score per query
     int32_t r_ld;
 };
 
 struct RescoreArgs {
-    const void* emb;                  // FP32 copy (32x32x2 layout)
+    const void* emb;                  // FP32 copy (row-major)
     const float* user;                // B x D
     int64_t n_ads;
     const int32_t* kq;

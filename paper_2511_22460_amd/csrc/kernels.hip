@@ -410,10 +410,10 @@ __global__ __launch_bounds__(1024) void k_select(SelectArgs a) {
 //  C < Kc        - too few ads reached the threshold: status NeedLower (revise and rescan)
 //  C > capacity  - overflow: the threshold becomes the Kc-th largest stored key (it strictly
 //                  rises, since keys are distinct) and the query is rescanned
-//  otherwise     - output mode: the first K are the result (ids, FP32 scores);
-//                  prep mode: the first Kc go, in rank order, to the rescore scratch (id and
-//                  the cross-term value carried with the candidate), with the Kc-th
-//                  approximate score for the recall certificate.
+//  otherwise     - output mode: the first K after a sort are the result (ids, FP32 scores);
+//                  prep mode: the Kc best (by radix select, in no particular order) go to the
+//                  rescore scratch (id and the cross-term value carried with the candidate),
+//                  with the Kc-th approximate score for the recall certificate.
 __global__ __launch_bounds__(1024) void k_finalize(FinalArgs a) {
     __shared__ unsigned long long s[kCandCap];
     __shared__ uint32_t s_hist[256];

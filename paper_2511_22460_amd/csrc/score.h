@@ -489,7 +489,8 @@ __device__ __forceinline__ int f32_slot_d(int j) {
     return i * 64 + ((((c & 1) << 5) | o) ^ (2 * i));
 }
 
-// Embedding copies the scan can stream (DT): 0 = FP32 (32x32x2 layout), 1 = BF16 and
+// Embedding copies the scan can stream (DT): 0 = FP32 (row-major; staged into the 32x32x2
+// operand order in LDS), 1 = BF16 and
 // 2 = FP8 (both in the 32x32x16 BF16 operand layout; FP8 is expanded to BF16 in LDS and its
 // per-ad scale applied to the finished dot product).
 template <int D, int DT> struct EmbStage {
@@ -1048,10 +1049,10 @@ __global__ __launch_bounds__((ScoreShape<D, W64>::NT), 1) void k_score(ScoreArgs
 }
 
 // Exact FP32 rescore of the Kc approximate-best candidates of query q (one work-group): each
-// candidate's FP32 row is gathered from the 32x32x2 layout by one thread, whose dot product is
-// the FP32 scan's own FMA chain, so the rescored score is bit-identical to the FP32 scan's;
-// the score adds the carried cross term. The Kc exact keys are sorted and the first K
-// written. Certificate:
+// candidate's FP32 row (row-major copy) is gathered by one thread, whose dot product is the
+// FP32 scan's own FMA chain, so the rescored score is bit-identical to the FP32 scan's; the
+// score adds the carried cross term. The K best exact keys are found by radix select, sorted
+// and written. Certificate:
 // every ad outside the candidates has an approximate score <= the Kc-th approximate score s~
 // and differs from its exact score by at most eps_q, so s~ + eps_q < (K-th exact score)
 // proves the result is the exact top-K; otherwise the query is marked uncertified.
