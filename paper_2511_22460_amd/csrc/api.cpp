@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -1306,30 +1307,71 @@ static ebr_status plan_batch(const Index& ix, const ebr_batch* bt, bool topk, Pl
     return EBR_OK;
 }
 
-static std::vector<char> pack_plan(const Plan& P) {
-    std::vector<char> blob(P.plan_bytes, 0);
-    auto cp = [&](size_t o, const void* src, size_t n) { if (n) std::memcpy(blob.data() + o - P.off_plan, src, n); };
-    cp(P.o_ukb, P.uk_chunk_begin.data(), 4 * P.uk_chunk_begin.size());
-    cp(P.o_ukp, P.uk_chunk_prefix.data(), 4 * P.uk_chunk_prefix.size());
-    cp(P.o_uoff, P.users_off.data(), 4 * P.users_off.size());
-    cp(P.o_users, P.users.data(), 4 * P.users.size());
-    cp(P.o_ukw, P.uk_wshift.data(), 4 * P.uk_wshift.size());
-    cp(P.o_qi, P.qinv.data(), 8 * P.qinv.size());
-    cp(P.o_kq, P.kq.data(), 4 * P.kq.size());
-    cp(P.o_jq, P.jq.data(), 4 * P.jq.size());
-    cp(P.o_kc, P.kcnt.data(), 4 * P.kcnt.size());
-    cp(P.o_aq, P.aq.data(), 8 * P.aq.size());
-    cp(P.o_werr, P.werr.data(), 4 * P.werr.size());
-    cp(P.o_oo, P.out_off.data(), 8 * P.out_off.size());
-    cp(P.o_st, P.sample_tiles.data(), 4 * P.sample_tiles.size());
+// The plan's arrays into dst (P.plan_bytes bytes: the workspace's plan section), copied in
+// pieces of at most 1 MiB spread over the host threads; the bytes between the arrays
+// (alignment padding, reserved space a batch leaves unused) are zeroed.
+static void pack_plan_into(const Plan& P, char* dst) {
+    struct Piece {
+        size_t o;
+        const void* src;
+        size_t n;
+    };
+    std::vector<Piece> pcs;
+    auto add = [&](size_t o, const void* src, size_t n) { if (n) pcs.push_back({o - P.off_plan, src, n}); };
+    add(P.o_ukb, P.uk_chunk_begin.data(), 4 * P.uk_chunk_begin.size());
+    add(P.o_ukp, P.uk_chunk_prefix.data(), 4 * P.uk_chunk_prefix.size());
+    add(P.o_uoff, P.users_off.data(), 4 * P.users_off.size());
+    add(P.o_users, P.users.data(), 4 * P.users.size());
+    add(P.o_ukw, P.uk_wshift.data(), 4 * P.uk_wshift.size());
+    add(P.o_qi, P.qinv.data(), 8 * P.qinv.size());
+    add(P.o_kq, P.kq.data(), 4 * P.kq.size());
+    add(P.o_jq, P.jq.data(), 4 * P.jq.size());
+    add(P.o_kc, P.kcnt.data(), 4 * P.kcnt.size());
+    add(P.o_aq, P.aq.data(), 8 * P.aq.size());
+    add(P.o_werr, P.werr.data(), 4 * P.werr.size());
+    add(P.o_oo, P.out_off.data(), 8 * P.out_off.size());
+    add(P.o_st, P.sample_tiles.data(), 4 * P.sample_tiles.size());
     if (P.split) {
-        cp(P.o_htab, P.hot_tab.data(), 4 * (size_t)P.n_hot * (P.hot_users_off.size() - 1));
-        cp(P.o_husers, P.hot_users.data(), 4 * P.hot_users.size());
-        cp(P.o_hoff, P.hot_users_off.data(), 4 * P.hot_users_off.size());
-        cp(P.o_coff, P.cold_off.data(), 4 * P.cold_off.size());
-        cp(P.o_cusers, P.cold_users.data(), 4 * P.cold_users.size());
+        add(P.o_htab, P.hot_tab.data(), 4 * (size_t)P.n_hot * (P.hot_users_off.size() - 1));
+        add(P.o_husers, P.hot_users.data(), 4 * P.hot_users.size());
+        add(P.o_hoff, P.hot_users_off.data(), 4 * P.hot_users_off.size());
+        add(P.o_coff, P.cold_off.data(), 4 * P.cold_off.size());
+        add(P.o_cusers, P.cold_users.data(), 4 * P.cold_users.size());
     }
-    return blob;
+    std::sort(pcs.begin(), pcs.end(), [](const Piece& a, const Piece& b) { return a.o < b.o; });
+    std::vector<Piece> parts;
+    size_t at = 0;
+    static const char kZeros[4096] = {};
+    auto zero = [&](size_t o, size_t n) {
+        for (size_t b = 0; b < n; b += sizeof(kZeros)) parts.push_back({o + b, kZeros, std::min(sizeof(kZeros), n - b)});
+    };
+    constexpr size_t kPiece = 1 << 20;
+    for (const Piece& p : pcs) {
+        if (p.o > at) zero(at, p.o - at);
+        for (size_t b = 0; b < p.n; b += kPiece)
+            parts.push_back({p.o + b, static_cast<const char*>(p.src) + b, std::min(kPiece, p.n - b)});
+        at = std::max(at, p.o + p.n);
+    }
+    if (P.plan_bytes > at) zero(at, P.plan_bytes - at);
+    parallel_for((int64_t)parts.size(), [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i) std::memcpy(dst + parts[i].o, parts[i].src, parts[i].n);
+    }, parts.size() > 64 ? 8 : (int64_t)parts.size());
+}
+
+// The packed plan in host memory (for an upload from pageable memory).
+struct PlanBlob {
+    std::unique_ptr<char[]> p;
+    size_t n = 0;
+    const char* data() const { return p.get(); }
+    size_t size() const { return n; }
+};
+
+static PlanBlob pack_plan(const Plan& P) {
+    PlanBlob b;
+    b.n = P.plan_bytes;
+    b.p.reset(new char[std::max<size_t>(b.n, 1)]);
+    pack_plan_into(P, b.p.get());
+    return b;
 }
 
 // Chunks one decode wavefront takes unless a launch shape says otherwise.
@@ -1538,24 +1580,27 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
             set_error("launch shape out of range");
             return EBR_EINVAL;
         }
-        std::vector<char> blob = pack_plan(P);
-        const char* src = blob.data();
         ebr_graph* g = opt.graph;
         hipStream_t ls = s;  // the stream the device sequence is enqueued (or captured) on
+        PlanBlob blob;
+        const char* src = nullptr;
         if (g) {
-            if (g->pinned_cap < blob.size()) {
+            if (g->pinned_cap < P.plan_bytes) {
                 if (g->pinned) (void)hipHostFree(g->pinned);
                 g->pinned = nullptr;
                 g->pinned_cap = 0;
-                const size_t cap = std::max<size_t>(blob.size() + blob.size() / 4, 1 << 20);
+                const size_t cap = std::max<size_t>(P.plan_bytes + P.plan_bytes / 4, 1 << 20);
                 HIP_TRY(hipHostMalloc((void**)&g->pinned, cap, hipHostMallocDefault));
                 g->pinned_cap = cap;
             }
-            std::memcpy(g->pinned, blob.data(), blob.size());
-            // the plan goes up on the caller's stream ahead of the graph, which holds kernels only
-            HIP_TRY(hipMemcpyAsync(ws + P.off_plan, g->pinned, blob.size(), hipMemcpyHostToDevice, s));
-            src = nullptr;
+            // packed straight into the pinned buffer; the plan goes up on the caller's stream
+            // ahead of the graph, which holds kernels only
+            pack_plan_into(P, g->pinned);
+            HIP_TRY(hipMemcpyAsync(ws + P.off_plan, g->pinned, P.plan_bytes, hipMemcpyHostToDevice, s));
             ls = g->cs;
+        } else {
+            blob = pack_plan(P);
+            src = blob.data();
         }
         const double host_ms = ms_since(t_host);
         PhaseClock clk(ls, !g && (opt.force_timing || g_timing.load() != 0));
@@ -1651,7 +1696,7 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
         // The device sequence of the batch, enqueued on ls without host synchronisation.
         auto enqueue = [&]() -> ebr_status {
             e_dec0 = clk.mark();
-            ebr_status r = run_decode(ix, P, ws, ls, src, blob.size(), sh.decode_chunks);
+            ebr_status r = run_decode(ix, P, ws, ls, src, P.plan_bytes, sh.decode_chunks);
             if (r) return r;
             e_dec1 = clk.mark();
             // per-query set-up on the device: user rows finite, status / activity, certificate eps
@@ -1869,7 +1914,7 @@ static ebr_status topk_impl(const Index& ix, const ebr_batch* batch, char* ws, s
         st = plan_batch(ix, &b1, false, &Pd);
         if (st) return st;
         if (Pd.total > P.off_big_deep) { set_error("full-sort plan exceeds its workspace"); return EBR_EDEVICE; }
-        const std::vector<char> blob = pack_plan(Pd);
+        const PlanBlob blob = pack_plan(Pd);
         st = run_decode(ix, Pd, ws, s, blob.data(), blob.size(), kDefaultDecodeChunks);
         if (st) return st;
         float* deep = (float*)(ws + P.off_big_deep);
@@ -2145,7 +2190,7 @@ ebr_status ebr_score_dense(const ebr_index* index, const ebr_batch* batch, void*
         st = check_users(batch, P.B, ix.dim, s);
         if (st) return st;
         char* ws = (char*)ws_v;
-        const std::vector<char> blob = pack_plan(P);
+        const PlanBlob blob = pack_plan(P);
         st = run_decode(ix, P, ws, s, blob.data(), blob.size(), kDefaultDecodeChunks);
         if (st) return st;
         ScoreArgs a = score_args(ix, P, batch, ws);
